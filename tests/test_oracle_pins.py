@@ -1,0 +1,227 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper or by mathematics.
+
+Each test names what it pins.  None of them calls the HIP path.
+"""
+import numpy as np
+import pytest
+
+from oracle import eig, generator, jacobi, lanczos, lattice, ldlt
+
+
+# --- O1: SplitMix64 / box distribution ---------------------------------------------
+
+def test_splitmix64_published_outputs():
+    # Reference outputs of SplitMix64 (Steele, Lea & Flood 2014; Vigna's reference
+    # implementation) for the stream seeded with 0: the first three outputs.
+    out = generator.splitmix64(0, 3)
+    assert [int(v) for v in out] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    assert generator.splitmix64_scalar(0, 2) == 0x6E789E6AA1B965F4
+
+
+def test_splitmix64_counter_based():
+    # output m of seed s equals output 1 of seed s + (m-1)*gamma (counter form)
+    s = 987654321
+    a = generator.splitmix64(s, 10)
+    for m in range(1, 11):
+        assert int(a[m - 1]) == generator.splitmix64_scalar((s + (m - 1) * generator.GAMMA) % 2**64, 1)
+
+
+def test_box_distribution():
+    # section 3: eps iid uniform in the box [-w/2, w/2]
+    W = 16.5
+    e = generator.disorder(40, W, 7)
+    assert e.min() >= -W / 2 and e.max() < W / 2
+    n = e.size
+    assert abs(e.mean()) < 5 * W / np.sqrt(12 * n)
+    assert abs(e.var() - W * W / 12) < 0.02 * W * W / 12
+    # two seeds give different, reproducible draws
+    assert np.array_equal(e, generator.disorder(40, W, 7))
+    assert not np.array_equal(e, generator.disorder(40, W, 8))
+
+
+# --- O2/O3: operator and dense Jacobi ---------------------------------------------
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6])
+def test_clean_spectrum_closed_form(L):
+    # W = 0: the spectrum of the periodic lattice is -2 (cos kx + cos ky + cos kz),
+    # k = 2 pi a / L.  Odd L makes the sign of the hopping visible (non-bipartite).
+    A = lattice.hamiltonian(L, np.zeros(L ** 3)).toarray()
+    w, V = jacobi.eigh(A)
+    assert np.allclose(w, np.sort(lattice.clean_spectrum(L)), atol=1e-12, rtol=0)
+    assert np.allclose(A @ V, V * w, atol=1e-12)
+    assert np.allclose(V.T @ V, np.eye(L ** 3), atol=1e-12)
+
+
+def test_hamiltonian_structure():
+    for L in (2, 3, 5):
+        e = generator.disorder(L, 12.0, 3)
+        A = lattice.hamiltonian(L, e)
+        assert abs(A - A.T).max() == 0
+        assert np.array_equal(A.diagonal(), e)
+        rowsum = np.asarray(abs(A).sum(axis=1)).ravel()
+        assert np.allclose(rowsum, 6 + np.abs(e))  # six couplings of modulus 1
+        assert np.isclose(lattice.inf_norm(e), abs(A).sum(axis=1).max())
+        nnz_row = np.diff(A.indptr)
+        assert set(nnz_row) == ({4} if L == 2 else {7})
+    A2 = lattice.hamiltonian(2, np.zeros(8)).toarray()
+    assert set(np.unique(A2)) == {0.0, -2.0}  # L = 2: the two neighbours coincide
+
+
+def test_matvec_matches_csr():
+    L = 7
+    e = generator.disorder(L, 16.5, 1)
+    x = np.random.default_rng(0).standard_normal(L ** 3)
+    A = lattice.hamiltonian(L, e)
+    assert np.allclose(lattice.matvec(L, e, x, shift=0.3), A @ x - 0.3 * x, atol=1e-13, rtol=0)
+
+
+def test_jacobi_against_library_eigh():
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((60, 60))
+    A = B + B.T
+    w, V = jacobi.eigh(A)
+    assert np.allclose(w, np.linalg.eigvalsh(A), atol=1e-12)
+    assert np.allclose(A @ V, V * w, atol=1e-11)
+    assert np.allclose(V.T @ V, np.eye(60), atol=1e-12)
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_gauge_and_hopping_sign_even_L(L):
+    # even L: U = diag((-1)^{i+j+k}) gives U T U = -T, so spec H(eps) = -spec H(-eps)
+    # and the +1 (paper) and -1 hopping conventions share one spectrum.
+    e = generator.disorder(L, 16.5, 2)
+    w = jacobi.eigh(lattice.hamiltonian(L, e).toarray(), vectors=False)[0]
+    wm = jacobi.eigh(lattice.hamiltonian(L, -e).toarray(), vectors=False)[0]
+    wp = jacobi.eigh(lattice.hamiltonian(L, e, hopping=+1.0).toarray(), vectors=False)[0]
+    assert np.allclose(w, -wm[::-1], atol=1e-12)
+    assert np.allclose(w, wp, atol=1e-12)
+
+
+def test_gershgorin_bound():
+    # section 3: the eigenvalues lie in [-6 - w/2, 6 + w/2]
+    L, W = 6, 21.0
+    e = generator.disorder(L, W, 4)
+    w = jacobi.eigh(lattice.hamiltonian(L, e).toarray(), vectors=False)[0]
+    assert w.min() >= -6 - W / 2 and w.max() <= 6 + W / 2
+
+
+def test_translation_and_reflection_invariance():
+    L = 6
+    e = generator.disorder(L, 16.5, 9).reshape(L, L, L)
+    w0 = jacobi.eigh(lattice.hamiltonian(L, e.ravel()).toarray(), vectors=False)[0]
+    for f in (np.roll(e, 2, axis=0).ravel(), e[:, ::-1, :].ravel(), e.transpose(1, 0, 2).ravel()):
+        w1 = jacobi.eigh(lattice.hamiltonian(L, f.copy()).toarray(), vectors=False)[0]
+        assert np.allclose(w0, w1, atol=1e-12)
+
+
+# --- O4/O6: exact sparse LDL^T and inertia ------------------------------------------
+
+@pytest.mark.parametrize("L,seed", [(3, 0), (4, 1), (6, 2), (7, 3)])
+def test_inertia_matches_dense_count(L, seed):
+    e = generator.disorder(L, 16.5, seed)
+    A = lattice.hamiltonian(L, e).toarray()
+    w = jacobi.eigh(A, vectors=False)[0]
+    for tau in (0.0, 0.41, -2.3, 5.0):
+        f = ldlt.LDLT(L, e, tau, leaf=20)
+        neg, zero, pos = f.inertia()
+        assert neg == int((w < tau).sum()) and zero == 0 and neg + pos == L ** 3
+        b = np.random.default_rng(1).standard_normal(L ** 3)
+        x = f.solve(b)
+        assert np.linalg.norm(A @ x - tau * x - b) <= 1e-12 * np.linalg.norm(b) * lattice.inf_norm(e)
+
+
+@pytest.mark.parametrize("L", [8, 12, 16])
+def test_inertia_closed_form_clean_lattice(L):
+    # W = 0: count of eigenvalues below tau from the closed form, at sizes beyond
+    # the dense path; tau placed away from every lattice eigenvalue.
+    spec = lattice.clean_spectrum(L)
+    for tau in (0.1234, -1.777, 3.05):
+        assert np.min(np.abs(spec - tau)) > 1e-3
+        neg, zero = ldlt.count_below(L, np.zeros(L ** 3), tau)
+        assert zero == 0 and neg == int((spec < tau).sum())
+
+
+def test_nested_dissection_partitions_sites():
+    for L in (5, 8, 11):
+        nodes = ldlt.nested_dissection(L, leaf=30)
+        allv = np.concatenate([n.own for n in nodes])
+        assert np.array_equal(np.sort(allv), np.arange(L ** 3))
+
+
+# --- O5/O7: shift-and-invert Lanczos and the result definition ----------------------
+
+def test_lanczos_matches_dense_jacobi():
+    L = 8
+    e = generator.disorder(L, 16.5, 0)
+    l1, X1, r1, an = eig.nearest_eigenpairs(L, e, 0.0, 6, method="dense")
+    l2, X2, r2, _ = eig.nearest_eigenpairs(L, e, 0.0, 6, method="lanczos")
+    assert np.allclose(l1, l2, atol=1e-12, rtol=0)
+    assert np.allclose(X1, X2, atol=1e-8)  # same sign convention
+    assert r1.max() <= 1e-12 * an and r2.max() <= 1e-12 * an
+
+
+def _chain(f):
+    # 1D periodic chain with hopping -1 and diagonal f
+    m = len(f)
+    H = np.diag(f)
+    for i in range(m):
+        H[i, (i + 1) % m] -= 1.0
+        H[(i + 1) % m, i] -= 1.0
+    return H
+
+
+@pytest.mark.parametrize("L,sigma", [(16, 0.3), (20, -0.7)])
+def test_separable_diagonal_kronecker_sum(L, sigma):
+    # eps_{ijk} = f_i + g_j + h_k makes A a Kronecker sum of three periodic chains:
+    # its eigenvalues are all sums a + b + c of the chains' eigenvalues.
+    rng = np.random.default_rng(L)
+    f, g, h = (rng.uniform(-2.5, 2.5, L) for _ in range(3))
+    eps = (f[None, None, :] + g[None, :, None] + h[:, None, None]).reshape(-1)
+    ea, eb, ec = (jacobi.eigh(_chain(v), vectors=False)[0] for v in (f, g, h))
+    sums = (ea[None, None, :] + eb[None, :, None] + ec[:, None, None]).reshape(-1)
+    k = 8
+    ref = sums[eig.select_nearest(sums, sigma, k)]
+    lams, X, res, an = eig.nearest_eigenpairs(L, eps, sigma, k)
+    assert np.allclose(lams, ref, atol=1e-11, rtol=0)
+    assert res.max() <= 1e-12 * an
+
+
+def test_window_count_by_inertia():
+    L = 6
+    e = generator.disorder(L, 16.5, 5)
+    w = jacobi.eigh(lattice.hamiltonian(L, e).toarray(), vectors=False)[0]
+    assert eig.count_in_window(L, e, -0.5, 0.7) == int(((w >= -0.5) & (w < 0.7)).sum())
+
+
+def test_selection_order_rule():
+    lams = np.array([0.3, -0.1, 0.1, -0.3, 0.05])
+    idx = eig.select_nearest(lams, 0.0, 5)
+    assert list(lams[idx]) == [0.05, -0.1, 0.1, -0.3, 0.3]
+
+
+# --- planted mistakes: each plausible slip in the operator fails a pin above --------
+
+@pytest.mark.parametrize("mistake", ["sign", "dropped_z", "wrong_index"])
+def test_planted_mistakes_are_caught(monkeypatch, mistake):
+    L = 5  # odd: the hopping sign changes the clean spectrum
+    if mistake == "sign":
+        A = lattice.hamiltonian(L, np.zeros(L ** 3), hopping=+1.0).toarray()
+    elif mistake == "dropped_z":
+        monkeypatch.setattr(lattice, "NEIGHBOURS", lattice.NEIGHBOURS[:4])
+        A = lattice.hamiltonian(L, np.zeros(L ** 3)).toarray()
+    else:
+        # x and y swapped in the neighbour arithmetic only: the diagonal stays in
+        # site order, so the operator no longer matches the stencil definition
+        e = generator.disorder(L, 4.0, 1)
+        orig = lattice.site_coords
+        monkeypatch.setattr(lattice, "site_coords",
+                            lambda L_: (lambda c: (c[1], c[0], c[2]))(orig(L_)))
+        Aw = lattice.hamiltonian(L, e)
+        monkeypatch.undo()
+        x = np.random.default_rng(0).standard_normal(L ** 3)
+        y = lattice.matvec(L, e, x)  # the stencil written out neighbour by neighbour
+        assert not np.allclose(Aw @ x, y)
+        assert np.allclose(lattice.hamiltonian(L, e) @ x, y)
+        return
+    w = jacobi.eigh(A, vectors=False)[0]
+    assert not np.allclose(w, np.sort(lattice.clean_spectrum(L)), atol=1e-9)
