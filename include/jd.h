@@ -1,0 +1,187 @@
+/*
+ * jd.h -- C ABI of the MI355X (gfx950) shift-and-invert Jacobi-Davidson library
+ * for the 3D Anderson model of localization.
+ *
+ * Method: Schenk, Bollhoefer & Roemer, "On large scale diagonalization techniques
+ * for the Anderson model of localization".  The operator is the Anderson matrix of
+ * section 3, eq. (eigenequation), on the periodic L x L x L lattice, written here
+ * as A = -T + diag(eps) (hopping -1; for even L the staggered gauge maps it onto
+ * the paper's +1 convention with the same spectrum).  eps_s = W (u_s - 1/2),
+ * u_s the top 53 bits of output s+1 of SplitMix64 seeded with `seed`, site
+ * s = i + L (j + L k) (x fastest, 0-based).
+ *
+ * Conventions for every entry point:
+ *  - Return value: JD_OK (0) on success, JD_ENOCONV (1) for a partial result,
+ *    a negative JD_E* code on failure; jd_last_error() then describes it
+ *    (thread-local string owned by the library, valid until the next call on the
+ *    same thread).  No C++ exception crosses this interface.
+ *  - "host" pointers are ordinary CPU memory owned by the caller; "device"
+ *    pointers are HIP device memory on the current device, owned by the caller
+ *    (the library never frees them).  Handles (jd_problem, jd_precond) are owned
+ *    by the library and released by their *_free call.
+ *  - Vectors over the lattice have length n = L^3 in site order; multi-column
+ *    arrays are column-major with leading dimension n.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Device work of
+ *    a call is ordered on that stream; calls returning host results synchronise it.
+ *  - Distinct handles may be used from distinct threads; one handle must not be
+ *    used by two threads at once.
+ */
+#ifndef JD_H
+#define JD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    JD_OK = 0,
+    JD_ENOCONV = 1,    /* partial result: fewer than k pairs met the tolerance */
+    JD_EINVAL = -1,    /* invalid argument (sizes, non-finite values, NULL outputs) */
+    JD_ENOMEM = -2,    /* device or host allocation failed */
+    JD_EDEVICE = -3,   /* a HIP call failed (message names it) */
+    JD_ESETUP = -4,    /* preconditioner construction failed (e.g. singular coarse level) */
+    JD_ENOTIMPL = -5   /* option combination not provided */
+};
+
+enum { JD_FP64 = 0, JD_MIXED = 1 };
+
+/*
+ * Options; a zero-initialised struct selects every default.
+ *  precision  JD_FP64: every step in binary64.  JD_MIXED: stencil SpMV,
+ *             preconditioner factors and the inner SQMR iteration in binary32
+ *             (binary32 accumulation); Gram-Schmidt, Rayleigh-Ritz, residual
+ *             norms and acceptance in binary64.
+ *  drop_tol   epsilon of section 7.2: an entry of a factor column is dropped when
+ *             its modulus is below drop_tol / kappa (0 -> 1e-2).
+ *  kappa      bound on ||L^{-1}|| of inverse-based pivoting, section 7.2 (0 -> 5).
+ *  agg_tau    tau of the aggressive dropping rule of section 7.3 (0 -> 0.1).
+ *  schur_tol  off-diagonal entries of a scaled Schur complement below this are
+ *             dropped (0 -> drop_tol).
+ *  coarse_max the multilevel recursion (section 7.3) stops at this size and the
+ *             last Schur complement is inverted exactly (0 -> 1536).
+ *  max_levels cap on the number of levels (0 -> 64).
+ *  jmin, jmax search-space sizes after / before a restart (0 -> max(k+5,10), 2 jmin).
+ *  max_outer  outer Jacobi-Davidson iterations (0 -> 60 k + 200).
+ *  max_inner  SQMR steps per correction equation (0 -> 40).
+ *  switch_tol the correction operator uses sigma until ||r|| < switch_tol ||A||_inf,
+ *             then the Ritz value theta (0 -> 1e-3).
+ */
+typedef struct jd_options {
+    int precision;
+    double drop_tol;
+    double kappa;
+    double agg_tau;
+    double schur_tol;
+    int coarse_max;
+    int max_levels;
+    int jmin, jmax;
+    int max_outer, max_inner;
+    double switch_tol;
+    void *stream;
+} jd_options;
+
+/* Statistics of a solve (the paper's Tables 3-5 quantities plus timings). */
+typedef struct jd_info {
+    int n_converged;      /* eigenpairs that met the tolerance */
+    int outer_its;        /* Jacobi-Davidson outer iterations */
+    int inner_its;        /* SQMR steps summed over all correction equations */
+    int levels;           /* multilevel factorisation: number of levels */
+    int n_2x2;            /* 2x2 pivots over all levels */
+    int coarse_n;         /* size of the exactly inverted last Schur complement */
+    double setup_s;       /* host setup: matching, scaling, ordering, factorisation, upload */
+    double solve_s;       /* device solve (outer + inner iterations) */
+    double fill;          /* (nnz strict lower L + nnz D + coarse entries) / nnz lower(A) */
+    double anorm;         /* ||A||_inf = 6 + max |eps| */
+    size_t device_bytes;  /* device memory held by the problem */
+} jd_info;
+
+typedef struct jd_problem jd_problem;
+typedef struct jd_precond jd_precond;
+
+/*
+ * jd_solve -- the k eigenpairs of A nearest sigma (abstract; section 4.2;
+ * section 8.2: "five eigenvalues closest to lambda = 0").
+ *  L >= 2 with L^3 < 2^31; W >= 0 finite; sigma finite; 1 <= k <= min(n, 64);
+ *  tol in [1e-14, 1): a pair is accepted when ||A x - lambda x||_2 <= tol ||A||_inf
+ *  with ||x||_2 = 1.
+ *  evals [k] host (required): sorted by (|lambda - sigma|, lambda).
+ *  evecs [n*k] host or NULL: column c is the unit eigenvector of evals[c].
+ *  resid [k] host or NULL: ||A x - lambda x||_2 / ||A||_inf per pair (binary64).
+ *  opt, info may be NULL.
+ *  Returns JD_ENOCONV with the converged prefix filled and NaN in the rest when
+ *  max_outer is exhausted.
+ */
+int jd_solve(int L, double W, uint64_t seed, double sigma, int k, double tol,
+             double *evals, double *evecs, double *resid,
+             const jd_options *opt, jd_info *info);
+
+/* Split form: the setup (timed separately) keeps the factors resident. */
+int jd_setup(int L, double W, uint64_t seed, double sigma, const jd_options *opt,
+             jd_problem **out);
+/* Same contract as jd_solve.  evecs_device, if not NULL, is a caller-owned device
+ * array of n*k binary64 values that receives the eigenvectors. */
+int jd_problem_solve(jd_problem *p, int k, double tol, double *evals, double *evecs_host,
+                     void *evecs_device, double *resid, jd_info *info);
+/* Setup statistics of a problem (levels, fill, timings so far). */
+int jd_problem_info(const jd_problem *p, jd_info *info);
+void jd_problem_free(jd_problem *p);
+
+/*
+ * Hot-path steps exposed on their own (used by the parity tests and the benchmark).
+ *
+ * jd_gen_diag -- K1: eps (n binary64) and its binary32 rounding into device arrays.
+ *   d_eps32 may be NULL.
+ */
+int jd_gen_diag(int L, double W, uint64_t seed, double *d_eps, float *d_eps32, void *stream);
+
+/*
+ * jd_stencil_spmv -- y = (A - shift I) x on the periodic lattice (section 3,
+ * eq. (eigenequation)); only eps is stored, the couplings are implicit.
+ *   precision JD_FP64: d_eps, d_x, d_y are double*; JD_MIXED: float*.
+ */
+int jd_stencil_spmv(int L, int precision, const void *d_eps, double shift,
+                    const void *d_x, void *d_y, void *stream);
+
+/*
+ * jd_precond_create -- host setup of the matching-based multilevel incomplete
+ * LDL^T of A - sigma I (sections 6 and 7): maximum weight matching, 1x1/2x2
+ * cycle split, symmetric scaling, block independent-set ordering, inverse-based
+ * pivot acceptance with bound kappa, dropping, explicit Schur complement, recursion,
+ * exactly inverted last level; factors uploaded in binary64 and binary32.
+ * With drop_tol < 0 nothing is dropped and kappa is ignored (exact factorisation
+ * up to rounding: the apply then equals (A - sigma I)^{-1}).
+ */
+int jd_precond_create(int L, double W, uint64_t seed, double sigma, const jd_options *opt,
+                      jd_precond **out);
+/* out = K^{-1} in (device vectors of length n, double* for JD_FP64, float* for
+ * JD_MIXED); in and out must not overlap. */
+int jd_precond_apply(jd_precond *p, int precision, const void *d_in, void *d_out, void *stream);
+/* Level structure: sizes[l] = unknowns entering level l (l < levels), sizes[levels] =
+ * coarse size; nB[l] = pivots accepted at level l; nnzG[l] = stored coupling entries.
+ * Arrays of length cap (host); returns the number of levels. */
+int jd_precond_levels(const jd_precond *p, int cap, int *sizes, int *nB, long long *nnzG);
+void jd_precond_free(jd_precond *p);
+
+/*
+ * jd_problem_linear_solve -- the inner iteration on its own: simplified QMR with
+ * the projected preconditioner (section 4.2) for
+ *   (I - Q Q^T)(A - shift I)(I - Q Q^T) x = (I - Q Q^T) b,  x = (I - Q Q^T) x,
+ * Q the p orthonormal binary64 columns of d_Q (p may be 0, d_Q then NULL).
+ * d_b, d_x: device binary64 n-vectors.  Stops when the quasi-residual bound
+ * reaches rtol ||b|| or after maxit steps; *its receives the step count.
+ */
+int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int pcols,
+                            const double *d_b, double *d_x, double rtol, int maxit, int *its);
+
+const char *jd_last_error(void);
+/* Library version string. */
+const char *jd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JD_H */

@@ -1,0 +1,226 @@
+"""Shift-and-invert Jacobi-Davidson for the 3D Anderson model on MI355X (gfx950).
+
+Thin ctypes binding of ``libjdmi.so`` (declared in ``include/jd.h``).  It only
+marshals arguments: every step of the solve runs in the library's HIP kernels and
+host setup.  Device arrays are passed as torch CUDA tensors (their data pointers);
+host outputs are numpy arrays.  If the library is missing this module raises on
+first use; there is no fallback.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjdmi.so")
+
+JD_OK, JD_ENOCONV, JD_EINVAL, JD_ENOMEM, JD_EDEVICE, JD_ESETUP, JD_ENOTIMPL = 0, 1, -1, -2, -3, -4, -5
+JD_FP64, JD_MIXED = 0, 1
+_PREC = {"fp64": JD_FP64, "mixed": JD_MIXED, JD_FP64: JD_FP64, JD_MIXED: JD_MIXED}
+
+
+class JdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"jd error {code}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("drop_tol", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("agg_tau", ctypes.c_double), ("schur_tol", ctypes.c_double), ("coarse_max", ctypes.c_int),
+                ("max_levels", ctypes.c_int), ("jmin", ctypes.c_int), ("jmax", ctypes.c_int),
+                ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int), ("switch_tol", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_converged", ctypes.c_int), ("outer_its", ctypes.c_int), ("inner_its", ctypes.c_int),
+                ("levels", ctypes.c_int), ("n_2x2", ctypes.c_int), ("coarse_n", ctypes.c_int),
+                ("setup_s", ctypes.c_double), ("solve_s", ctypes.c_double), ("fill", ctypes.c_double),
+                ("anorm", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+EXPORTS = ["jd_solve", "jd_setup", "jd_problem_solve", "jd_problem_info", "jd_problem_free", "jd_gen_diag",
+           "jd_stencil_spmv", "jd_precond_create", "jd_precond_apply", "jd_precond_levels", "jd_precond_free",
+           "jd_problem_linear_solve", "jd_last_error", "jd_version"]
+
+_lib = None
+
+
+def lib():
+    """Load libjdmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_math_0508111_amd.build` first")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D, U64, DP = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)
+    OP, IP = ctypes.POINTER(Options), ctypes.POINTER(Info)
+    sig = {
+        "jd_solve": (I, [I, D, U64, D, I, D, P, P, P, OP, IP]),
+        "jd_setup": (I, [I, D, U64, D, OP, ctypes.POINTER(P)]),
+        "jd_problem_solve": (I, [P, I, D, P, P, P, P, IP]),
+        "jd_problem_info": (I, [P, IP]),
+        "jd_problem_free": (None, [P]),
+        "jd_gen_diag": (I, [I, D, U64, P, P, P]),
+        "jd_stencil_spmv": (I, [I, I, P, D, P, P, P]),
+        "jd_precond_create": (I, [I, D, U64, D, OP, ctypes.POINTER(P)]),
+        "jd_precond_apply": (I, [P, I, P, P, P]),
+        "jd_precond_levels": (I, [P, I, P, P, P]),
+        "jd_precond_free": (None, [P]),
+        "jd_problem_linear_solve": (I, [P, D, P, I, P, P, D, I, ctypes.POINTER(I)]),
+        "jd_last_error": (ctypes.c_char_p, []),
+        "jd_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc, allow_partial=False):
+    if rc == JD_OK or (allow_partial and rc == JD_ENOCONV):
+        return rc
+    raise JdError(rc, lib().jd_last_error().decode())
+
+
+def make_options(precision="fp64", stream=None, **kw):
+    o = Options()
+    o.precision = _PREC[precision]
+    for k, v in kw.items():
+        if v is not None:
+            setattr(o, k, v)
+    if stream is not None:
+        o.stream = ctypes.c_void_p(_stream_ptr(stream))
+    return o
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def solve(L, W, seed, sigma, k, tol=1e-10, vectors=False, precision="fp64", **opts):
+    """k eigenpairs of the Anderson matrix nearest sigma (jd_solve)."""
+    n = L ** 3
+    evals = np.full(k, np.nan)
+    resid = np.full(k, np.nan)
+    evecs = np.empty((k, n)) if vectors else None
+    info = Info()
+    o = make_options(precision, **opts)
+    rc = lib().jd_solve(L, float(W), seed, float(sigma), k, float(tol), _host(evals),
+                        _host(evecs), _host(resid), ctypes.byref(o), ctypes.byref(info))
+    _check(rc, allow_partial=True)
+    return evals, (evecs.T if vectors else None), resid, dict(info.as_dict(), status=rc)
+
+
+class Problem:
+    """jd_setup / jd_problem_solve: setup once, factors resident on the device."""
+
+    def __init__(self, L, W, seed, sigma, precision="fp64", **opts):
+        self.L, self.n = L, L ** 3
+        self._opts = make_options(precision, **opts)
+        h = ctypes.c_void_p()
+        _check(lib().jd_setup(L, float(W), seed, float(sigma), ctypes.byref(self._opts), ctypes.byref(h)))
+        self._h = h
+
+    def info(self):
+        i = Info()
+        _check(lib().jd_problem_info(self._h, ctypes.byref(i)))
+        return i.as_dict()
+
+    def solve(self, k, tol=1e-10, vectors=False, device_out=None):
+        evals = np.full(k, np.nan)
+        resid = np.full(k, np.nan)
+        evecs = np.empty((k, self.n)) if vectors else None
+        info = Info()
+        rc = lib().jd_problem_solve(self._h, k, float(tol), _host(evals), _host(evecs), _ptr(device_out),
+                                    _host(resid), ctypes.byref(info))
+        _check(rc, allow_partial=True)
+        return evals, (evecs.T if vectors else None), resid, dict(info.as_dict(), status=rc)
+
+    def linear_solve(self, shift, b, x, Q=None, rtol=1e-8, maxit=200):
+        """Q: (n, p) device tensor of orthonormal columns (laid out column-major for the ABI)."""
+        its = ctypes.c_int(0)
+        p = 0 if Q is None else int(Q.shape[1])
+        Qc = None if Q is None else Q.t().contiguous()
+        qp = None if Qc is None else ctypes.c_void_p(Qc.data_ptr())
+        _check(lib().jd_problem_linear_solve(self._h, float(shift), qp, p, _ptr(b), _ptr(x), float(rtol),
+                                             int(maxit), ctypes.byref(its)))
+        return its.value
+
+    def close(self):
+        if self._h:
+            lib().jd_problem_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Precond:
+    """jd_precond_create / jd_precond_apply: the multilevel ILDL^T preconditioner alone."""
+
+    def __init__(self, L, W, seed, sigma, **opts):
+        self.L, self.n = L, L ** 3
+        self._opts = make_options("fp64", **opts)
+        h = ctypes.c_void_p()
+        _check(lib().jd_precond_create(L, float(W), seed, float(sigma), ctypes.byref(self._opts), ctypes.byref(h)))
+        self._h = h
+
+    def apply(self, x, y, precision="fp64", stream=None):
+        _check(lib().jd_precond_apply(self._h, _PREC[precision], _ptr(x), _ptr(y), _stream_ptr(stream)))
+
+    def levels(self, cap=256):
+        sizes = np.zeros(cap, np.int32)
+        nb = np.zeros(cap, np.int32)
+        nnz = np.zeros(cap, np.int64)
+        nl = lib().jd_precond_levels(self._h, cap, _host(sizes), _host(nb), _host(nnz))
+        if nl < 0:
+            _check(nl)
+        return dict(levels=nl, sizes=sizes[:nl + 1].tolist(), nB=nb[:nl].tolist(), nnzG=nnz[:nl].tolist())
+
+    def close(self):
+        if self._h:
+            lib().jd_precond_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gen_diag(L, W, seed, eps64, eps32=None, stream=None):
+    _check(lib().jd_gen_diag(L, float(W), seed, _ptr(eps64), _ptr(eps32), _stream_ptr(stream)))
+
+
+def stencil_spmv(L, eps, shift, x, y, precision="fp64", stream=None):
+    _check(lib().jd_stencil_spmv(L, _PREC[precision], _ptr(eps), float(shift), _ptr(x), _ptr(y),
+                                 _stream_ptr(stream)))
+
+
+def version():
+    return lib().jd_version().decode()

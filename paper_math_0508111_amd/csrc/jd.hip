@@ -1,0 +1,917 @@
+// Jacobi-Davidson driver and the C ABI (include/jd.h).
+//
+// Outer iteration (section 4.2): expand the search space V with the correction,
+// orthogonalised against the locked eigenvectors Q and V (classical Gram-Schmidt,
+// twice), Rayleigh-Ritz on H = V^T A V, select the Ritz pair nearest sigma, lock it
+// when its residual meets the tolerance (deflation against [Q, u], section 4.2),
+// restart from jmax to jmin vectors.  Inner iteration: simplified QMR on the
+// correction equation with operator (I - Qt Qt^T)(A - s I) and the projected
+// preconditioner K^{-1} - Y (Qt^T Y)^{-1} Y^T, Y = K^{-1} Qt, Qt = [Q, u].
+// All n-vector work runs in device kernels; the host holds only the m x m
+// projected matrices and the per-outer-iteration status.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/jd.h"
+#include "kernels.h"
+#include "setup.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+struct JdError : std::runtime_error {
+    int code;
+    JdError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(call)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            throw JdError(e_ == hipErrorOutOfMemory ? JD_ENOMEM : JD_EDEVICE,                      \
+                          std::string(#call) + ": " + hipGetErrorString(e_));                      \
+    } while (0)
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device allocation list owned by a handle.
+struct DevMem {
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+    template <typename T>
+    T *alloc(size_t count)
+    {
+        if (count == 0) count = 1;
+        void *p = nullptr;
+        HIPCHK(hipMalloc(&p, count * sizeof(T)));
+        ptrs.push_back(p);
+        bytes += count * sizeof(T);
+        return static_cast<T *>(p);
+    }
+    template <typename T>
+    T *upload(const std::vector<T> &v, hipStream_t s)
+    {
+        T *p = alloc<T>(v.size());
+        (void)s;
+        if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        return p;
+    }
+    void release()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+        bytes = 0;
+    }
+    ~DevMem() { release(); }
+};
+
+template <typename To>
+std::vector<To> cast_vec(const std::vector<double> &v)
+{
+    return std::vector<To>(v.begin(), v.end());
+}
+
+// The multilevel factors on the device in one precision.
+template <typename T>
+struct DevPrecond {
+    int n = 0;
+    int *perm = nullptr;
+    std::vector<jdmi::DevLevel<T>> levels;
+    int coarse_off = 0, coarse_n = 0;
+    T *cinv = nullptr;
+    T *w = nullptr, *x = nullptr;  // workspaces
+
+    void upload(const jdmi::Multilevel &ml, const int *dperm, DevMem &mem, hipStream_t s)
+    {
+        n = ml.n;
+        perm = const_cast<int *>(dperm);
+        levels.clear();
+        for (const auto &L : ml.levels) {
+            jdmi::DevLevel<T> d{};
+            d.off = L.off;
+            d.nB = L.nB;
+            d.n_after = L.n_after;
+            d.g_ptr = mem.upload(L.g_ptr, s);
+            d.g_col = mem.upload(L.g_col, s);
+            d.g_val = mem.upload(cast_vec<T>(L.g_val), s);
+            d.gt_ptr = mem.upload(L.gt_ptr, s);
+            d.gt_col = mem.upload(L.gt_col, s);
+            d.gt_val = mem.upload(cast_vec<T>(L.gt_val), s);
+            d.bd = mem.upload(cast_vec<T>(L.bd), s);
+            d.bo = mem.upload(cast_vec<T>(L.bo), s);
+            d.bp = mem.upload(L.bp, s);
+            levels.push_back(d);
+        }
+        coarse_off = ml.coarse_off;
+        coarse_n = ml.coarse_n;
+        cinv = mem.upload(cast_vec<T>(ml.coarse_inv), s);
+        w = mem.alloc<T>(n);
+        x = mem.alloc<T>(n);
+        // keep the converted host vectors alive until the copies are done
+        HIPCHK(hipStreamSynchronize(s));
+    }
+
+    // out = K^{-1} in
+    void apply(const T *in, T *out, hipStream_t s, const int *skip = nullptr) const
+    {
+        jdmi::launch_gather<T>(n, perm, in, w, s, skip);
+        for (const auto &lv : levels) jdmi::launch_down<T>(lv, w, s, skip);
+        jdmi::launch_coarse<T>(coarse_n, coarse_off, cinv, w, x, s, skip);
+        for (int l = int(levels.size()) - 1; l >= 0; --l) jdmi::launch_up<T>(levels[l], w, x, s, skip);
+        jdmi::launch_scatter<T>(n, perm, x, out, s, skip);
+    }
+};
+
+struct Setup {
+    int L = 0, n = 0;
+    double W = 0, sigma = 0;
+    uint64_t seed = 0;
+    jd_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    DevMem mem;
+    double *eps64 = nullptr;
+    float *eps32 = nullptr;
+    double anorm = 0;
+    jdmi::Multilevel ml;
+    DevPrecond<double> pc64;
+    DevPrecond<float> pc32;
+    double setup_s = 0;
+    int n2x2 = 0;
+};
+
+void fill_defaults(jd_options &o)
+{
+    if (o.drop_tol == 0) o.drop_tol = 1e-2;
+    if (o.kappa == 0) o.kappa = 5.0;
+    if (o.agg_tau == 0) o.agg_tau = 0.1;
+    if (o.schur_tol == 0) o.schur_tol = o.drop_tol > 0 ? o.drop_tol : -1.0;
+    if (o.coarse_max == 0) o.coarse_max = 1536;
+    if (o.max_levels == 0) o.max_levels = 64;
+    if (o.max_inner == 0) o.max_inner = 40;
+    if (o.switch_tol == 0) o.switch_tol = 1e-3;
+}
+
+void check_problem_args(int L, double W, double sigma, const jd_options *opt)
+{
+    if (L < 2 || (long long)L * L * L >= (1LL << 31)) throw JdError(JD_EINVAL, "L must satisfy L >= 2 and L^3 < 2^31");
+    if (!(W >= 0) || !std::isfinite(W)) throw JdError(JD_EINVAL, "W must be finite and >= 0");
+    if (!std::isfinite(sigma)) throw JdError(JD_EINVAL, "sigma must be finite");
+    if (opt) {
+        if (opt->precision != JD_FP64 && opt->precision != JD_MIXED) throw JdError(JD_EINVAL, "unknown precision");
+        if (opt->coarse_max < 0 || opt->coarse_max > 8192) throw JdError(JD_EINVAL, "coarse_max must be in [0, 8192]");
+        if (opt->jmin < 0 || opt->jmax < 0 || opt->jmax > 120) throw JdError(JD_EINVAL, "jmin/jmax out of range");
+        if (opt->max_inner < 0 || opt->max_outer < 0 || opt->max_levels < 0) throw JdError(JD_EINVAL, "negative iteration cap");
+        if (!std::isfinite(opt->drop_tol) || !std::isfinite(opt->kappa) || opt->kappa < 0 ||
+            !std::isfinite(opt->agg_tau) || !std::isfinite(opt->schur_tol) || !std::isfinite(opt->switch_tol))
+            throw JdError(JD_EINVAL, "non-finite option");
+    }
+}
+
+void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const jd_options *opt)
+{
+    check_problem_args(L, W, sigma, opt);
+    const double t0 = now_s();
+    S.L = L;
+    S.n = L * L * L;
+    S.W = W;
+    S.seed = seed;
+    S.sigma = sigma;
+    if (opt) S.opt = *opt;
+    fill_defaults(S.opt);
+    if (S.opt.stream) {
+        S.stream = static_cast<hipStream_t>(S.opt.stream);
+    } else {
+        // a blocking stream: its work is ordered after the legacy default stream's,
+        // so device inputs written there by the caller are complete
+        HIPCHK(hipStreamCreate(&S.stream));
+        S.own_stream = true;
+    }
+    const int n = S.n;
+    S.eps64 = S.mem.alloc<double>(n);
+    S.eps32 = S.mem.alloc<float>(n);
+    jdmi::launch_gen_diag(L, W, seed, S.eps64, S.eps32, S.stream);
+    HIPCHK(hipGetLastError());
+    std::vector<double> eps(n);
+    HIPCHK(hipMemcpyAsync(eps.data(), S.eps64, n * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+    HIPCHK(hipStreamSynchronize(S.stream));
+    double emax = 0;
+    for (double e : eps) emax = std::max(emax, std::fabs(e));
+    S.anorm = 6.0 + emax;
+    jdmi::Csr A = jdmi::anderson_shifted(L, eps.data(), sigma);
+    jdmi::SetupParams prm;
+    prm.drop_tol = S.opt.drop_tol;
+    prm.kappa = S.opt.kappa;
+    prm.agg_tau = S.opt.agg_tau;
+    prm.schur_tol = S.opt.schur_tol;
+    prm.coarse_max = S.opt.coarse_max;
+    prm.max_levels = S.opt.max_levels;
+    std::string err = jdmi::build_multilevel(A, prm, S.ml);
+    if (!err.empty()) throw JdError(JD_ESETUP, err);
+    S.n2x2 = 0;
+    for (auto &lv : S.ml.levels) S.n2x2 += lv.n2x2;
+    int *dperm = S.mem.upload(S.ml.perm, S.stream);
+    S.pc64.upload(S.ml, dperm, S.mem, S.stream);
+    S.pc32.upload(S.ml, dperm, S.mem, S.stream);
+    HIPCHK(hipStreamSynchronize(S.stream));
+    S.setup_s = now_s() - t0;
+}
+
+// ---------------------------------------------------------------------------------
+// Small dense helpers on the host (m <= 120): cyclic Jacobi for the projected
+// matrix, Gauss-Jordan for the p x p matrix of the projected preconditioner.
+// ---------------------------------------------------------------------------------
+void small_symeig(int m, std::vector<double> H /* m*m col-major */, std::vector<double> &w, std::vector<double> &Z)
+{
+    Z.assign(size_t(m) * m, 0.0);
+    for (int i = 0; i < m; ++i) Z[i + size_t(i) * m] = 1.0;
+    auto at = [&](int i, int j) -> double & { return H[i + size_t(j) * m]; };
+    double fro = 0;
+    for (double v : H) fro += v * v;
+    fro = std::sqrt(fro);
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0;
+        for (int j = 0; j < m; ++j)
+            for (int i = 0; i < m; ++i)
+                if (i != j) off += at(i, j) * at(i, j);
+        if (std::sqrt(off) <= 1e-16 * fro || off == 0) break;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                const double hpq = at(p, q);
+                if (hpq == 0.0) continue;
+                const double zeta = (at(q, q) - at(p, p)) / (2.0 * hpq);
+                const double t = std::copysign(1.0, zeta) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+                for (int k = 0; k < m; ++k) {  // columns p, q
+                    const double a = at(k, p), b = at(k, q);
+                    at(k, p) = c * a - s * b;
+                    at(k, q) = s * a + c * b;
+                }
+                for (int k = 0; k < m; ++k) {  // rows p, q
+                    const double a = at(p, k), b = at(q, k);
+                    at(p, k) = c * a - s * b;
+                    at(q, k) = s * a + c * b;
+                }
+                at(p, q) = at(q, p) = 0.0;
+                for (int k = 0; k < m; ++k) {
+                    const double a = Z[k + size_t(p) * m], b = Z[k + size_t(q) * m];
+                    Z[k + size_t(p) * m] = c * a - s * b;
+                    Z[k + size_t(q) * m] = s * a + c * b;
+                }
+            }
+    }
+    w.resize(m);
+    for (int i = 0; i < m; ++i) w[i] = at(i, i);
+}
+
+bool small_inverse(int p, std::vector<double> &A /* p*p col-major, overwritten by inverse */)
+{
+    std::vector<double> I(size_t(p) * p, 0.0);
+    for (int i = 0; i < p; ++i) I[i + size_t(i) * p] = 1.0;
+    auto a = [&](int i, int j) -> double & { return A[i + size_t(j) * p]; };
+    auto b = [&](int i, int j) -> double & { return I[i + size_t(j) * p]; };
+    for (int c = 0; c < p; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < p; ++r)
+            if (std::fabs(a(r, c)) > std::fabs(a(piv, c))) piv = r;
+        if (a(piv, c) == 0.0) return false;
+        for (int k = 0; k < p; ++k) { std::swap(a(c, k), a(piv, k)); std::swap(b(c, k), b(piv, k)); }
+        const double d = 1.0 / a(c, c);
+        for (int k = 0; k < p; ++k) { a(c, k) *= d; b(c, k) *= d; }
+        for (int r = 0; r < p; ++r) {
+            if (r == c) continue;
+            const double f = a(r, c);
+            if (f == 0.0) continue;
+            for (int k = 0; k < p; ++k) { a(r, k) -= f * a(c, k); b(r, k) -= f * b(c, k); }
+        }
+    }
+    A.swap(I);
+    return true;
+}
+
+// Work buffers of one solve.
+template <typename T>
+struct SqmrBufs {
+    T *r, *q, *t, *d, *x, *u, *b;
+    jdmi::SqmrState *st;
+    double *partial, *red, *coef, *g;
+    int *done_host;  // pinned
+};
+
+template <typename T>
+struct Solver {
+    Setup &S;
+    const DevPrecond<T> &pc;
+    const T *eps;
+    hipStream_t s;
+    int n;
+    SqmrBufs<T> B{};
+    DevMem mem;
+
+    Solver(Setup &S_, const DevPrecond<T> &pc_, const T *eps_) : S(S_), pc(pc_), eps(eps_), s(S_.stream), n(S_.n)
+    {
+        B.r = mem.alloc<T>(n);
+        B.q = mem.alloc<T>(n);
+        B.t = mem.alloc<T>(n);
+        B.d = mem.alloc<T>(n);
+        B.x = mem.alloc<T>(n);
+        B.u = mem.alloc<T>(n);
+        B.b = mem.alloc<T>(n);
+        B.st = mem.alloc<jdmi::SqmrState>(1);
+        B.partial = mem.alloc<double>(size_t(256) * jdmi::kRedBlocks);
+        B.red = mem.alloc<double>(256);
+        B.coef = mem.alloc<double>(256);
+        B.g = mem.alloc<double>(256);
+        HIPCHK(hipHostMalloc((void **)&B.done_host, sizeof(int), hipHostMallocDefault));
+    }
+    ~Solver() { (void)hipHostFree(B.done_host); }
+
+    // Simplified QMR for (I - Qt Qt^T)(A - shift I) x = b, b already orthogonal to Qt,
+    // with preconditioner K^{-1} - Y M Y^T (M = (Qt^T Y)^{-1}, p x p on the device).
+    // Returns the number of steps.  x is left in B.x.
+    int sqmr(double shift, const T *Qt, const T *Y, int p, const double *dM, double rtol, int maxit)
+    {
+        const int *skip_a = &B.st->done;
+        const int *skip_b = &B.st->done_next;
+        jdmi::launch_sqmr_init<T>(n, B.b, B.r, B.x, B.d, s);
+        jdmi::launch_dot<T>(n, B.r, B.r, B.partial, B.red + 0, s);
+        // u = P r
+        precond_projected(B.r, B.u, Qt, Y, p, dM, nullptr);
+        jdmi::launch_dot<T>(n, B.r, B.u, B.partial, B.red + 1, s);
+        jdmi::launch_sqmr_scalar_start(B.st, B.red + 0, B.red + 1, rtol, s);
+        HIPCHK(hipMemcpyAsync(B.q, B.u, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+        int its = 0;
+        for (int j = 1; j <= maxit; ++j) {
+            // t = (I - Qt Qt^T)(A - shift I) q
+            jdmi::launch_stencil<T>(S.L, eps, shift, B.q, B.t, s, skip_a);
+            if (p > 0) {
+                jdmi::launch_multidot<T>(n, p, Qt, n, B.t, B.partial, B.coef, s, skip_a);
+                jdmi::launch_sub_qc<T>(n, p, Qt, n, B.coef, B.t, s, skip_a);
+            }
+            jdmi::launch_dot<T>(n, B.q, B.t, B.partial, B.red + 2, s, skip_a);
+            jdmi::launch_sqmr_scalar_alpha(B.st, B.red + 2, s);
+            jdmi::launch_sqmr_update_r<T>(n, B.st, B.t, B.r, B.partial, B.red + 3, s);
+            jdmi::launch_sqmr_scalar_theta(B.st, B.red + 3, s);
+            jdmi::launch_sqmr_update_xd<T>(n, B.st, B.q, B.d, B.x, s);
+            precond_projected(B.r, B.u, Qt, Y, p, dM, skip_b);
+            jdmi::launch_dot<T>(n, B.r, B.u, B.partial, B.red + 4, s, skip_b);
+            jdmi::launch_sqmr_scalar_beta(B.st, B.red + 4, s);
+            jdmi::launch_sqmr_update_q<T>(n, B.st, B.u, B.q, s);
+            HIPCHK(hipMemcpyAsync(B.done_host, &B.st->done, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            its = j;
+            if (*B.done_host) break;
+        }
+        HIPCHK(hipGetLastError());
+        jdmi::SqmrState hs;
+        HIPCHK(hipMemcpyAsync(&hs, B.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        (void)its;
+        return hs.j;
+    }
+
+    void precond_projected(const T *in, T *out, const T *Qt, const T *Y, int p, const double *dM, const int *skip)
+    {
+        pc.apply(in, out, s, skip);
+        if (p > 0) {
+            jdmi::launch_multidot<T>(n, p, Qt, n, out, B.partial, B.coef, s, skip);
+            jdmi::launch_small_matvec(p, dM, B.coef, B.g, skip, s);
+            jdmi::launch_sub_qc<T>(n, p, Y, n, B.g, out, s, skip);
+        }
+    }
+};
+
+struct Outputs {
+    double *evals, *evecs_host, *resid;
+    void *evecs_device;
+};
+
+template <typename T>
+int jd_run(Setup &S, const DevPrecond<T> &pc, const T *eps, int k, double tol, Outputs out, jd_info *info)
+{
+    const double t0 = now_s();
+    const int n = S.n;
+    hipStream_t s = S.stream;
+    jd_options o = S.opt;
+    const int jmin = o.jmin > 0 ? o.jmin : std::max(k + 5, 10);
+    const int jmax = o.jmax > 0 ? std::max(o.jmax, jmin + 1) : 2 * jmin;
+    const int max_outer = o.max_outer > 0 ? o.max_outer : 60 * k + 200;
+    if (jmax > 120) throw JdError(JD_EINVAL, "jmax too large");
+    const double anorm = S.anorm;
+    const double sigma = S.sigma;
+
+    Solver<T> sv(S, pc, eps);
+    DevMem mem;
+    double *V = mem.alloc<double>(size_t(n) * jmax);
+    double *AV = mem.alloc<double>(size_t(n) * jmax);
+    double *V2 = mem.alloc<double>(size_t(n) * jmax);  // restart / deflation target
+    double *Q = mem.alloc<double>(size_t(n) * k);
+    double *t64 = mem.alloc<double>(n);
+    double *u64 = mem.alloc<double>(n);
+    double *Au64 = mem.alloc<double>(n);
+    double *r64 = mem.alloc<double>(n);
+    T *Qt = mem.alloc<T>(size_t(n) * (k + 1));
+    T *Y = mem.alloc<T>(size_t(n) * (k + 1));
+    double *dsm = mem.alloc<double>(size_t(jmax) * jmax);  // small matrices / vectors
+    double *dM = mem.alloc<double>(size_t(k + 1) * (k + 1));
+    double *partial = sv.B.partial;
+    double *red = mem.alloc<double>(256);
+
+    auto d2h = [&](double *h, const double *d, size_t cnt) {
+        HIPCHK(hipMemcpyAsync(h, d, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    };
+    auto h2d = [&](double *d, const double *h, size_t cnt) {
+        HIPCHK(hipMemcpyAsync(d, h, cnt * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    };
+
+    // start: t = K^{-1} (seeded random vector)
+    jdmi::launch_random_vector(n, S.seed ^ 0x5DEECE66Dull, r64, s);
+    jdmi::launch_convert<double, T>(n, r64, sv.B.b, 1.0, s);
+    pc.apply(sv.B.b, sv.B.u, s);
+    jdmi::launch_convert<T, double>(n, sv.B.u, t64, 1.0, s);
+
+    int m = 0, nq = 0, outer = 0, inner_total = 0, solves_this_pair = 0;
+    std::vector<double> H(size_t(jmax) * jmax, 0.0), lam(k, 0.0);
+    std::vector<double> Hq(size_t(k + 1) * (k + 1), 0.0);
+    std::vector<double> hw, hZ, hcol(256);
+    bool finished = false;
+    while (!finished && outer < max_outer) {
+        ++outer;
+        // ---- orthogonalise t against [Q V] (classical Gram-Schmidt, twice) ----
+        for (int pass = 0; pass < 2; ++pass) {
+            if (nq > 0) {
+                jdmi::launch_multidot<double>(n, nq, Q, n, t64, partial, red, s);
+                jdmi::launch_sub_qc<double>(n, nq, Q, n, red, t64, s);
+            }
+            if (m > 0) {
+                jdmi::launch_multidot<double>(n, m, V, n, t64, partial, red + 128, s);
+                jdmi::launch_sub_qc<double>(n, m, V, n, red + 128, t64, s);
+            }
+        }
+        jdmi::launch_dot<double>(n, t64, t64, partial, red, s);
+        double nrm2;
+        d2h(&nrm2, red, 1);
+        if (!(nrm2 > 1e-24) || !std::isfinite(nrm2)) {
+            // the correction lies in the search space: continue with a fresh direction
+            jdmi::launch_random_vector(n, S.seed + 7919ull * uint64_t(outer), t64, s);
+            continue;
+        }
+        jdmi::launch_scale_by_inv_sqrt(n, red, t64, s);
+        HIPCHK(hipMemcpyAsync(V + size_t(m) * n, t64, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        jdmi::launch_stencil<double>(S.L, S.eps64, 0.0, V + size_t(m) * n, AV + size_t(m) * n, s);
+        jdmi::launch_multidot<double>(n, m + 1, V, n, AV + size_t(m) * n, partial, red, s);
+        d2h(hcol.data(), red, m + 1);
+        for (int i = 0; i <= m; ++i) {
+            H[i + size_t(m) * jmax] = hcol[i];
+            H[m + size_t(i) * jmax] = hcol[i];
+        }
+        ++m;
+        // ---- Rayleigh-Ritz, selection, acceptance, locking ----
+        double theta = 0, rnorm = 0;
+        std::vector<int> ord;
+        while (true) {
+            std::vector<double> Hm(size_t(m) * m);
+            for (int j = 0; j < m; ++j)
+                for (int i = 0; i < m; ++i) Hm[i + size_t(j) * m] = H[i + size_t(j) * jmax];
+            small_symeig(m, Hm, hw, hZ);
+            ord.resize(m);
+            std::iota(ord.begin(), ord.end(), 0);
+            std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+                const double da = std::fabs(hw[a] - sigma), db = std::fabs(hw[b] - sigma);
+                return da != db ? da < db : hw[a] < hw[b];
+            });
+            theta = hw[ord[0]];
+            // S columns in selection order on the device
+            std::vector<double> Sord(size_t(m) * m);
+            for (int c = 0; c < m; ++c)
+                for (int i = 0; i < m; ++i) Sord[i + size_t(c) * m] = hZ[i + size_t(ord[c]) * m];
+            h2d(dsm, Sord.data(), Sord.size());
+            jdmi::launch_gemv_vs(n, m, V, n, dsm, u64, s);
+            jdmi::launch_gemv_vs(n, m, AV, n, dsm, Au64, s);
+            HIPCHK(hipMemcpyAsync(r64, Au64, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            jdmi::launch_axpby_d(n, -theta, u64, 1.0, r64, s);
+            jdmi::launch_dot<double>(n, r64, r64, partial, red, s);
+            double rr;
+            d2h(&rr, red, 1);
+            rnorm = std::sqrt(std::max(rr, 0.0));
+            bool locked = false;
+            if (rnorm <= tol * anorm) {
+                // acceptance on a freshly computed residual and Rayleigh quotient
+                jdmi::launch_stencil<double>(S.L, S.eps64, 0.0, u64, Au64, s);
+                jdmi::launch_dot<double>(n, u64, Au64, partial, red, s);
+                jdmi::launch_dot<double>(n, u64, u64, partial, red + 1, s);
+                double q2[2];
+                d2h(q2, red, 2);
+                const double rq = q2[0] / q2[1];
+                HIPCHK(hipMemcpyAsync(r64, Au64, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                jdmi::launch_axpby_d(n, -rq, u64, 1.0, r64, s);
+                jdmi::launch_dot<double>(n, r64, r64, partial, red, s);
+                d2h(&rr, red, 1);
+                const double rfresh = std::sqrt(std::max(rr, 0.0) / q2[1]);
+                if (rfresh <= tol * anorm) {
+                    jdmi::launch_axpby_d(n, 1.0 / std::sqrt(q2[1]), u64, 0.0, Q + size_t(nq) * n, s);
+                    lam[nq] = rq;
+                    // preconditioner image of the new locked vector, and its row of Qt^T Y
+                    jdmi::launch_convert<double, T>(n, Q + size_t(nq) * n, Qt + size_t(nq) * n, 1.0, s);
+                    pc.apply(Qt + size_t(nq) * n, Y + size_t(nq) * n, s);
+                    jdmi::launch_multidot<T>(n, nq + 1, Qt, n, Y + size_t(nq) * n, partial, red, s);
+                    d2h(hcol.data(), red, nq + 1);
+                    for (int i = 0; i <= nq; ++i) {
+                        Hq[i + size_t(nq) * (k + 1)] = hcol[i];
+                        Hq[nq + size_t(i) * (k + 1)] = hcol[i];
+                    }
+                    ++nq;
+                    solves_this_pair = 0;
+                    locked = true;
+                    // deflate: keep the other Ritz vectors
+                    if (m > 1) {
+                        jdmi::launch_gemm_vs(n, m, m - 1, V, n, dsm + m, m, V2, n, s);
+                        HIPCHK(hipMemcpyAsync(V, V2, size_t(n) * (m - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
+                        jdmi::launch_gemm_vs(n, m, m - 1, AV, n, dsm + m, m, V2, n, s);
+                        HIPCHK(hipMemcpyAsync(AV, V2, size_t(n) * (m - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
+                    }
+                    std::fill(H.begin(), H.end(), 0.0);
+                    for (int c = 1; c < m; ++c) H[(c - 1) + size_t(c - 1) * jmax] = hw[ord[c]];
+                    --m;
+                    if (nq == k) { finished = true; break; }
+                    if (m == 0) break;
+                    continue;
+                }
+                rnorm = rfresh;
+                theta = rq;
+            }
+            if (!locked) break;
+        }
+        if (finished) break;
+        if (m == 0) {
+            jdmi::launch_random_vector(n, S.seed + 104729ull * uint64_t(outer), r64, s);
+            jdmi::launch_convert<double, T>(n, r64, sv.B.b, 1.0, s);
+            pc.apply(sv.B.b, sv.B.u, s);
+            jdmi::launch_convert<T, double>(n, sv.B.u, t64, 1.0, s);
+            continue;
+        }
+        // ---- restart ----
+        if (m == jmax) {
+            jdmi::launch_gemm_vs(n, m, jmin, V, n, dsm, m, V2, n, s);
+            HIPCHK(hipMemcpyAsync(V, V2, size_t(n) * jmin * sizeof(double), hipMemcpyDeviceToDevice, s));
+            jdmi::launch_gemm_vs(n, m, jmin, AV, n, dsm, m, V2, n, s);
+            HIPCHK(hipMemcpyAsync(AV, V2, size_t(n) * jmin * sizeof(double), hipMemcpyDeviceToDevice, s));
+            std::fill(H.begin(), H.end(), 0.0);
+            for (int c = 0; c < jmin; ++c) H[c + size_t(c) * jmax] = hw[ord[c]];
+            m = jmin;
+        }
+        // ---- correction equation ----
+        const int p = nq + 1;
+        jdmi::launch_convert<double, T>(n, u64, Qt + size_t(nq) * n, 1.0, s);
+        pc.apply(Qt + size_t(nq) * n, Y + size_t(nq) * n, s);
+        jdmi::launch_multidot<T>(n, p, Qt, n, Y + size_t(nq) * n, partial, red, s);
+        d2h(hcol.data(), red, p);
+        std::vector<double> Mh(size_t(p) * p);
+        for (int j = 0; j < p; ++j)
+            for (int i = 0; i < p; ++i) {
+                double v;
+                if (i == nq) v = hcol[j];
+                else if (j == nq) v = hcol[i];
+                else v = Hq[i + size_t(j) * (k + 1)];
+                Mh[i + size_t(j) * p] = v;
+            }
+        if (!small_inverse(p, Mh)) throw JdError(JD_EDEVICE, "singular projected preconditioner matrix");
+        h2d(dM, Mh.data(), Mh.size());
+        const double shift = (rnorm < o.switch_tol * anorm) ? theta : sigma;
+        // rhs = -(I - Qt Qt^T) r
+        jdmi::launch_convert<double, T>(n, r64, sv.B.b, -1.0, s);
+        jdmi::launch_multidot<T>(n, p, Qt, n, sv.B.b, partial, red, s);
+        jdmi::launch_sub_qc<T>(n, p, Qt, n, red, sv.B.b, s);
+        ++solves_this_pair;
+        const double rtol = std::max(std::pow(2.0, -double(solves_this_pair)), 1e-10);
+        inner_total += sv.sqmr(shift, Qt, Y, p, dM, rtol, o.max_inner);
+        jdmi::launch_convert<T, double>(n, sv.B.x, t64, 1.0, s);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    const double solve_s = now_s() - t0;
+
+    // ---- outputs: sorted pairs, residuals from a fresh product, sign convention ----
+    std::vector<int> idx(nq);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+        const double da = std::fabs(lam[a] - sigma), db = std::fabs(lam[b] - sigma);
+        return da != db ? da < db : lam[a] < lam[b];
+    });
+    std::vector<double> hostQ;
+    const bool want_vec = out.evecs_host || out.evecs_device;
+    if (want_vec) {
+        hostQ.resize(size_t(n) * std::max(nq, 1));
+        if (nq > 0) d2h(hostQ.data(), Q, size_t(n) * nq);
+    }
+    for (int c = 0; c < k; ++c) {
+        if (c >= nq) {
+            out.evals[c] = std::nan("");
+            if (out.resid) out.resid[c] = std::nan("");
+            continue;
+        }
+        const int q = idx[c];
+        out.evals[c] = lam[q];
+        if (out.resid) {
+            jdmi::launch_stencil<double>(S.L, S.eps64, 0.0, Q + size_t(q) * n, Au64, s);
+            jdmi::launch_axpby_d(n, -lam[q], Q + size_t(q) * n, 1.0, Au64, s);
+            jdmi::launch_dot<double>(n, Au64, Au64, partial, red, s);
+            double rr;
+            d2h(&rr, red, 1);
+            out.resid[c] = std::sqrt(std::max(rr, 0.0)) / anorm;
+        }
+    }
+    if (want_vec) {
+        std::vector<double> col(n);
+        for (int c = 0; c < std::min(k, nq); ++c) {
+            const double *src = &hostQ[size_t(idx[c]) * n];
+            int imax = 0;
+            for (int i = 1; i < n; ++i)
+                if (std::fabs(src[i]) > std::fabs(src[imax])) imax = i;
+            const double sg = src[imax] < 0 ? -1.0 : 1.0;
+            for (int i = 0; i < n; ++i) col[i] = sg * src[i];
+            if (out.evecs_host) std::memcpy(out.evecs_host + size_t(c) * n, col.data(), n * sizeof(double));
+            if (out.evecs_device)
+                HIPCHK(hipMemcpyAsync(static_cast<double *>(out.evecs_device) + size_t(c) * n, col.data(),
+                                      n * sizeof(double), hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        for (int c = nq; c < k; ++c) {
+            if (out.evecs_host) std::fill(out.evecs_host + size_t(c) * n, out.evecs_host + size_t(c + 1) * n, std::nan(""));
+        }
+    }
+    if (info) {
+        info->n_converged = nq;
+        info->outer_its = outer;
+        info->inner_its = inner_total;
+        info->solve_s = solve_s;
+        info->setup_s = S.setup_s;
+        info->levels = int(S.ml.levels.size());
+        info->n_2x2 = S.n2x2;
+        info->coarse_n = S.ml.coarse_n;
+        info->fill = S.ml.fill;
+        info->anorm = anorm;
+        info->device_bytes = S.mem.bytes + mem.bytes + sv.mem.bytes;
+    }
+    return nq == k ? JD_OK : JD_ENOCONV;
+}
+
+template <typename F>
+int guarded(F &&f)
+{
+    try {
+        g_err.clear();
+        return f();
+    } catch (const JdError &e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return JD_ENOMEM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return JD_EDEVICE;
+    }
+}
+
+void check_solve_args(int n, int k, double tol, const double *evals)
+{
+    if (k < 1 || k > n || k > 64) throw JdError(JD_EINVAL, "k must satisfy 1 <= k <= min(n, 64)");
+    if (!(tol >= 1e-14 && tol < 1.0)) throw JdError(JD_EINVAL, "tol must be in [1e-14, 1)");
+    if (!evals) throw JdError(JD_EINVAL, "evals must not be NULL");
+}
+
+}  // namespace
+
+struct jd_problem {
+    Setup S;
+};
+struct jd_precond {
+    Setup S;
+};
+
+extern "C" {
+
+const char *jd_last_error(void) { return g_err.c_str(); }
+const char *jd_version(void) { return "jdmi 0.1 (gfx950)"; }
+
+int jd_setup(int L, double W, uint64_t seed, double sigma, const jd_options *opt, jd_problem **out)
+{
+    return guarded([&] {
+        if (!out) throw JdError(JD_EINVAL, "out must not be NULL");
+        *out = nullptr;
+        auto p = std::make_unique<jd_problem>();
+        build_setup(p->S, L, W, seed, sigma, opt);
+        *out = p.release();
+        return JD_OK;
+    });
+}
+
+void jd_problem_free(jd_problem *p)
+{
+    if (!p) return;
+    const bool own = p->S.own_stream;
+    hipStream_t s = p->S.stream;
+    p->S.mem.release();
+    delete p;
+    if (own) (void)hipStreamDestroy(s);
+}
+
+int jd_problem_info(const jd_problem *p, jd_info *info)
+{
+    return guarded([&] {
+        if (!p || !info) throw JdError(JD_EINVAL, "NULL argument");
+        std::memset(info, 0, sizeof(*info));
+        info->levels = int(p->S.ml.levels.size());
+        info->n_2x2 = p->S.n2x2;
+        info->coarse_n = p->S.ml.coarse_n;
+        info->fill = p->S.ml.fill;
+        info->setup_s = p->S.setup_s;
+        info->anorm = p->S.anorm;
+        info->device_bytes = p->S.mem.bytes;
+        return JD_OK;
+    });
+}
+
+int jd_problem_solve(jd_problem *p, int k, double tol, double *evals, double *evecs_host, void *evecs_device,
+                     double *resid, jd_info *info)
+{
+    return guarded([&] {
+        if (!p) throw JdError(JD_EINVAL, "NULL problem");
+        check_solve_args(p->S.n, k, tol, evals);
+        Outputs o{evals, evecs_host, resid, evecs_device};
+        if (p->S.opt.precision == JD_MIXED) return jd_run<float>(p->S, p->S.pc32, p->S.eps32, k, tol, o, info);
+        return jd_run<double>(p->S, p->S.pc64, p->S.eps64, k, tol, o, info);
+    });
+}
+
+int jd_solve(int L, double W, uint64_t seed, double sigma, int k, double tol, double *evals, double *evecs,
+             double *resid, const jd_options *opt, jd_info *info)
+{
+    jd_problem *p = nullptr;
+    int rc = guarded([&] {
+        check_problem_args(L, W, sigma, opt);
+        check_solve_args(L * L * L, k, tol, evals);
+        return JD_OK;
+    });
+    if (rc != JD_OK) return rc;
+    rc = jd_setup(L, W, seed, sigma, opt, &p);
+    if (rc != JD_OK) return rc;
+    rc = jd_problem_solve(p, k, tol, evals, evecs, nullptr, resid, info);
+    std::string keep = g_err;
+    jd_problem_free(p);
+    g_err = keep;
+    return rc;
+}
+
+int jd_gen_diag(int L, double W, uint64_t seed, double *d_eps, float *d_eps32, void *stream)
+{
+    return guarded([&] {
+        check_problem_args(L, W, 0.0, nullptr);
+        if (!d_eps) throw JdError(JD_EINVAL, "d_eps must not be NULL");
+        jdmi::launch_gen_diag(L, W, seed, d_eps, d_eps32, static_cast<hipStream_t>(stream));
+        HIPCHK(hipGetLastError());
+        return JD_OK;
+    });
+}
+
+int jd_stencil_spmv(int L, int precision, const void *d_eps, double shift, const void *d_x, void *d_y, void *stream)
+{
+    return guarded([&] {
+        check_problem_args(L, 0.0, shift, nullptr);
+        if (!d_eps || !d_x || !d_y) throw JdError(JD_EINVAL, "NULL device pointer");
+        if (d_x == d_y) throw JdError(JD_EINVAL, "x and y must not alias");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (precision == JD_FP64)
+            jdmi::launch_stencil<double>(L, static_cast<const double *>(d_eps), shift, static_cast<const double *>(d_x),
+                                         static_cast<double *>(d_y), s);
+        else if (precision == JD_MIXED)
+            jdmi::launch_stencil<float>(L, static_cast<const float *>(d_eps), shift, static_cast<const float *>(d_x),
+                                        static_cast<float *>(d_y), s);
+        else
+            throw JdError(JD_EINVAL, "unknown precision");
+        HIPCHK(hipGetLastError());
+        return JD_OK;
+    });
+}
+
+int jd_precond_create(int L, double W, uint64_t seed, double sigma, const jd_options *opt, jd_precond **out)
+{
+    return guarded([&] {
+        if (!out) throw JdError(JD_EINVAL, "out must not be NULL");
+        *out = nullptr;
+        auto p = std::make_unique<jd_precond>();
+        build_setup(p->S, L, W, seed, sigma, opt);
+        *out = p.release();
+        return JD_OK;
+    });
+}
+
+int jd_precond_apply(jd_precond *p, int precision, const void *d_in, void *d_out, void *stream)
+{
+    return guarded([&] {
+        if (!p || !d_in || !d_out) throw JdError(JD_EINVAL, "NULL argument");
+        if (d_in == d_out) throw JdError(JD_EINVAL, "in and out must not overlap");
+        hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the legacy default stream
+        if (precision == JD_FP64)
+            p->S.pc64.apply(static_cast<const double *>(d_in), static_cast<double *>(d_out), s);
+        else if (precision == JD_MIXED)
+            p->S.pc32.apply(static_cast<const float *>(d_in), static_cast<float *>(d_out), s);
+        else
+            throw JdError(JD_EINVAL, "unknown precision");
+        HIPCHK(hipGetLastError());
+        return JD_OK;
+    });
+}
+
+int jd_precond_levels(const jd_precond *p, int cap, int *sizes, int *nB, long long *nnzG)
+{
+    if (!p) { g_err = "NULL precond"; return JD_EINVAL; }
+    const auto &ml = p->S.ml;
+    const int nl = int(ml.levels.size());
+    for (int l = 0; l <= nl && l < cap; ++l) {
+        if (sizes) sizes[l] = (l < nl) ? ml.levels[l].nB + ml.levels[l].n_after : ml.coarse_n;
+        if (nB) nB[l] = (l < nl) ? ml.levels[l].nB : 0;
+        if (nnzG) nnzG[l] = (l < nl) ? (long long)ml.levels[l].g_col.size() : 0;
+    }
+    return nl;
+}
+
+void jd_precond_free(jd_precond *p)
+{
+    if (!p) return;
+    const bool own = p->S.own_stream;
+    hipStream_t s = p->S.stream;
+    p->S.mem.release();
+    delete p;
+    if (own) (void)hipStreamDestroy(s);
+}
+
+int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int pcols, const double *d_b, double *d_x,
+                            double rtol, int maxit, int *its)
+{
+    return guarded([&] {
+        if (!p || !d_b || !d_x) throw JdError(JD_EINVAL, "NULL argument");
+        if (pcols < 0 || pcols > 64 || (pcols > 0 && !d_Q)) throw JdError(JD_EINVAL, "bad projection block");
+        if (!(rtol > 0) || maxit < 1) throw JdError(JD_EINVAL, "rtol must be > 0 and maxit >= 1");
+        if (!std::isfinite(shift)) throw JdError(JD_EINVAL, "shift must be finite");
+        Setup &S = p->S;
+        const int n = S.n;
+        hipStream_t s = S.stream;
+        auto run = [&](auto tag, const auto &pc, const auto *eps) {
+            using T = decltype(tag);
+            Solver<T> sv(S, pc, eps);
+            DevMem mem;
+            const int pc_ = pcols;
+            T *Qt = mem.alloc<T>(size_t(n) * std::max(pc_, 1));
+            T *Y = mem.alloc<T>(size_t(n) * std::max(pc_, 1));
+            double *dM = mem.alloc<double>(size_t(std::max(pc_, 1)) * std::max(pc_, 1));
+            std::vector<double> Mh(size_t(pc_) * pc_);
+            for (int c = 0; c < pc_; ++c) {
+                jdmi::launch_convert<double, T>(n, d_Q + size_t(c) * n, Qt + size_t(c) * n, 1.0, s);
+                pc.apply(Qt + size_t(c) * n, Y + size_t(c) * n, s);
+            }
+            for (int c = 0; c < pc_; ++c) {
+                jdmi::launch_multidot<T>(n, pc_, Qt, n, Y + size_t(c) * n, sv.B.partial, sv.B.red, s);
+                std::vector<double> h(pc_);
+                HIPCHK(hipMemcpyAsync(h.data(), sv.B.red, pc_ * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                for (int i = 0; i < pc_; ++i) Mh[i + size_t(c) * pc_] = h[i];
+            }
+            if (pc_ > 0) {
+                if (!small_inverse(pc_, Mh)) throw JdError(JD_EINVAL, "projection block is singular for K^{-1}");
+                HIPCHK(hipMemcpyAsync(dM, Mh.data(), Mh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            }
+            jdmi::launch_convert<double, T>(n, d_b, sv.B.b, 1.0, s);
+            if (pc_ > 0) {
+                jdmi::launch_multidot<T>(n, pc_, Qt, n, sv.B.b, sv.B.partial, sv.B.red, s);
+                jdmi::launch_sub_qc<T>(n, pc_, Qt, n, sv.B.red, sv.B.b, s);
+            }
+            const int k_ = sv.sqmr(shift, Qt, Y, pc_, dM, rtol, maxit);
+            jdmi::launch_convert<T, double>(n, sv.B.x, d_x, 1.0, s);
+            HIPCHK(hipStreamSynchronize(s));
+            if (its) *its = k_;
+        };
+        if (S.opt.precision == JD_MIXED) run(float(0), S.pc32, S.eps32);
+        else run(double(0), S.pc64, S.eps64);
+        return JD_OK;
+    });
+}
+
+}  // extern "C"

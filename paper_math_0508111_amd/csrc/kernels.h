@@ -1,0 +1,88 @@
+// Device kernels of the Jacobi-Davidson hot path (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace jdmi {
+
+constexpr int kBlock = 256;        // threads per workgroup for streaming kernels
+constexpr int kRedBlocks = 1024;   // fixed grid of the deterministic reductions
+
+// Device-resident scalar state of one simplified-QMR solve.
+struct SqmrState {
+    double rho, sigma, alpha, tau, tau0, theta, theta_old, c1, c2, beta, rr;
+    double tol;       // stop when tau * sqrt(j+1) <= tol * tau0
+    int j;
+    int done;         // set before this step: every kernel of the step is skipped
+    int done_next;    // set during this step: the rest of the step is skipped
+    int breakdown;
+};
+
+// ---- K1 / K2 --------------------------------------------------------------------
+void launch_gen_diag(int L, double W, uint64_t seed, double *eps, float *eps32, hipStream_t s);
+template <typename T>
+void launch_stencil(int L, const T *eps, double shift, const T *x, T *y, hipStream_t s,
+                    const int *skip = nullptr);
+
+// ---- multilevel apply ---------------------------------------------------------------
+template <typename T>
+struct DevLevel {
+    int off, nB, n_after;
+    const int64_t *g_ptr; const int *g_col; const T *g_val;
+    const int64_t *gt_ptr; const int *gt_col; const T *gt_val;
+    const T *bd, *bo; const int *bp;
+};
+template <typename T>
+void launch_gather(int n, const int *perm, const T *b, T *w, hipStream_t s, const int *skip);
+template <typename T>
+void launch_scatter(int n, const int *perm, const T *x, T *out, hipStream_t s, const int *skip);
+template <typename T>
+void launch_down(const DevLevel<T> &lv, T *w, hipStream_t s, const int *skip);
+template <typename T>
+void launch_up(const DevLevel<T> &lv, const T *w, T *x, hipStream_t s, const int *skip);
+template <typename T>
+void launch_coarse(int nc, int off, const T *cinv, const T *w, T *x, hipStream_t s, const int *skip);
+
+// ---- reductions (deterministic two-stage; results stay on the device) ---------------
+// partial[c * kRedBlocks + b] for c < ncols; out[c] = sum
+template <typename T>
+void launch_multidot(int n, int ncols, const T *Q, int64_t ldq, const T *y, double *partial,
+                     double *out, hipStream_t s, const int *skip = nullptr);
+template <typename T>
+void launch_dot(int n, const T *x, const T *y, double *partial, double *out, hipStream_t s,
+                const int *skip = nullptr);
+
+// y -= Q c   (c on the device, ncols entries, double); optional skip flag
+template <typename T>
+void launch_sub_qc(int n, int ncols, const T *Q, int64_t ldq, const double *c, T *y, hipStream_t s,
+                   const int *skip = nullptr, double alpha = 1.0);
+// y = V s for an n x m column-major V (double); y may not alias V
+void launch_gemv_vs(int n, int m, const double *V, int64_t ldv, const double *s, double *y, hipStream_t st);
+// Vout[:, c] = V * S[:, c] for c < mout (S m x mout column-major, leading dim lds)
+void launch_gemm_vs(int n, int m, int mout, const double *V, int64_t ldv, const double *S, int lds,
+                    double *Vout, int64_t ldo, hipStream_t st);
+
+// elementwise helpers
+template <typename Tin, typename Tout>
+void launch_convert(int n, const Tin *x, Tout *y, double scale, hipStream_t s);
+void launch_axpby_d(int n, double a, const double *x, double b, double *y, hipStream_t s);
+void launch_scale_by_inv_sqrt(int n, const double *nrm2, double *x, hipStream_t s);
+void launch_random_vector(int n, uint64_t seed, double *x, hipStream_t s);
+
+// ---- simplified QMR pieces (scalars read from SqmrState on the device) -----------------
+template <typename T>
+void launch_sqmr_init(int n, const T *b, T *r, T *x, T *d, hipStream_t s);
+void launch_sqmr_scalar_start(SqmrState *st, const double *rr, const double *rho, double tol, hipStream_t s);
+void launch_sqmr_scalar_alpha(SqmrState *st, const double *sigma, hipStream_t s);
+void launch_sqmr_scalar_theta(SqmrState *st, const double *rr, hipStream_t s);
+void launch_sqmr_scalar_beta(SqmrState *st, const double *rho, hipStream_t s);
+template <typename T>
+void launch_sqmr_update_r(int n, SqmrState *st, const T *t, T *r, double *partial, double *rr, hipStream_t s);
+template <typename T>
+void launch_sqmr_update_xd(int n, SqmrState *st, const T *q, T *d, T *x, hipStream_t s);
+template <typename T>
+void launch_sqmr_update_q(int n, SqmrState *st, const T *u, T *q, hipStream_t s);
+// small dense product on the device: out = M c (p x p, double), skip if done
+void launch_small_matvec(int p, const double *M, const double *c, double *out, const int *skip, hipStream_t s);
+
+}  // namespace jdmi

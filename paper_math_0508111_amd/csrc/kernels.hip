@@ -1,0 +1,590 @@
+// Device kernels of the Jacobi-Davidson hot path for gfx950 (wave64, 256 CUs).
+//
+// All streaming kernels are HBM-bound: one thread per row or site, unit-stride
+// access along the fastest lattice direction, no host synchronisation.  Reductions
+// are deterministic two-stage trees (wave shuffles, then LDS, then a fixed-order
+// final pass), so a result never depends on what else runs on the device.
+#include "kernels.h"
+
+#include <cmath>
+
+namespace jdmi {
+
+namespace {
+
+__host__ __device__ inline int nblocks(int64_t n, int b = kBlock)
+{
+    return int((n + b - 1) / b);
+}
+
+inline int red_blocks(int64_t n)
+{
+    int b = nblocks(n);
+    return b < 1 ? 1 : (b > kRedBlocks ? kRedBlocks : b);
+}
+
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// sum over a kBlock-thread workgroup, result in thread 0; fixed order
+__device__ inline double block_sum(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBlock / 64; ++w) r += sh[w];
+    __syncthreads();
+    return r;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------
+// K1: the disorder eps_s = W (u_s - 1/2), u_s from SplitMix64 output s+1 (counter form:
+// state = seed + (s+1) * 0x9E3779B97F4A7C15, then the two xor-shift-multiply rounds).
+// ---------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_gen_diag(int n, double W, uint64_t seed, double *eps, float *eps32)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    uint64_t z = seed + uint64_t(s + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double u = double(z >> 11) * 0x1.0p-53;
+    const double e = W * (u - 0.5);
+    eps[s] = e;
+    if (eps32) eps32[s] = float(e);
+}
+
+void launch_gen_diag(int L, double W, uint64_t seed, double *eps, float *eps32, hipStream_t s)
+{
+    const int n = L * L * L;
+    hipLaunchKernelGGL(k_gen_diag, dim3(nblocks(n)), dim3(kBlock), 0, s, n, W, seed, eps, eps32);
+}
+
+// ---------------------------------------------------------------------------------
+// K2: y = (A - shift I) x with A = -T + diag(eps) on the periodic lattice.
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_stencil(int L, int n, const T *__restrict__ eps, T shift,
+                                                    const T *__restrict__ x, T *__restrict__ y,
+                                                    const int *skip)
+{
+    if (skip && *skip) return;
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const int LL = L * L;
+    const int i = s % L, jk = s / L, j = jk % L, k = jk / L;
+    const int xm = (i == 0) ? s + L - 1 : s - 1;
+    const int xp = (i == L - 1) ? s - L + 1 : s + 1;
+    const int ym = (j == 0) ? s + LL - L : s - L;
+    const int yp = (j == L - 1) ? s - LL + L : s + L;
+    const int zm = (k == 0) ? s + n - LL : s - LL;
+    const int zp = (k == L - 1) ? s - n + LL : s + LL;
+    const T nb = ((x[xm] + x[xp]) + (x[ym] + x[yp])) + (x[zm] + x[zp]);
+    y[s] = (eps[s] - shift) * x[s] - nb;
+}
+
+template <typename T>
+void launch_stencil(int L, const T *eps, double shift, const T *x, T *y, hipStream_t s, const int *skip)
+{
+    const int n = L * L * L;
+    hipLaunchKernelGGL(k_stencil<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, L, n, eps, T(shift), x, y, skip);
+}
+
+// ---------------------------------------------------------------------------------
+// Multilevel preconditioner apply (global permuted positions, scalings folded in).
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gather(int n, const int *__restrict__ perm, const T *__restrict__ b,
+                                                   T *__restrict__ w, const int *skip)
+{
+    if (skip && *skip) return;
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) w[p] = b[perm[p]];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_scatter(int n, const int *__restrict__ perm, const T *__restrict__ x,
+                                                    T *__restrict__ out, const int *skip)
+{
+    if (skip && *skip) return;
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) out[perm[p]] = x[p];
+}
+
+// w[r] -= sum_c G[r, c] w[c] for the complement rows of one level
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_down(int row0, int nrows, const int64_t *__restrict__ ptr,
+                                                 const int *__restrict__ col, const T *__restrict__ val,
+                                                 T *__restrict__ w, const int *skip)
+{
+    if (skip && *skip) return;
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= nrows) return;
+    const int64_t b = ptr[q], e = ptr[q + 1];
+    if (b == e) return;
+    T acc = T(0);
+    for (int64_t p = b; p < e; ++p) acc += val[p] * w[col[p]];
+    w[row0 + q] -= acc;
+}
+
+// x[j] = D^{-1} w (1x1 or 2x2 block) - sum_r G^T[j, r] x[r] for the pivots of one level
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_up(int off, int nB, const int64_t *__restrict__ ptr,
+                                               const int *__restrict__ col, const T *__restrict__ val,
+                                               const T *__restrict__ bd, const T *__restrict__ bo,
+                                               const int *__restrict__ bp, const T *__restrict__ w,
+                                               T *__restrict__ x, const int *skip)
+{
+    if (skip && *skip) return;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nB) return;
+    const int j = off + t;
+    T acc = bd[t] * w[j] + bo[t] * w[bp[t]];
+    for (int64_t p = ptr[t], e = ptr[t + 1]; p < e; ++p) acc -= val[p] * x[col[p]];
+    x[j] = acc;
+}
+
+// x[off + i] = sum_j Cinv[i, j] w[off + j]: one wave per row
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_coarse(int nc, int off, const T *__restrict__ cinv,
+                                                   const T *__restrict__ w, T *__restrict__ x, const int *skip)
+{
+    if (skip && *skip) return;
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= nc) return;
+    const T *a = cinv + int64_t(row) * nc;
+    double acc = 0.0;
+    for (int c = lane; c < nc; c += 64) acc += double(a[c]) * double(w[off + c]);
+    acc = wave_sum(acc);
+    if (lane == 0) x[off + row] = T(acc);
+}
+
+template <typename T>
+void launch_gather(int n, const int *perm, const T *b, T *w, hipStream_t s, const int *skip)
+{
+    hipLaunchKernelGGL(k_gather<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, perm, b, w, skip);
+}
+template <typename T>
+void launch_scatter(int n, const int *perm, const T *x, T *out, hipStream_t s, const int *skip)
+{
+    hipLaunchKernelGGL(k_scatter<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, perm, x, out, skip);
+}
+template <typename T>
+void launch_down(const DevLevel<T> &lv, T *w, hipStream_t s, const int *skip)
+{
+    if (lv.n_after <= 0) return;
+    hipLaunchKernelGGL(k_down<T>, dim3(nblocks(lv.n_after)), dim3(kBlock), 0, s, lv.off + lv.nB, lv.n_after,
+                       lv.g_ptr, lv.g_col, lv.g_val, w, skip);
+}
+template <typename T>
+void launch_up(const DevLevel<T> &lv, const T *w, T *x, hipStream_t s, const int *skip)
+{
+    if (lv.nB <= 0) return;
+    hipLaunchKernelGGL(k_up<T>, dim3(nblocks(lv.nB)), dim3(kBlock), 0, s, lv.off, lv.nB, lv.gt_ptr, lv.gt_col,
+                       lv.gt_val, lv.bd, lv.bo, lv.bp, w, x, skip);
+}
+template <typename T>
+void launch_coarse(int nc, int off, const T *cinv, const T *w, T *x, hipStream_t s, const int *skip)
+{
+    if (nc <= 0) return;
+    hipLaunchKernelGGL(k_coarse<T>, dim3(nblocks(nc, kBlock / 64)), dim3(kBlock), 0, s, nc, off, cinv, w, x, skip);
+}
+
+// ---------------------------------------------------------------------------------
+// Reductions.
+// ---------------------------------------------------------------------------------
+constexpr int kDotChunk = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_multidot_partial(int n, int ncols, const T *__restrict__ Q, int64_t ldq,
+                                                             const T *__restrict__ y, double *__restrict__ partial,
+                                                             int pstride, const int *skip)
+{
+    if (skip && *skip) return;
+    __shared__ double sh[kBlock / 64];
+    const int c0 = blockIdx.y * kDotChunk;
+    const int nc = min(kDotChunk, ncols - c0);
+    double acc[kDotChunk];
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c) acc[c] = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+        const double yi = double(y[i]);
+#pragma unroll
+        for (int c = 0; c < kDotChunk; ++c)
+            if (c < nc) acc[c] += double(Q[i + int64_t(c0 + c) * ldq]) * yi;
+    }
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c) {
+        if (c < nc) {
+            const double r = block_sum(acc[c], sh);
+            if (threadIdx.x == 0) partial[int64_t(c0 + c) * pstride + blockIdx.x] = r;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_final_sum(int nparts, int pstride, const double *__restrict__ partial,
+                                                      double *__restrict__ out, const int *skip)
+{
+    if (skip && *skip) return;
+    __shared__ double sh[kBlock / 64];
+    const int c = blockIdx.x;
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kBlock) a += partial[int64_t(c) * pstride + b];
+    const double r = block_sum(a, sh);
+    if (threadIdx.x == 0) out[c] = r;
+}
+
+template <typename T>
+void launch_multidot(int n, int ncols, const T *Q, int64_t ldq, const T *y, double *partial, double *out,
+                     hipStream_t s, const int *skip)
+{
+    if (ncols <= 0) return;
+    const int nb = red_blocks(n);
+    dim3 grid(nb, (ncols + kDotChunk - 1) / kDotChunk);
+    hipLaunchKernelGGL(k_multidot_partial<T>, grid, dim3(kBlock), 0, s, n, ncols, Q, ldq, y, partial, kRedBlocks, skip);
+    hipLaunchKernelGGL(k_final_sum, dim3(ncols), dim3(kBlock), 0, s, nb, kRedBlocks, partial, out, skip);
+}
+
+template <typename T>
+void launch_dot(int n, const T *x, const T *y, double *partial, double *out, hipStream_t s, const int *skip)
+{
+    launch_multidot<T>(n, 1, x, n, y, partial, out, s, skip);
+}
+
+// y -= alpha * Q c
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sub_qc(int n, int ncols, const T *__restrict__ Q, int64_t ldq,
+                                                   const double *__restrict__ c, T *__restrict__ y, double alpha,
+                                                   const int *skip)
+{
+    if (skip && *skip) return;
+    __shared__ double cs[128];
+    for (int t = threadIdx.x; t < ncols; t += kBlock) cs[t] = c[t] * alpha;
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int k = 0; k < ncols; ++k) acc += double(Q[i + int64_t(k) * ldq]) * cs[k];
+    y[i] = T(double(y[i]) - acc);
+}
+
+template <typename T>
+void launch_sub_qc(int n, int ncols, const T *Q, int64_t ldq, const double *c, T *y, hipStream_t s,
+                   const int *skip, double alpha)
+{
+    if (ncols <= 0) return;
+    hipLaunchKernelGGL(k_sub_qc<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, ncols, Q, ldq, c, y, alpha, skip);
+}
+
+__global__ void __launch_bounds__(kBlock) k_gemv_vs(int n, int m, const double *__restrict__ V, int64_t ldv,
+                                                    const double *__restrict__ sv, double *__restrict__ y)
+{
+    __shared__ double cs[128];
+    for (int t = threadIdx.x; t < m; t += kBlock) cs[t] = sv[t];
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) acc += V[i + int64_t(k) * ldv] * cs[k];
+    y[i] = acc;
+}
+
+void launch_gemv_vs(int n, int m, const double *V, int64_t ldv, const double *s, double *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gemv_vs, dim3(nblocks(n)), dim3(kBlock), 0, st, n, m, V, ldv, s, y);
+}
+
+// Vout[:, c0 .. c0+7] = V * S[:, c0 .. c0+7]
+__global__ void __launch_bounds__(kBlock) k_gemm_vs(int n, int m, int mout, const double *__restrict__ V,
+                                                    int64_t ldv, const double *__restrict__ S, int lds,
+                                                    double *__restrict__ Vout, int64_t ldo)
+{
+    __shared__ double ss[128 * 8];
+    const int c0 = blockIdx.y * 8;
+    const int nc = min(8, mout - c0);
+    for (int t = threadIdx.x; t < m * 8; t += kBlock) {
+        const int r = t / 8, c = t % 8;
+        ss[t] = (c < nc) ? S[r + int64_t(c0 + c) * lds] : 0.0;
+    }
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    for (int k = 0; k < m; ++k) {
+        const double v = V[i + int64_t(k) * ldv];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] += v * ss[k * 8 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        if (c < nc) Vout[i + int64_t(c0 + c) * ldo] = acc[c];
+}
+
+void launch_gemm_vs(int n, int m, int mout, const double *V, int64_t ldv, const double *S, int lds, double *Vout,
+                    int64_t ldo, hipStream_t st)
+{
+    if (mout <= 0) return;
+    dim3 grid(nblocks(n), (mout + 7) / 8);
+    hipLaunchKernelGGL(k_gemm_vs, grid, dim3(kBlock), 0, st, n, m, mout, V, ldv, S, lds, Vout, ldo);
+}
+
+// ---------------------------------------------------------------------------------
+// Elementwise helpers.
+// ---------------------------------------------------------------------------------
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(kBlock) k_convert(int n, const Tin *__restrict__ x, Tout *__restrict__ y,
+                                                    double scale)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = Tout(double(x[i]) * scale);
+}
+template <typename Tin, typename Tout>
+void launch_convert(int n, const Tin *x, Tout *y, double scale, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(nblocks(n)), dim3(kBlock), 0, s, n, x, y, scale);
+}
+
+__global__ void __launch_bounds__(kBlock) k_axpby_d(int n, double a, const double *__restrict__ x, double b,
+                                                    double *__restrict__ y)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + b * y[i];
+}
+void launch_axpby_d(int n, double a, const double *x, double b, double *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpby_d, dim3(nblocks(n)), dim3(kBlock), 0, s, n, a, x, b, y);
+}
+
+__global__ void __launch_bounds__(kBlock) k_scale_inv_sqrt(int n, const double *__restrict__ nrm2, double *__restrict__ x)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const double sc = 1.0 / sqrt(*nrm2);
+    if (i < n) x[i] *= sc;
+}
+void launch_scale_by_inv_sqrt(int n, const double *nrm2, double *x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_inv_sqrt, dim3(nblocks(n)), dim3(kBlock), 0, s, n, nrm2, x);
+}
+
+// start vector entries u - 1/2 from SplitMix64 (seeded, independent of the disorder stream)
+__global__ void __launch_bounds__(kBlock) k_random(int n, uint64_t seed, double *x)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    uint64_t z = seed + uint64_t(s + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[s] = double(z >> 11) * 0x1.0p-53 - 0.5;
+}
+void launch_random_vector(int n, uint64_t seed, double *x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_random, dim3(nblocks(n)), dim3(kBlock), 0, s, n, seed, x);
+}
+
+// ---------------------------------------------------------------------------------
+// Simplified QMR (Freund & Nachtigal) with device-resident scalars.
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sqmr_init(int n, const T *__restrict__ b, T *__restrict__ r,
+                                                      T *__restrict__ x, T *__restrict__ d)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    r[i] = b[i];
+    x[i] = T(0);
+    d[i] = T(0);
+}
+template <typename T>
+void launch_sqmr_init(int n, const T *b, T *r, T *x, T *d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sqmr_init<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, b, r, x, d);
+}
+
+__global__ void k_sqmr_start(SqmrState *st, const double *rr, const double *rho, double tol)
+{
+    if (threadIdx.x != 0) return;
+    st->tau = sqrt(*rr);
+    st->tau0 = st->tau;
+    st->rho = *rho;
+    st->theta_old = 0.0;
+    st->j = 0;
+    st->tol = tol;
+    st->breakdown = 0;
+    st->done = (st->tau == 0.0 || st->rho == 0.0 || !isfinite(st->rho)) ? 1 : 0;
+    st->done_next = st->done;
+}
+void launch_sqmr_scalar_start(SqmrState *st, const double *rr, const double *rho, double tol, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sqmr_start, dim3(1), dim3(64), 0, s, st, rr, rho, tol);
+}
+
+__global__ void k_sqmr_alpha(SqmrState *st, const double *sigma)
+{
+    if (threadIdx.x != 0 || st->done) return;
+    st->sigma = *sigma;
+    if (st->sigma == 0.0 || !isfinite(st->sigma)) {
+        st->breakdown = 1;
+        st->done = 1;
+        st->done_next = 1;
+        return;
+    }
+    st->alpha = st->rho / st->sigma;
+}
+void launch_sqmr_scalar_alpha(SqmrState *st, const double *sigma, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sqmr_alpha, dim3(1), dim3(64), 0, s, st, sigma);
+}
+
+__global__ void k_sqmr_theta(SqmrState *st, const double *rr)
+{
+    if (threadIdx.x != 0 || st->done) return;
+    st->rr = *rr;
+    const double th = sqrt(st->rr) / st->tau;
+    const double c2 = 1.0 / (1.0 + th * th);
+    st->tau = st->tau * th * sqrt(c2);
+    st->c1 = c2 * st->theta_old * st->theta_old;
+    st->c2 = c2 * st->alpha;
+    st->theta_old = th;
+    st->theta = th;
+    st->j += 1;
+    if (st->tau * sqrt(double(st->j + 1)) <= st->tol * st->tau0 || !isfinite(st->tau)) st->done_next = 1;
+}
+void launch_sqmr_scalar_theta(SqmrState *st, const double *rr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sqmr_theta, dim3(1), dim3(64), 0, s, st, rr);
+}
+
+__global__ void k_sqmr_beta(SqmrState *st, const double *rho)
+{
+    if (threadIdx.x != 0) return;
+    if (!st->done && !st->done_next) {
+        const double rn = *rho;
+        if (rn == 0.0 || !isfinite(rn)) {
+            st->breakdown = 1;
+            st->done_next = 1;
+        } else {
+            st->beta = rn / st->rho;
+            st->rho = rn;
+        }
+    }
+    st->done = st->done_next;
+}
+void launch_sqmr_scalar_beta(SqmrState *st, const double *rho, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sqmr_beta, dim3(1), dim3(64), 0, s, st, rho);
+}
+
+// r -= alpha t, with the partial sums of |r|^2
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sqmr_update_r(int n, const SqmrState *st, const T *__restrict__ t,
+                                                          T *__restrict__ r, double *__restrict__ partial)
+{
+    if (st->done) return;
+    __shared__ double sh[kBlock / 64];
+    const T a = T(st->alpha);
+    double acc = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+        const T v = r[i] - a * t[i];
+        r[i] = v;
+        acc += double(v) * double(v);
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+template <typename T>
+void launch_sqmr_update_r(int n, SqmrState *st, const T *t, T *r, double *partial, double *rr, hipStream_t s)
+{
+    const int nb = red_blocks(n);
+    hipLaunchKernelGGL(k_sqmr_update_r<T>, dim3(nb), dim3(kBlock), 0, s, n, st, t, r, partial);
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, s, nb, kRedBlocks, partial, rr, &st->done);
+}
+
+// d = c1 d + c2 q ; x += d
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sqmr_update_xd(int n, const SqmrState *st, const T *__restrict__ q,
+                                                           T *__restrict__ d, T *__restrict__ x)
+{
+    if (st->done) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const T dv = T(st->c1) * d[i] + T(st->c2) * q[i];
+    d[i] = dv;
+    x[i] += dv;
+}
+template <typename T>
+void launch_sqmr_update_xd(int n, SqmrState *st, const T *q, T *d, T *x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sqmr_update_xd<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, st, q, d, x);
+}
+
+// q = u + beta q (runs after the beta kernel, so it checks the committed flag)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sqmr_update_q(int n, const SqmrState *st, const T *__restrict__ u,
+                                                          T *__restrict__ q)
+{
+    if (st->done) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    q[i] = u[i] + T(st->beta) * q[i];
+}
+template <typename T>
+void launch_sqmr_update_q(int n, SqmrState *st, const T *u, T *q, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sqmr_update_q<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, st, u, q);
+}
+
+__global__ void k_small_matvec(int p, const double *__restrict__ M, const double *__restrict__ c,
+                               double *__restrict__ out, const int *skip)
+{
+    if (skip && *skip) return;
+    const int i = threadIdx.x;
+    if (i >= p) return;
+    double a = 0.0;
+    for (int k = 0; k < p; ++k) a += M[i + k * p] * c[k];
+    out[i] = a;
+}
+void launch_small_matvec(int p, const double *M, const double *c, double *out, const int *skip, hipStream_t s)
+{
+    if (p <= 0) return;
+    hipLaunchKernelGGL(k_small_matvec, dim3(1), dim3(128), 0, s, p, M, c, out, skip);
+}
+
+// ---- explicit instantiations ------------------------------------------------------
+#define JD_INST(T)                                                                                        \
+    template void launch_stencil<T>(int, const T *, double, const T *, T *, hipStream_t, const int *);    \
+    template void launch_gather<T>(int, const int *, const T *, T *, hipStream_t, const int *);            \
+    template void launch_scatter<T>(int, const int *, const T *, T *, hipStream_t, const int *);           \
+    template void launch_down<T>(const DevLevel<T> &, T *, hipStream_t, const int *);                      \
+    template void launch_up<T>(const DevLevel<T> &, const T *, T *, hipStream_t, const int *);             \
+    template void launch_coarse<T>(int, int, const T *, const T *, T *, hipStream_t, const int *);         \
+    template void launch_multidot<T>(int, int, const T *, int64_t, const T *, double *, double *,          \
+                                     hipStream_t, const int *);                                            \
+    template void launch_dot<T>(int, const T *, const T *, double *, double *, hipStream_t, const int *);  \
+    template void launch_sub_qc<T>(int, int, const T *, int64_t, const double *, T *, hipStream_t,        \
+                                   const int *, double);                                                   \
+    template void launch_sqmr_init<T>(int, const T *, T *, T *, T *, hipStream_t);                        \
+    template void launch_sqmr_update_r<T>(int, SqmrState *, const T *, T *, double *, double *,           \
+                                          hipStream_t);                                                    \
+    template void launch_sqmr_update_xd<T>(int, SqmrState *, const T *, T *, T *, hipStream_t);           \
+    template void launch_sqmr_update_q<T>(int, SqmrState *, const T *, T *, hipStream_t);
+JD_INST(float)
+JD_INST(double)
+template void launch_convert<double, float>(int, const double *, float *, double, hipStream_t);
+template void launch_convert<float, double>(int, const float *, double *, double, hipStream_t);
+template void launch_convert<double, double>(int, const double *, double *, double, hipStream_t);
+template void launch_convert<float, float>(int, const float *, float *, double, hipStream_t);
+
+}  // namespace jdmi

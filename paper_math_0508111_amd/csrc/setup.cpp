@@ -1,0 +1,748 @@
+// Host setup of the multilevel incomplete LDL^T (sections 6 and 7).
+//
+// GPU-first reading of the paper's level structure: the symmetric ordering Pi of
+// each level (section 7.1) puts an independent set of the compressed 1x1/2x2 block
+// graph first.  The leading block of that level is then exactly the block diagonal
+// D11 of 1x1 and 2x2 pivots and L11 = I, so the factor of a level is the coupling
+// block L21 = F D11^{-1} alone, and applying a level costs two fully parallel sparse
+// passes instead of a level-scheduled triangular solve.  Everything else follows the
+// paper's order: maximum weight matching, cycle split into 1x1/2x2 blocks, symmetric
+// scaling, inverse-based acceptance of pivots with bound kappa (postponed pivots go
+// to the next level), dropping with epsilon/kappa and the aggressive tau rule,
+// explicit Schur complement of the postponed part, recursion, exact last level.
+#include "setup.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <queue>
+#include <utility>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace jdmi {
+
+namespace {
+constexpr double kInf = std::numeric_limits<double>::infinity();
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+inline double get(const Csr &A, int i, int j)
+{
+    auto b = A.col.begin() + A.ptr[i], e = A.col.begin() + A.ptr[i + 1];
+    auto it = std::lower_bound(b, e, j);
+    return (it != e && *it == j) ? A.val[it - A.col.begin()] : 0.0;
+}
+}  // namespace
+
+Csr anderson_shifted(int L, const double *eps, double sigma)
+{
+    const int n = L * L * L;
+    Csr A;
+    A.n = n;
+    A.ptr.assign(n + 1, 0);
+    A.col.reserve(size_t(n) * 7);
+    A.val.reserve(size_t(n) * 7);
+    for (int s = 0; s < n; ++s) {
+        const int i = s % L, j = (s / L) % L, k = s / (L * L);
+        std::pair<int, double> e[7];
+        int m = 0;
+        auto add = [&](int c, double v) {
+            for (int t = 0; t < m; ++t)
+                if (e[t].first == c) { e[t].second += v; return; }
+            e[m++] = {c, v};
+        };
+        add(s, eps[s] - sigma);
+        add((i + 1) % L + L * (j + L * k), -1.0);
+        add((i + L - 1) % L + L * (j + L * k), -1.0);
+        add(i + L * ((j + 1) % L + L * k), -1.0);
+        add(i + L * ((j + L - 1) % L + L * k), -1.0);
+        add(i + L * (j + L * ((k + 1) % L)), -1.0);
+        add(i + L * (j + L * ((k + L - 1) % L)), -1.0);
+        std::sort(e, e + m);
+        for (int t = 0; t < m; ++t) { A.col.push_back(e[t].first); A.val.push_back(e[t].second); }
+        A.ptr[s + 1] = int64_t(A.col.size());
+    }
+    return A;
+}
+
+// ---------------------------------------------------------------------------------
+// Maximum-product matching by shortest augmenting paths (Dijkstra on reduced costs).
+// ---------------------------------------------------------------------------------
+MatchResult max_product_matching(const Csr &A)
+{
+    const int n = A.n;
+    std::vector<double> lmax(n, -kInf);
+    std::vector<double> cost(A.val.size());
+    for (int i = 0; i < n; ++i) {
+        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p)
+            if (A.val[p] != 0.0) lmax[i] = std::max(lmax[i], std::log(std::fabs(A.val[p])));
+        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p)
+            cost[p] = (A.val[p] != 0.0) ? lmax[i] - std::log(std::fabs(A.val[p])) : kInf;
+    }
+    std::vector<double> u(n, 0.0), v(n, 0.0);  // c_ij >= 0 and min_j c_ij = 0: feasible
+    std::vector<int> rmatch(n, -1), cmatch(n, -1);
+    // greedy start on tight edges
+    for (int i = 0; i < n; ++i)
+        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+            const int j = A.col[p];
+            if (cost[p] == 0.0 && cmatch[j] < 0) { rmatch[i] = j; cmatch[j] = i; break; }
+        }
+    std::vector<double> d(n, kInf);
+    std::vector<int> pred(n, -1);
+    std::vector<char> scanned(n, 0);
+    std::vector<int> touched, scanned_list;
+    using HE = std::pair<double, int>;
+    int unmatched = 0;
+    for (int i0 = 0; i0 < n; ++i0) {
+        if (rmatch[i0] >= 0) continue;
+        std::priority_queue<HE, std::vector<HE>, std::greater<HE>> heap;
+        touched.clear();
+        scanned_list.clear();
+        auto relax_row = [&](int i, double base) {
+            for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+                if (cost[p] == kInf) continue;
+                const int j = A.col[p];
+                if (scanned[j]) continue;
+                const double nd = base + cost[p] - u[i] - v[j];
+                if (nd < d[j]) {
+                    if (d[j] == kInf) touched.push_back(j);
+                    d[j] = nd;
+                    pred[j] = i;
+                    heap.push({nd, j});
+                }
+            }
+        };
+        relax_row(i0, 0.0);
+        int sink = -1;
+        double delta = 0.0;
+        while (!heap.empty()) {
+            auto [dj, j] = heap.top();
+            heap.pop();
+            if (scanned[j] || dj > d[j]) continue;
+            scanned[j] = 1;
+            if (cmatch[j] < 0) { sink = j; delta = dj; break; }
+            scanned_list.push_back(j);
+            relax_row(cmatch[j], dj);
+        }
+        if (sink >= 0) {
+            // dual update keeps c_ij - u_i - v_j >= 0, = 0 on the matching
+            u[i0] += delta;
+            for (int j : scanned_list) {
+                const double t = delta - d[j];
+                u[cmatch[j]] += t;
+                v[j] -= t;
+            }
+            // augment along the predecessor chain
+            int j = sink;
+            while (true) {
+                const int i = pred[j];
+                const int nxt = rmatch[i];
+                rmatch[i] = j;
+                cmatch[j] = i;
+                if (i == i0) break;
+                j = nxt;
+            }
+        } else {
+            ++unmatched;
+        }
+        for (int j : touched) { d[j] = kInf; pred[j] = -1; scanned[j] = 0; }
+        if (sink >= 0) scanned[sink] = 0;
+        for (int j : scanned_list) scanned[j] = 0;
+    }
+    MatchResult r;
+    r.match = rmatch;
+    r.unmatched = unmatched;
+    r.logd.resize(n);
+    for (int i = 0; i < n; ++i) {
+        if (unmatched == 0)
+            r.logd[i] = 0.5 * (u[i] - lmax[i] + v[i]);
+        else
+            r.logd[i] = -0.5 * lmax[i];  // no perfect matching: row-maximum equilibration
+        if (!std::isfinite(r.logd[i])) r.logd[i] = 0.0;
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------------------------
+// Cycle split (section 6.2).  Tie rules (the paper's "structural metric" is not
+// spelled out): minimise the summed size of the union of the two rows' patterns
+// over the pairs, then maximise the product of the pairs' scaled couplings, then
+// take the first candidate; in odd cycles the 1x1 element must have a nonzero
+// diagonal when possible.
+// ---------------------------------------------------------------------------------
+std::vector<std::pair<int, int>> split_cycles(const Csr &A, const std::vector<int> &match,
+                                              const std::vector<double> &logd)
+{
+    const int n = A.n;
+    std::vector<std::pair<int, int>> blocks;
+    std::vector<char> seen(n, 0);
+    std::vector<int> mark(n, -1);
+    int stamp = 0;
+    auto union_size = [&](int a, int b) {
+        ++stamp;
+        int c = 0;
+        for (int64_t p = A.ptr[a]; p < A.ptr[a + 1]; ++p) { mark[A.col[p]] = stamp; ++c; }
+        for (int64_t p = A.ptr[b]; p < A.ptr[b + 1]; ++p)
+            if (mark[A.col[p]] != stamp) { mark[A.col[p]] = stamp; ++c; }
+        return c;
+    };
+    auto coupling = [&](int a, int b) {
+        return std::fabs(get(A, a, b)) * std::exp(logd[a] + logd[b]);
+    };
+    std::vector<int> cyc;
+    for (int s = 0; s < n; ++s) {
+        if (seen[s]) continue;
+        cyc.clear();
+        int t = s;
+        while (t >= 0 && !seen[t]) { seen[t] = 1; cyc.push_back(t); t = match[t]; }
+        const int m = int(cyc.size());
+        if (m == 1) { blocks.push_back({cyc[0], -1}); continue; }
+        if (t != s) {
+            // an open chain (only when the matching is not perfect): pair consecutively
+            int q = 0;
+            for (; q + 1 < m; q += 2) blocks.push_back({cyc[q], cyc[q + 1]});
+            if (q < m) blocks.push_back({cyc[q], -1});
+            continue;
+        }
+        // pair metrics for consecutive positions q -> q+1 (mod m)
+        std::vector<double> pu(m), pc(m);
+        for (int q = 0; q < m; ++q) {
+            const int a = cyc[q], b = cyc[(q + 1) % m];
+            pu[q] = union_size(a, b);
+            pc[q] = std::log(std::max(coupling(a, b), 1e-300));
+        }
+        if (m % 2 == 0) {
+            double u0 = 0, u1 = 0, c0 = 0, c1 = 0;
+            for (int q = 0; q < m; q += 2) { u0 += pu[q]; c0 += pc[q]; }
+            for (int q = 1; q < m; q += 2) { u1 += pu[q]; c1 += pc[q]; }
+            const int st = (u1 < u0 || (u1 == u0 && c1 > c0)) ? 1 : 0;
+            for (int q = st; q < m + st; q += 2) blocks.push_back({cyc[q % m], cyc[(q + 1) % m]});
+        } else {
+            int best = -1;
+            double bu = kInf, bc = -kInf;
+            bool bnz = false;
+            const int lim = std::min(m, 257);  // very long cycles: first choices only
+            for (int sgl = 0; sgl < lim; ++sgl) {
+                const bool nz = get(A, cyc[sgl], cyc[sgl]) != 0.0;
+                double us = 0, cs = 0;
+                for (int q = sgl + 1; q < sgl + m; q += 2) { us += pu[q % m]; cs += pc[q % m]; }
+                bool better;
+                if (best < 0) better = true;
+                else if (nz != bnz) better = nz;
+                else if (us != bu) better = us < bu;
+                else better = cs > bc;
+                if (better) { best = sgl; bu = us; bc = cs; bnz = nz; }
+            }
+            blocks.push_back({cyc[best], -1});
+            for (int q = best + 1; q < best + m; q += 2) blocks.push_back({cyc[q % m], cyc[(q + 1) % m]});
+        }
+    }
+    return blocks;
+}
+
+// ---------------------------------------------------------------------------------
+// Dense inverse by LU with partial pivoting (last level).
+// ---------------------------------------------------------------------------------
+static bool dense_inverse(int n, std::vector<double> &a)
+{
+    std::vector<double> inv(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[size_t(i) * n + i] = 1.0;
+    double amax = 0;
+    for (double x : a) amax = std::max(amax, std::fabs(x));
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        double best = std::fabs(a[size_t(c) * n + c]);
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(a[size_t(r) * n + c]) > best) { best = std::fabs(a[size_t(r) * n + c]); piv = r; }
+        if (!(best > 1e-14 * std::max(amax, 1e-300))) return false;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) {
+                std::swap(a[size_t(c) * n + k], a[size_t(piv) * n + k]);
+                std::swap(inv[size_t(c) * n + k], inv[size_t(piv) * n + k]);
+            }
+        }
+        const double pinv = 1.0 / a[size_t(c) * n + c];
+        for (int k = 0; k < n; ++k) { a[size_t(c) * n + k] *= pinv; inv[size_t(c) * n + k] *= pinv; }
+        const double *arow = &a[size_t(c) * n];
+        const double *irow = &inv[size_t(c) * n];
+#pragma omp parallel for schedule(static)
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = a[size_t(r) * n + c];
+            if (f == 0.0) continue;
+            double *ar = &a[size_t(r) * n];
+            double *ir = &inv[size_t(r) * n];
+            for (int k = 0; k < n; ++k) { ar[k] -= f * arow[k]; ir[k] -= f * irow[k]; }
+        }
+    }
+    // symmetrise (the exact inverse of a symmetric matrix is symmetric)
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const double s = 0.5 * (inv[size_t(i) * n + j] + inv[size_t(j) * n + i]);
+            inv[size_t(i) * n + j] = inv[size_t(j) * n + i] = s;
+        }
+    a.swap(inv);
+    return true;
+}
+
+// ---------------------------------------------------------------------------------
+// One level.
+// ---------------------------------------------------------------------------------
+namespace {
+
+struct LevelLocal {
+    // in level-local numbering (0..n-1 of this level's matrix)
+    std::vector<int> B, C;           // pivots (block members adjacent), complement
+    std::vector<int> partner;        // level-local partner (self for 1x1), for B members
+    std::vector<double> bd, bo;      // scaled block inverse entries for B members
+    // G over C rows (local C index) -> B local index, scaled domain
+    std::vector<int64_t> g_ptr;
+    std::vector<int> g_col;
+    std::vector<double> g_val;
+    int n2x2 = 0, rejected = 0;
+};
+
+// scaled value
+struct Scaled {
+    const Csr &A;
+    const std::vector<double> &d;
+    double operator()(int64_t p, int i) const { return A.val[p] * d[i] * d[A.col[p]]; }
+};
+
+}  // namespace
+
+static std::string factor_level(const Csr &A, const SetupParams &prm, const std::vector<double> &d,
+                                const std::vector<std::pair<int, int>> &blocks, LevelLocal &lv, Csr &S_next)
+{
+    const int n = A.n;
+    const bool exact = prm.drop_tol < 0;
+    const double kappa = exact ? kInf : prm.kappa;
+    auto sv = [&](int64_t p, int i) { return A.val[p] * d[i] * d[A.col[p]]; };
+    auto sget = [&](int i, int j) { return get(A, i, j) * d[i] * d[j]; };
+
+    // candidate pivots with their inverse-bound measure (1-norm of the L columns)
+    struct Cand { int a, b; double q; int deg; double i00, i01, i11; };
+    std::vector<Cand> cands;
+    cands.reserve(blocks.size() + 16);
+    auto colsum1 = [&](int i) {
+        double s = 0;
+        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p)
+            if (A.col[p] != i) s += std::fabs(sv(p, i));
+        return s;
+    };
+    auto push1 = [&](int i) {
+        const double dii = sget(i, i);
+        if (!(std::fabs(dii) > 0.0)) return;
+        const double q = colsum1(i) / std::fabs(dii);
+        cands.push_back({i, -1, q, int(A.ptr[i + 1] - A.ptr[i]), 1.0 / dii, 0.0, 0.0});
+    };
+    for (auto [a, b] : blocks) {
+        if (b < 0) { push1(a); continue; }
+        const double saa = sget(a, a), sab = sget(a, b), sbb = sget(b, b);
+        const double det = saa * sbb - sab * sab;
+        const double scale = std::max({std::fabs(saa), std::fabs(sbb), std::fabs(sab)});
+        double d2 = kInf, cs_a = 0, cs_b = 0;
+        double i00 = 0, i01 = 0, i11 = 0;
+        if (std::fabs(det) > 1e-12 * scale * scale) {
+            i00 = sbb / det; i01 = -sab / det; i11 = saa / det;
+            // rows of (s_r,a  s_r,b) S2^{-1} over the union of both columns' rows
+            d2 = 0;
+            std::vector<std::pair<int, double>> ra, rb;
+            for (int64_t p = A.ptr[a]; p < A.ptr[a + 1]; ++p)
+                if (A.col[p] != a && A.col[p] != b) ra.push_back({A.col[p], sv(p, a)});
+            for (int64_t p = A.ptr[b]; p < A.ptr[b + 1]; ++p)
+                if (A.col[p] != a && A.col[p] != b) rb.push_back({A.col[p], sv(p, b)});
+            size_t x = 0, y = 0;
+            while (x < ra.size() || y < rb.size()) {
+                int r;
+                double va = 0, vb = 0;
+                if (y >= rb.size() || (x < ra.size() && ra[x].first < rb[y].first)) { r = ra[x].first; va = ra[x++].second; }
+                else if (x >= ra.size() || rb[y].first < ra[x].first) { r = rb[y].first; vb = rb[y++].second; }
+                else { r = ra[x].first; va = ra[x++].second; vb = rb[y++].second; }
+                (void)r;
+                const double za = va * i00 + vb * i01, zb = va * i01 + vb * i11;
+                d2 += std::max(std::fabs(za), std::fabs(zb));  // infinity norm of the row
+                cs_a += std::fabs(za);
+                cs_b += std::fabs(zb);
+            }
+        }
+        const double d1a = (saa != 0.0) ? colsum1(a) / std::fabs(saa) : kInf;
+        const double d1b = (sbb != 0.0) ? colsum1(b) / std::fabs(sbb) : kInf;
+        if (d2 < std::min(d1a, d1b)) {
+            int deg = int(A.ptr[a + 1] - A.ptr[a] + A.ptr[b + 1] - A.ptr[b]);
+            cands.push_back({a, b, std::max(cs_a, cs_b), deg, i00, i01, i11});
+        } else {
+            push1(a);
+            push1(b);
+        }
+    }
+    // greedy independent set of the compressed graph: fewest couplings first
+    std::vector<int> order(cands.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (cands[x].deg != cands[y].deg) return cands[x].deg < cands[y].deg;
+        return std::min(cands[x].a, cands[x].b < 0 ? cands[x].a : cands[x].b) <
+               std::min(cands[y].a, cands[y].b < 0 ? cands[y].a : cands[y].b);
+    });
+    enum : char { FREE = 0, INB = 1, INC = 2 };
+    std::vector<char> state(n, FREE);
+    std::vector<int> cand_of(n, -1);
+    int rejected = 0;
+    for (int ci : order) {
+        const Cand &c = cands[ci];
+        if (state[c.a] != FREE || (c.b >= 0 && state[c.b] != FREE)) continue;
+        if (!(1.0 + c.q <= kappa)) { ++rejected; continue; }  // postponed
+        state[c.a] = INB;
+        cand_of[c.a] = ci;
+        if (c.b >= 0) { state[c.b] = INB; cand_of[c.b] = ci; }
+        for (int v : {c.a, c.b}) {
+            if (v < 0) continue;
+            for (int64_t p = A.ptr[v]; p < A.ptr[v + 1]; ++p)
+                if (state[A.col[p]] == FREE) state[A.col[p]] = INC;
+        }
+    }
+    lv.B.clear();
+    lv.C.clear();
+    std::vector<int> loc(n, -1);
+    for (int i = 0; i < n; ++i) {
+        if (state[i] == INB) { loc[i] = int(lv.B.size()); lv.B.push_back(i); }
+        else { loc[i] = int(lv.C.size()); lv.C.push_back(i); }
+    }
+    const int nB = int(lv.B.size()), nC = int(lv.C.size());
+    lv.rejected = rejected;
+    lv.partner.assign(nB, 0);
+    lv.bd.assign(nB, 0.0);
+    lv.bo.assign(nB, 0.0);
+    lv.n2x2 = 0;
+    for (int t = 0; t < nB; ++t) {
+        const int i = lv.B[t];
+        const Cand &c = cands[cand_of[i]];
+        if (c.b < 0) { lv.partner[t] = t; lv.bd[t] = c.i00; lv.bo[t] = 0.0; }
+        else if (i == c.a) { lv.partner[t] = loc[c.b]; lv.bd[t] = c.i00; lv.bo[t] = c.i01; ++lv.n2x2; }
+        else { lv.partner[t] = loc[c.a]; lv.bd[t] = c.i11; lv.bo[t] = c.i01; }
+    }
+    // G = F B^{-1} over C rows, scaled domain, then dropping
+    std::vector<std::vector<std::pair<int, double>>> grow(nC);
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int r = 0; r < nC; ++r) {
+        const int i = lv.C[r];
+        auto &row = grow[r];
+        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+            const int j = A.col[p];
+            if (state[j] != INB) continue;
+            const double f = sv(p, i);
+            const int tj = loc[j], tp = lv.partner[tj];
+            auto add = [&](int c, double v) {
+                for (auto &e : row) if (e.first == c) { e.second += v; return; }
+                row.push_back({c, v});
+            };
+            add(tj, f * lv.bd[tj]);
+            if (tp != tj) add(tp, f * lv.bo[tj]);
+        }
+        std::sort(row.begin(), row.end());
+    }
+    if (!exact) {
+        const double thr = prm.drop_tol / prm.kappa;
+        std::vector<int> cnt(nB, 0);
+        for (auto &row : grow) {
+            size_t w = 0;
+            for (auto &e : row)
+                if (std::fabs(e.second) >= thr) row[w++] = e;
+            row.resize(w);
+            for (auto &e : row) ++cnt[e.first];
+        }
+        // aggressive dropping: |l_rj| <= tau / (nu_r * nnz(column j)); nu_r = 1 for
+        // rows of the complement since L^{-1} e_r = e_r there.
+        for (auto &row : grow) {
+            size_t w = 0;
+            for (auto &e : row)
+                if (std::fabs(e.second) > prm.agg_tau / std::max(cnt[e.first], 1)) row[w++] = e;
+            row.resize(w);
+        }
+    }
+    lv.g_ptr.assign(nC + 1, 0);
+    for (int r = 0; r < nC; ++r) lv.g_ptr[r + 1] = lv.g_ptr[r] + int64_t(grow[r].size());
+    lv.g_col.resize(lv.g_ptr[nC]);
+    lv.g_val.resize(lv.g_ptr[nC]);
+    for (int r = 0; r < nC; ++r) {
+        int64_t p = lv.g_ptr[r];
+        for (auto &e : grow[r]) { lv.g_col[p] = e.first; lv.g_val[p] = e.second; ++p; }
+    }
+    grow.clear();
+    grow.shrink_to_fit();
+    // H^T = B G^T by B rows: HT[t, r] = sum_{t' in block(t)} B[t, t'] G[r, t']
+    //   with B the scaled pivot block itself (not its inverse).
+    std::vector<int64_t> gt_ptr(nB + 1, 0);
+    for (int r = 0; r < nC; ++r)
+        for (int64_t p = lv.g_ptr[r]; p < lv.g_ptr[r + 1]; ++p) ++gt_ptr[lv.g_col[p] + 1];
+    for (int t = 0; t < nB; ++t) gt_ptr[t + 1] += gt_ptr[t];
+    std::vector<int> gt_col(gt_ptr[nB]);
+    std::vector<double> gt_val(gt_ptr[nB]);
+    {
+        std::vector<int64_t> fillp(gt_ptr.begin(), gt_ptr.end() - 1);
+        for (int r = 0; r < nC; ++r)
+            for (int64_t p = lv.g_ptr[r]; p < lv.g_ptr[r + 1]; ++p) {
+                const int t = lv.g_col[p];
+                gt_col[fillp[t]] = r;
+                gt_val[fillp[t]++] = lv.g_val[p];
+            }
+    }
+    // scaled pivot block entries
+    std::vector<double> Bd(nB), Bo(nB);
+    for (int t = 0; t < nB; ++t) {
+        const int i = lv.B[t];
+        Bd[t] = sget(i, i);
+        Bo[t] = (lv.partner[t] != t) ? sget(i, lv.B[lv.partner[t]]) : 0.0;
+    }
+    // Schur complement S = C - G B G^T (rows of C), row by row
+    const double stol = exact ? -1.0 : prm.schur_tol;
+    S_next.n = nC;
+    std::vector<std::vector<std::pair<int, double>>> srow(nC);
+#pragma omp parallel
+    {
+        std::vector<double> acc(nC, 0.0);
+        std::vector<int> mark(nC, -1), list;
+#pragma omp for schedule(dynamic, 512)
+        for (int r = 0; r < nC; ++r) {
+            list.clear();
+            const int i = lv.C[r];
+            auto put = [&](int c, double v) {
+                if (mark[c] != r) { mark[c] = r; acc[c] = 0.0; list.push_back(c); }
+                acc[c] += v;
+            };
+            put(r, 0.0);  // keep the diagonal
+            for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+                const int j = A.col[p];
+                if (state[j] == INB) continue;
+                put(loc[j], sv(p, i));
+            }
+            for (int64_t p = lv.g_ptr[r]; p < lv.g_ptr[r + 1]; ++p) {
+                const int t = lv.g_col[p];
+                const double g = lv.g_val[p];
+                const int tp = lv.partner[t];
+                // (G B)[r, t'] for t' in block -> times G[c, t'] ... use HT rows
+                // contribution: g * sum_{c} (B G^T)[t, c]
+                for (int64_t q = gt_ptr[t]; q < gt_ptr[t + 1]; ++q) put(gt_col[q], -g * Bd[t] * gt_val[q]);
+                if (tp != t)
+                    for (int64_t q = gt_ptr[tp]; q < gt_ptr[tp + 1]; ++q) put(gt_col[q], -g * Bo[t] * gt_val[q]);
+            }
+            std::sort(list.begin(), list.end());
+            auto &out = srow[r];
+            for (int c : list) {
+                const double v = acc[c];
+                if (c == r || std::fabs(v) >= stol) out.push_back({c, v});
+            }
+        }
+    }
+    S_next.ptr.assign(nC + 1, 0);
+    for (int r = 0; r < nC; ++r) S_next.ptr[r + 1] = S_next.ptr[r] + int64_t(srow[r].size());
+    S_next.col.resize(S_next.ptr[nC]);
+    S_next.val.resize(S_next.ptr[nC]);
+    for (int r = 0; r < nC; ++r) {
+        int64_t p = S_next.ptr[r];
+        for (auto &e : srow[r]) { S_next.col[p] = e.first; S_next.val[p] = e.second; ++p; }
+    }
+    // the computed Schur complement is symmetric up to rounding; enforce it by
+    // averaging mirrored entries and keeping the union pattern
+    {
+        Csr T;
+        T.n = nC;
+        T.ptr.assign(nC + 1, 0);
+        for (int r = 0; r < nC; ++r)
+            for (int64_t p = S_next.ptr[r]; p < S_next.ptr[r + 1]; ++p) ++T.ptr[S_next.col[p] + 1];
+        for (int r = 0; r < nC; ++r) T.ptr[r + 1] += T.ptr[r];
+        T.col.resize(T.ptr[nC]);
+        T.val.resize(T.ptr[nC]);
+        std::vector<int64_t> fp(T.ptr.begin(), T.ptr.end() - 1);
+        for (int r = 0; r < nC; ++r)
+            for (int64_t p = S_next.ptr[r]; p < S_next.ptr[r + 1]; ++p) {
+                const int c = S_next.col[p];
+                T.col[fp[c]] = r;
+                T.val[fp[c]++] = S_next.val[p];
+            }
+        Csr U;
+        U.n = nC;
+        U.ptr.assign(nC + 1, 0);
+        std::vector<std::vector<std::pair<int, double>>> urow(nC);
+#pragma omp parallel for schedule(dynamic, 1024)
+        for (int r = 0; r < nC; ++r) {
+            int64_t a = S_next.ptr[r], ae = S_next.ptr[r + 1], b = T.ptr[r], be = T.ptr[r + 1];
+            auto &o = urow[r];
+            while (a < ae || b < be) {
+                if (b >= be || (a < ae && S_next.col[a] < T.col[b])) { o.push_back({S_next.col[a], 0.5 * S_next.val[a]}); ++a; }
+                else if (a >= ae || T.col[b] < S_next.col[a]) { o.push_back({T.col[b], 0.5 * T.val[b]}); ++b; }
+                else { o.push_back({S_next.col[a], 0.5 * (S_next.val[a] + T.val[b])}); ++a; ++b; }
+            }
+        }
+        for (int r = 0; r < nC; ++r) U.ptr[r + 1] = U.ptr[r] + int64_t(urow[r].size());
+        U.col.resize(U.ptr[nC]);
+        U.val.resize(U.ptr[nC]);
+        for (int r = 0; r < nC; ++r) {
+            int64_t p = U.ptr[r];
+            for (auto &e : urow[r]) { U.col[p] = e.first; U.val[p] = e.second; ++p; }
+        }
+        S_next = std::move(U);
+    }
+    return "";
+}
+
+std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &out)
+{
+    const double t0 = now_s();
+    const int n = A0.n;
+    out = Multilevel();
+    out.n = n;
+    {
+        long long low = 0;
+        for (int i = 0; i < n; ++i)
+            for (int64_t p = A0.ptr[i]; p < A0.ptr[i + 1]; ++p)
+                if (A0.col[p] <= i) ++low;
+        out.nnz_lower_A = low;
+    }
+    struct Pending {
+        LevelLocal lv;
+        std::vector<double> cum;   // cumulative scaling of this level's unknowns (incl. own d)
+        int off;
+    };
+    std::vector<Pending> pend;
+    Csr S = A0;
+    std::vector<int> orig(n);
+    std::iota(orig.begin(), orig.end(), 0);
+    std::vector<double> cum_prev(n, 1.0);
+    // level-local -> original sites of B members, per level, to build the permutation
+    std::vector<std::vector<int>> level_orig;
+    int off = 0;
+    while (S.n > prm.coarse_max && int(pend.size()) < prm.max_levels) {
+        MatchResult mr = max_product_matching(S);
+        auto blocks = split_cycles(S, mr.match, mr.logd);
+        std::vector<double> d(S.n);
+        for (int i = 0; i < S.n; ++i) d[i] = std::exp(mr.logd[i]);
+        Pending pl;
+        Csr Snext;
+        std::string err = factor_level(S, prm, d, blocks, pl.lv, Snext);
+        if (!err.empty()) return err;
+        if (pl.lv.B.empty()) break;  // no acceptable pivot: the rest is the last level
+        pl.cum.resize(S.n);
+        for (int i = 0; i < S.n; ++i) pl.cum[i] = cum_prev[i] * d[i];
+        pl.off = off;
+        std::vector<int> bo(pl.lv.B.size()), co(pl.lv.C.size());
+        for (size_t t = 0; t < pl.lv.B.size(); ++t) bo[t] = orig[pl.lv.B[t]];
+        for (size_t t = 0; t < pl.lv.C.size(); ++t) co[t] = orig[pl.lv.C[t]];
+        std::vector<double> cum_next(pl.lv.C.size());
+        for (size_t t = 0; t < pl.lv.C.size(); ++t) cum_next[t] = pl.cum[pl.lv.C[t]];
+        level_orig.push_back(bo);
+        off += int(pl.lv.B.size());
+        orig.swap(co);
+        cum_prev.swap(cum_next);
+        pend.push_back(std::move(pl));
+        S = std::move(Snext);
+    }
+    if (S.n > 8192) return "last Schur complement too large for the exact last level (" + std::to_string(S.n) + ")";
+    // permutation: level pivots in order, then the last level
+    out.perm.resize(n);
+    {
+        int p = 0;
+        for (auto &lo : level_orig) for (int s : lo) out.perm[p++] = s;
+        for (int s : orig) out.perm[p++] = s;
+    }
+    out.coarse_off = off;
+    out.coarse_n = S.n;
+    // global position of each level-local unknown, computed from the last level back
+    // gpos for the current (last) level: coarse positions
+    std::vector<int> gpos(S.n);
+    for (int i = 0; i < S.n; ++i) gpos[i] = off + i;
+    // last level: dense inverse with the cumulative scaling folded in
+    {
+        const int nc = S.n;
+        std::vector<double> dense(size_t(nc) * nc, 0.0);
+        for (int i = 0; i < nc; ++i)
+            for (int64_t p = S.ptr[i]; p < S.ptr[i + 1]; ++p) dense[size_t(i) * nc + S.col[p]] = S.val[p];
+        if (nc > 0 && !dense_inverse(nc, dense)) return "singular last level";
+        for (int i = 0; i < nc; ++i)
+            for (int j = 0; j < nc; ++j) dense[size_t(i) * nc + j] *= cum_prev[i] * cum_prev[j];
+        out.coarse_inv.swap(dense);
+    }
+    out.levels.resize(pend.size());
+    long long nnz_fact = 0;
+    for (int l = int(pend.size()) - 1; l >= 0; --l) {
+        Pending &pl = pend[l];
+        LevelLocal &lv = pl.lv;
+        Level &G = out.levels[l];
+        const int nB = int(lv.B.size()), nC = int(lv.C.size());
+        G.off = pl.off;
+        G.nB = nB;
+        G.n_after = nC;
+        G.n2x2 = lv.n2x2;
+        G.cand_rejected = lv.rejected;
+        // gpos (next level) -> this level
+        std::vector<int> gl(lv.B.size() + lv.C.size());
+        for (int t = 0; t < nB; ++t) gl[lv.B[t]] = pl.off + t;
+        for (int r = 0; r < nC; ++r) gl[lv.C[r]] = gpos[r];
+        const std::vector<double> &cum = pl.cum;
+        // G rows ordered by global position of the C unknown: positions off+nB .. n-1
+        std::vector<int> row_at(nC);  // global position - (off+nB) -> local C row
+        for (int r = 0; r < nC; ++r) row_at[gpos[r] - (pl.off + nB)] = r;
+        G.g_ptr.assign(nC + 1, 0);
+        for (int q = 0; q < nC; ++q) {
+            const int r = row_at[q];
+            G.g_ptr[q + 1] = G.g_ptr[q] + (lv.g_ptr[r + 1] - lv.g_ptr[r]);
+        }
+        G.g_col.resize(G.g_ptr[nC]);
+        G.g_val.resize(G.g_ptr[nC]);
+        for (int q = 0; q < nC; ++q) {
+            const int r = row_at[q];
+            const int ci = lv.C[r];
+            int64_t o = G.g_ptr[q];
+            for (int64_t p = lv.g_ptr[r]; p < lv.g_ptr[r + 1]; ++p, ++o) {
+                const int t = lv.g_col[p];
+                G.g_col[o] = pl.off + t;
+                G.g_val[o] = lv.g_val[p] * cum[lv.B[t]] / cum[ci];
+            }
+        }
+        // G^T rows = pivots in order
+        G.gt_ptr.assign(nB + 1, 0);
+        for (int r = 0; r < nC; ++r)
+            for (int64_t p = lv.g_ptr[r]; p < lv.g_ptr[r + 1]; ++p) ++G.gt_ptr[lv.g_col[p] + 1];
+        for (int t = 0; t < nB; ++t) G.gt_ptr[t + 1] += G.gt_ptr[t];
+        G.gt_col.resize(G.gt_ptr[nB]);
+        G.gt_val.resize(G.gt_ptr[nB]);
+        {
+            std::vector<int64_t> fp(G.gt_ptr.begin(), G.gt_ptr.end() - 1);
+            for (int q = 0; q < nC; ++q) {
+                const int r = row_at[q];
+                const int ci = lv.C[r];
+                for (int64_t p = lv.g_ptr[r]; p < lv.g_ptr[r + 1]; ++p) {
+                    const int t = lv.g_col[p];
+                    G.gt_col[fp[t]] = gpos[r];
+                    G.gt_val[fp[t]++] = lv.g_val[p] * cum[lv.B[t]] / cum[ci];
+                }
+            }
+        }
+        G.bd.resize(nB);
+        G.bo.resize(nB);
+        G.bp.resize(nB);
+        for (int t = 0; t < nB; ++t) {
+            const double ci = cum[lv.B[t]], cp = cum[lv.B[lv.partner[t]]];
+            G.bd[t] = lv.bd[t] * ci * ci;
+            G.bo[t] = lv.bo[t] * ci * cp;
+            G.bp[t] = pl.off + lv.partner[t];
+        }
+        nnz_fact += G.g_ptr[nC] + nB + lv.n2x2;
+        gpos.swap(gl);
+    }
+    nnz_fact += (long long)out.coarse_n * (out.coarse_n + 1) / 2;
+    out.fill = double(nnz_fact) / double(std::max<long long>(out.nnz_lower_A, 1));
+    out.seconds = now_s() - t0;
+    return "";
+}
+
+}  // namespace jdmi

@@ -1,0 +1,85 @@
+// Host-side construction of the matching-based multilevel incomplete LDL^T
+// (sections 6 and 7 of Schenk, Bollhoefer & Roemer).  Everything here runs on
+// the CPU once per problem; the factors it returns are uploaded and applied by
+// the device kernels.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace jdmi {
+
+// Symmetric sparse matrix, CSR with sorted column indices and an explicit
+// (possibly zero) diagonal entry in every row.
+struct Csr {
+    int n = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int> col;
+    std::vector<double> val;
+};
+
+struct MatchResult {
+    std::vector<int> match;     // row i -> column match[i] (-1: unmatched)
+    std::vector<double> logd;   // symmetric scaling, log d_i
+    int unmatched = 0;
+};
+
+// Maximum-product transversal (section 6.1, eq. (1)/(2)): minimise
+// sum_i c_{i, match(i)} with c_ij = log max_k |a_ik| - log |a_ij| by shortest
+// augmenting paths; the optimal duals give the symmetric scaling
+// log d_i = (u_i - log max_k|a_ik| + v_i) / 2 (|d_i a_ij d_j| <= 1).
+MatchResult max_product_matching(const Csr &A);
+
+// Split the cycles of the matching permutation into 1x1 and 2x2 blocks
+// (section 6.2, figures 3 and 4).  Returns blocks as (a, b) with b = -1 for 1x1.
+// Values are those of the scaled matrix (scale = exp(logd)).
+std::vector<std::pair<int, int>> split_cycles(const Csr &A, const std::vector<int> &match,
+                                              const std::vector<double> &logd);
+
+struct SetupParams {
+    double drop_tol = 1e-2;   // epsilon (< 0: exact factorisation, nothing dropped)
+    double kappa = 5.0;
+    double agg_tau = 0.1;
+    double schur_tol = 1e-2;
+    int coarse_max = 1536;
+    int max_levels = 64;
+};
+
+// One level of the multilevel factorisation in global (permuted) positions, with
+// every scaling folded into the stored values.
+//   rows [off, off+nB) are this level's pivots, rows [off+nB, n) its complement.
+//   down pass:  w[r] -= sum G[r, c] w[c]        r >= off+nB, c in [off, off+nB)
+//   up pass:    x[j]  = bd[j] w[j] + bo[j] w[bp[j]] - sum GT[j, r] x[r]
+struct Level {
+    int off = 0, nB = 0, n_after = 0;          // n_after = unknowns of the next level
+    int n2x2 = 0;
+    std::vector<int64_t> g_ptr;                 // n_after + 1 (rows off+nB .. n-1)
+    std::vector<int> g_col;
+    std::vector<double> g_val;
+    std::vector<int64_t> gt_ptr;                // nB + 1 (rows off .. off+nB-1)
+    std::vector<int> gt_col;
+    std::vector<double> gt_val;
+    std::vector<double> bd, bo;                 // nB
+    std::vector<int> bp;                        // nB, global partner position
+    int cand_rejected = 0;                      // candidates refused by the kappa test
+};
+
+struct Multilevel {
+    int n = 0;
+    std::vector<int> perm;        // perm[position] = original site index
+    std::vector<Level> levels;
+    int coarse_off = 0, coarse_n = 0;
+    std::vector<double> coarse_inv;  // coarse_n x coarse_n row-major, scalings folded in
+    long long nnz_lower_A = 0;
+    double fill = 0.0;
+    double seconds = 0.0;
+};
+
+// Build the multilevel factorisation of the symmetric matrix A.
+// Returns an empty string on success, else a message.
+std::string build_multilevel(const Csr &A, const SetupParams &prm, Multilevel &out);
+
+// A - sigma I for the periodic Anderson lattice (hopping -1), CSR.
+Csr anderson_shifted(int L, const double *eps, double sigma);
+
+}  // namespace jdmi

@@ -1,0 +1,187 @@
+"""GPU parity of the hot path against the FP64 oracle, through the C ABI.
+
+Every comparison uses seeded inputs; expected values come from ``oracle`` (live, or
+stored in tests/golden by tests/golden/make_golden.py).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_math_0508111_amd as jd  # noqa: E402
+from oracle import eig, generator, lattice, ldlt  # noqa: E402
+from tests import seeded_inputs  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+U32 = np.finfo(np.float32).eps / 2
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def stream():
+    return torch.cuda.current_stream()
+
+
+# --- K1: disorder ---------------------------------------------------------------------
+
+@pytest.mark.parametrize("L,W,seed", [(10, 16.5, 0), (7, 12.0, 3), (2, 16.5, 5), (33, 21.0, 11), (100, 16.5, 0)])
+def test_gen_diag_bit_exact(L, W, seed):
+    n = L ** 3
+    e64 = torch.empty(n, dtype=torch.float64, device="cuda")
+    e32 = torch.empty(n, dtype=torch.float32, device="cuda")
+    jd.gen_diag(L, W, seed, e64, e32, stream=stream())
+    torch.cuda.synchronize()
+    ref = generator.disorder(L, W, seed)
+    assert np.array_equal(e64.cpu().numpy(), ref)
+    assert np.array_equal(e32.cpu().numpy(), ref.astype(np.float32))
+
+
+# --- K2: stencil SpMV ---------------------------------------------------------------------
+
+@pytest.mark.parametrize("L,shift", [(2, 0.0), (3, 0.7), (10, 0.0), (33, -0.25), (100, 0.0), (150, 0.1)])
+def test_stencil_parity(L, shift):
+    n = L ** 3
+    eps = generator.disorder(L, 16.5, 1)
+    x = seeded_inputs.vector(n, 7)
+    ref = lattice.matvec(L, eps, x, shift=shift)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    jd.stencil_spmv(L, dev(eps), shift, dev(x), y, "fp64", stream=stream())
+    torch.cuda.synchronize()
+    scale = np.abs(eps - shift) * np.abs(x) + 6 * np.abs(x).max()
+    assert np.all(np.abs(y.cpu().numpy() - ref) <= 8 * np.finfo(float).eps * scale)
+    # binary32: error bound of 8 roundings of the inputs and the arithmetic
+    y32 = torch.empty(n, dtype=torch.float32, device="cuda")
+    jd.stencil_spmv(L, dev(eps, torch.float32), shift, dev(x, torch.float32), y32, "mixed", stream=stream())
+    torch.cuda.synchronize()
+    assert np.all(np.abs(y32.cpu().numpy().astype(np.float64) - ref) <= 16 * U32 * scale)
+
+
+# --- multilevel preconditioner -------------------------------------------------------------
+
+@pytest.mark.parametrize("L,cmax,sigma", [(4, 8, 0.0), (6, 16, 0.0), (8, 40, 0.37), (10, 60, -0.2)])
+def test_precond_exact_without_dropping(L, cmax, sigma):
+    # nothing dropped and every pivot accepted: the multilevel factorisation is exact,
+    # so K^{-1} (A - sigma I) x = x
+    W, seed = 16.5, 2
+    P = jd.Precond(L, W, seed, sigma, drop_tol=-1.0, coarse_max=cmax)
+    lv = P.levels()
+    assert lv["levels"] >= 1
+    eps = generator.disorder(L, W, seed)
+    x = seeded_inputs.vector(L ** 3, 3)
+    b = lattice.matvec(L, eps, x, shift=sigma)
+    y = torch.empty(L ** 3, dtype=torch.float64, device="cuda")
+    P.apply(dev(b), y, "fp64", stream=stream())
+    torch.cuda.synchronize()
+    assert np.linalg.norm(y.cpu().numpy() - x) <= 1e-9 * np.linalg.norm(x)
+    P.close()
+
+
+@pytest.mark.parametrize("L", [16, 30])
+def test_precond_symmetric_and_deterministic(L):
+    P = jd.Precond(L, 16.5, 0, 0.0)
+    n = L ** 3
+    u, v = seeded_inputs.vector(n, 1), seeded_inputs.vector(n, 2)
+    Ku = torch.empty(n, dtype=torch.float64, device="cuda")
+    Kv = torch.empty(n, dtype=torch.float64, device="cuda")
+    Ku2 = torch.empty(n, dtype=torch.float64, device="cuda")
+    P.apply(dev(u), Ku, stream=stream())
+    P.apply(dev(v), Kv, stream=stream())
+    P.apply(dev(u), Ku2, stream=stream())
+    torch.cuda.synchronize()
+    a, b = v @ Ku.cpu().numpy(), u @ Kv.cpu().numpy()
+    assert abs(a - b) <= 1e-11 * abs(a)
+    assert torch.equal(Ku, Ku2)
+    P.close()
+
+
+# --- inner iteration: simplified QMR with the projected preconditioner ----------------------
+
+def test_linear_solve_exact_preconditioner_one_step():
+    L, sigma = 8, 0.21
+    p = jd.Problem(L, 16.5, 4, sigma, drop_tol=-1.0, coarse_max=40)
+    eps = generator.disorder(L, 16.5, 4)
+    b = seeded_inputs.vector(L ** 3, 9)
+    x = torch.zeros(L ** 3, dtype=torch.float64, device="cuda")
+    its = p.linear_solve(sigma, dev(b), x, rtol=1e-12, maxit=10)
+    torch.cuda.synchronize()
+    ref = ldlt.LDLT(L, eps, sigma, leaf=64).solve(b)
+    assert its <= 2
+    assert np.linalg.norm(x.cpu().numpy() - ref) <= 1e-9 * np.linalg.norm(ref)
+    p.close()
+
+
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-10, 1e-9), ("mixed", 1e-5, 1e-4)])
+def test_linear_solve_projected(precision, rtol, tol):
+    L, sigma = 16, 0.05
+    n = L ** 3
+    p = jd.Problem(L, 16.5, 1, sigma, precision=precision)
+    eps = generator.disorder(L, 16.5, 1)
+    Q = seeded_inputs.orthonormal_block(n, 3, 5)
+    b = seeded_inputs.vector(n, 11)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    its = p.linear_solve(sigma, dev(b), x, Q=dev(Q), rtol=rtol, maxit=400)
+    torch.cuda.synchronize()
+    xs = x.cpu().numpy()
+    proj = lambda v: v - Q @ (Q.T @ v)
+    res = proj(lattice.matvec(L, eps, proj(xs), shift=sigma)) - proj(b)
+    assert np.abs(Q.T @ xs).max() <= 1e-6 * np.linalg.norm(xs)
+    assert np.linalg.norm(res) <= tol * np.linalg.norm(proj(b)) * 20
+    assert 1 <= its < 400
+    p.close()
+
+
+# --- the solve: eigenpairs nearest sigma -----------------------------------------------------
+
+def _check_pairs(L, W, seed, sigma, k, lams_ref, evals, evecs, resid, info, tol=1e-10, vec_ref=None):
+    eps = generator.disorder(L, W, seed)
+    anorm = lattice.inf_norm(eps)
+    assert info["n_converged"] == k
+    assert np.all(np.abs(evals - lams_ref) <= 1e-9), (evals, lams_ref)
+    # residuals recomputed by the oracle's own product
+    for c in range(k):
+        x = evecs[:, c]
+        r = np.linalg.norm(lattice.matvec(L, eps, x) - evals[c] * x)
+        assert r <= tol * anorm * 1.0001, (c, r / anorm)
+        assert abs(resid[c] - r / anorm) <= 1e-3 * max(r / anorm, 1e-16) + 1e-15
+    G = evecs.T @ evecs
+    assert np.abs(G - np.eye(k)).max() <= 1e-8
+    if vec_ref is not None:
+        for c in range(k):
+            assert abs(abs(evecs[:, c] @ vec_ref[:, c]) - 1.0) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_small_live_oracle(precision):
+    L, W, seed, sigma, k = 8, 16.5, 3, 0.0, 5
+    ref, X, _, _ = eig.anderson_nearest(L, W, seed, sigma, k, method="dense")
+    evals, evecs, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, vectors=True, precision=precision)
+    _check_pairs(L, W, seed, sigma, k, ref, evals, evecs, resid, info, vec_ref=X)
+    assert np.allclose(evecs, X, atol=1e-7)  # same sign convention
+
+
+@pytest.mark.parametrize("L,W,seed,sigma,k", [(12, 12.0, 5, 0.3, 7), (15, 21.0, 8, -0.6, 4)])
+def test_solve_ragged_live_oracle(L, W, seed, sigma, k):
+    ref, X, _, _ = eig.anderson_nearest(L, W, seed, sigma, k)
+    evals, evecs, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, vectors=True, precision="mixed")
+    _check_pairs(L, W, seed, sigma, k, ref, evals, evecs, resid, info, vec_ref=X)
+
+
+def _golden(name):
+    with open(os.path.join(GOLD, name + ".json")) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("name,precision", [("L10_W16.5_s0_k5", "fp64"), ("L10_W16.5_s0_k5", "mixed"),
+                                            ("L20_W12_s1000000_k7", "mixed"), ("L30_W21_s1000001_k3", "mixed"),
+                                            ("L40_W16.5_s1000002_k10", "mixed"), ("L50_W16.5_s0_k5", "fp64")])
+def test_solve_against_stored_oracle(name, precision):
+    g = _golden(name)
+    evals, evecs, resid, info = jd.solve(g["L"], g["W"], g["seed"], g["sigma"], g["k"], 1e-10, vectors=True,
+                                         precision=precision)
+    _check_pairs(g["L"], g["W"], g["seed"], g["sigma"], g["k"], np.array(g["lams"]), evals, evecs, resid, info)
