@@ -55,19 +55,29 @@ enum { JD_FP64 = 0, JD_MIXED = 1 };
  *             (binary32 accumulation); Gram-Schmidt, Rayleigh-Ritz, residual
  *             norms and acceptance in binary64.
  *  drop_tol   epsilon of section 7.2: an entry of a factor column is dropped when
- *             its modulus is below drop_tol / kappa (0 -> 1e-2).
+ *             its modulus is below drop_tol / kappa (0 -> 1/sqrt(n), the paper's
+ *             choice in section 8.2; < 0 -> nothing dropped, exact factorisation).
  *  kappa      bound on ||L^{-1}|| of inverse-based pivoting, section 7.2 (0 -> 5).
  *  agg_tau    tau of the aggressive dropping rule of section 7.3 (0 -> 0.1).
  *  schur_tol  off-diagonal entries of a scaled Schur complement below this are
  *             dropped (0 -> drop_tol).
  *  coarse_max the multilevel recursion (section 7.3) stops at this size and the
- *             last Schur complement is inverted exactly (0 -> 1536).
- *  max_levels cap on the number of levels (0 -> 64).
+ *             last Schur complement is inverted exactly (0 -> 1536); it also stops
+ *             once a level accepts fewer than 1% of its unknowns and at most 8192 remain.
+ *  max_levels cap on the number of levels (0 -> 400).
+ *  z_drop     the preconditioner is applied as P^T Z^T D^{-1} Z P with Z the explicit
+ *             inverse of the unit lower triangular factor of all levels; entries of Z
+ *             below z_drop (scaled domain) are dropped (0 -> 1e-2; < 0 -> none).
  *  jmin, jmax search-space sizes after / before a restart (0 -> max(k+5,10), 2 jmin).
  *  max_outer  outer Jacobi-Davidson iterations (0 -> 60 k + 200).
  *  max_inner  SQMR steps per correction equation (0 -> 40).
  *  switch_tol the correction operator uses sigma until ||r|| < switch_tol ||A||_inf,
  *             then the Ritz value theta (0 -> 1e-3).
+ *  flags      bit 0 (JD_FLAG_EAGER): launch the inner iteration kernel by kernel instead
+ *             of replaying it as a captured HIP graph (same arithmetic, same results).
+ *             bit 1 (JD_FLAG_LEVELS): apply the factorisation level by level (two
+ *             dependent sparse passes per level) instead of through Z.
+ *  stream     stream for the solve's device work (NULL: a library-created blocking stream).
  */
 typedef struct jd_options {
     int precision;
@@ -77,11 +87,15 @@ typedef struct jd_options {
     double schur_tol;
     int coarse_max;
     int max_levels;
+    double z_drop;
     int jmin, jmax;
     int max_outer, max_inner;
     double switch_tol;
+    int flags;
     void *stream;
 } jd_options;
+
+enum { JD_FLAG_EAGER = 1, JD_FLAG_LEVELS = 2 };
 
 /* Statistics of a solve (the paper's Tables 3-5 quantities plus timings). */
 typedef struct jd_info {
@@ -125,6 +139,9 @@ int jd_setup(int L, double W, uint64_t seed, double sigma, const jd_options *opt
  * array of n*k binary64 values that receives the eigenvectors. */
 int jd_problem_solve(jd_problem *p, int k, double tol, double *evals, double *evecs_host,
                      void *evecs_device, double *resid, jd_info *info);
+/* Switch the precision of later jd_problem_solve calls (JD_FP64 or JD_MIXED); the setup
+ * keeps the factors in both precisions, so no new setup is needed. */
+int jd_problem_set_precision(jd_problem *p, int precision);
 /* Setup statistics of a problem (levels, fill, timings so far). */
 int jd_problem_info(const jd_problem *p, jd_info *info);
 void jd_problem_free(jd_problem *p);

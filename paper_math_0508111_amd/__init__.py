@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libjdmi.so")
 
 JD_OK, JD_ENOCONV, JD_EINVAL, JD_ENOMEM, JD_EDEVICE, JD_ESETUP, JD_ENOTIMPL = 0, 1, -1, -2, -3, -4, -5
 JD_FP64, JD_MIXED = 0, 1
+JD_FLAG_EAGER = 1
+JD_FLAG_LEVELS = 2
 _PREC = {"fp64": JD_FP64, "mixed": JD_MIXED, JD_FP64: JD_FP64, JD_MIXED: JD_MIXED}
 
 
@@ -29,9 +31,9 @@ class JdError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("drop_tol", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("agg_tau", ctypes.c_double), ("schur_tol", ctypes.c_double), ("coarse_max", ctypes.c_int),
-                ("max_levels", ctypes.c_int), ("jmin", ctypes.c_int), ("jmax", ctypes.c_int),
+                ("max_levels", ctypes.c_int), ("z_drop", ctypes.c_double), ("jmin", ctypes.c_int), ("jmax", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int), ("switch_tol", ctypes.c_double),
-                ("stream", ctypes.c_void_p)]
+                ("flags", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -44,7 +46,7 @@ class Info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-EXPORTS = ["jd_solve", "jd_setup", "jd_problem_solve", "jd_problem_info", "jd_problem_free", "jd_gen_diag",
+EXPORTS = ["jd_solve", "jd_setup", "jd_problem_solve", "jd_problem_info", "jd_problem_set_precision", "jd_problem_free", "jd_gen_diag",
            "jd_stencil_spmv", "jd_precond_create", "jd_precond_apply", "jd_precond_levels", "jd_precond_free",
            "jd_problem_linear_solve", "jd_last_error", "jd_version"]
 
@@ -66,6 +68,7 @@ def lib():
         "jd_setup": (I, [I, D, U64, D, OP, ctypes.POINTER(P)]),
         "jd_problem_solve": (I, [P, I, D, P, P, P, P, IP]),
         "jd_problem_info": (I, [P, IP]),
+        "jd_problem_set_precision": (I, [P, I]),
         "jd_problem_free": (None, [P]),
         "jd_gen_diag": (I, [I, D, U64, P, P, P]),
         "jd_stencil_spmv": (I, [I, I, P, D, P, P, P]),
@@ -141,6 +144,9 @@ class Problem:
         h = ctypes.c_void_p()
         _check(lib().jd_setup(L, float(W), seed, float(sigma), ctypes.byref(self._opts), ctypes.byref(h)))
         self._h = h
+
+    def set_precision(self, precision):
+        _check(lib().jd_problem_set_precision(self._h, _PREC[precision]))
 
     def info(self):
         i = Info()

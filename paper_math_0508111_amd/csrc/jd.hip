@@ -94,6 +94,11 @@ struct DevPrecond {
     int coarse_off = 0, coarse_n = 0;
     T *cinv = nullptr;
     T *w = nullptr, *x = nullptr;  // workspaces
+    // explicit inverse factor form
+    bool inv = false;
+    const int64_t *zptr = nullptr, *ztptr = nullptr;
+    const int *zcol = nullptr, *ztcol = nullptr, *dp = nullptr;
+    const T *zval = nullptr, *ztval = nullptr, *dd = nullptr, *dof = nullptr;
 
     void upload(const jdmi::Multilevel &ml, const int *dperm, DevMem &mem, hipStream_t s)
     {
@@ -121,6 +126,18 @@ struct DevPrecond {
         cinv = mem.upload(cast_vec<T>(ml.coarse_inv), s);
         w = mem.alloc<T>(n);
         x = mem.alloc<T>(n);
+        inv = !ml.z.ptr.empty();
+        if (inv) {
+            zptr = mem.upload(ml.z.ptr, s);
+            zcol = mem.upload(ml.z.col, s);
+            zval = mem.upload(cast_vec<T>(ml.z.val), s);
+            ztptr = mem.upload(ml.z.tptr, s);
+            ztcol = mem.upload(ml.z.tcol, s);
+            ztval = mem.upload(cast_vec<T>(ml.z.tval), s);
+            dd = mem.upload(cast_vec<T>(ml.z.dd), s);
+            dof = mem.upload(cast_vec<T>(ml.z.dof), s);
+            dp = mem.upload(ml.z.dp, s);
+        }
         // keep the converted host vectors alive until the copies are done
         HIPCHK(hipStreamSynchronize(s));
     }
@@ -128,6 +145,16 @@ struct DevPrecond {
     // out = K^{-1} in
     void apply(const T *in, T *out, hipStream_t s, const int *skip = nullptr) const
     {
+        if (inv) {
+            // P^T Z^T D^{-1} Z P in: gather, sparse product, block diagonal (+ exact last
+            // level), transposed sparse product with the inverse permutation on output
+            jdmi::launch_gather<T>(n, perm, in, w, s, skip);
+            jdmi::launch_zspmv<T>(n, zptr, zcol, zval, w, x, nullptr, s, skip);
+            jdmi::launch_dinv<T>(coarse_off, dd, dof, dp, x, w, s, skip);
+            jdmi::launch_coarse<T>(coarse_n, coarse_off, cinv, x, w, s, skip);
+            jdmi::launch_zspmv<T>(n, ztptr, ztcol, ztval, w, out, perm, s, skip);
+            return;
+        }
         jdmi::launch_gather<T>(n, perm, in, w, s, skip);
         for (const auto &lv : levels) jdmi::launch_down<T>(lv, w, s, skip);
         jdmi::launch_coarse<T>(coarse_n, coarse_off, cinv, w, x, s, skip);
@@ -154,14 +181,15 @@ struct Setup {
     int n2x2 = 0;
 };
 
-void fill_defaults(jd_options &o)
+void fill_defaults(jd_options &o, int n)
 {
-    if (o.drop_tol == 0) o.drop_tol = 1e-2;
+    if (o.drop_tol == 0) o.drop_tol = 1.0 / std::sqrt(double(n));
     if (o.kappa == 0) o.kappa = 5.0;
     if (o.agg_tau == 0) o.agg_tau = 0.1;
     if (o.schur_tol == 0) o.schur_tol = o.drop_tol > 0 ? o.drop_tol : -1.0;
     if (o.coarse_max == 0) o.coarse_max = 1536;
-    if (o.max_levels == 0) o.max_levels = 64;
+    if (o.max_levels == 0) o.max_levels = 400;
+    if (o.z_drop == 0) o.z_drop = o.drop_tol < 0 ? -1.0 : 1e-2;
     if (o.max_inner == 0) o.max_inner = 40;
     if (o.switch_tol == 0) o.switch_tol = 1e-3;
 }
@@ -176,6 +204,8 @@ void check_problem_args(int L, double W, double sigma, const jd_options *opt)
         if (opt->coarse_max < 0 || opt->coarse_max > 8192) throw JdError(JD_EINVAL, "coarse_max must be in [0, 8192]");
         if (opt->jmin < 0 || opt->jmax < 0 || opt->jmax > 120) throw JdError(JD_EINVAL, "jmin/jmax out of range");
         if (opt->max_inner < 0 || opt->max_outer < 0 || opt->max_levels < 0) throw JdError(JD_EINVAL, "negative iteration cap");
+        if (opt->flags & ~(JD_FLAG_EAGER | JD_FLAG_LEVELS)) throw JdError(JD_EINVAL, "unknown flag bits");
+        if (!std::isfinite(opt->z_drop)) throw JdError(JD_EINVAL, "non-finite option");
         if (!std::isfinite(opt->drop_tol) || !std::isfinite(opt->kappa) || opt->kappa < 0 ||
             !std::isfinite(opt->agg_tau) || !std::isfinite(opt->schur_tol) || !std::isfinite(opt->switch_tol))
             throw JdError(JD_EINVAL, "non-finite option");
@@ -192,7 +222,7 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
     S.seed = seed;
     S.sigma = sigma;
     if (opt) S.opt = *opt;
-    fill_defaults(S.opt);
+    fill_defaults(S.opt, S.n);
     if (S.opt.stream) {
         S.stream = static_cast<hipStream_t>(S.opt.stream);
     } else {
@@ -220,6 +250,8 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
     prm.schur_tol = S.opt.schur_tol;
     prm.coarse_max = S.opt.coarse_max;
     prm.max_levels = S.opt.max_levels;
+    prm.z_drop = S.opt.z_drop;
+    prm.inverse_factor = (S.opt.flags & JD_FLAG_LEVELS) == 0;
     std::string err = jdmi::build_multilevel(A, prm, S.ml);
     if (!err.empty()) throw JdError(JD_ESETUP, err);
     S.n2x2 = 0;
@@ -309,9 +341,13 @@ struct SqmrBufs {
     T *r, *q, *t, *d, *x, *u, *b;
     jdmi::SqmrState *st;
     double *partial, *red, *coef, *g;
-    int *done_host;  // pinned
+    int *flags_host;  // pinned, two slots
 };
 
+// Simplified QMR on the device.  The start and one step are each captured once per
+// projection width p into a HIP graph and replayed; every scalar (alpha, theta, c,
+// tau, beta, the shift and the stop flag) lives in device memory, and the host reads
+// only the stop flag, one step behind the device.
 template <typename T>
 struct Solver {
     Setup &S;
@@ -319,10 +355,15 @@ struct Solver {
     const T *eps;
     hipStream_t s;
     int n;
+    bool graphs;
     SqmrBufs<T> B{};
     DevMem mem;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    struct Pair { hipGraphExec_t init = nullptr, step = nullptr; const T *Qt = nullptr, *Y = nullptr; const double *M = nullptr; };
+    std::vector<Pair> cache;
 
-    Solver(Setup &S_, const DevPrecond<T> &pc_, const T *eps_) : S(S_), pc(pc_), eps(eps_), s(S_.stream), n(S_.n)
+    Solver(Setup &S_, const DevPrecond<T> &pc_, const T *eps_, bool graphs_)
+        : S(S_), pc(pc_), eps(eps_), s(S_.stream), n(S_.n), graphs(graphs_)
     {
         B.r = mem.alloc<T>(n);
         B.q = mem.alloc<T>(n);
@@ -336,51 +377,110 @@ struct Solver {
         B.red = mem.alloc<double>(256);
         B.coef = mem.alloc<double>(256);
         B.g = mem.alloc<double>(256);
-        HIPCHK(hipHostMalloc((void **)&B.done_host, sizeof(int), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&B.flags_host, 2 * sizeof(int), hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        cache.resize(130);
     }
-    ~Solver() { (void)hipHostFree(B.done_host); }
+    ~Solver()
+    {
+        for (auto &c : cache) {
+            if (c.init) (void)hipGraphExecDestroy(c.init);
+            if (c.step) (void)hipGraphExecDestroy(c.step);
+        }
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        (void)hipHostFree(B.flags_host);
+    }
 
-    // Simplified QMR for (I - Qt Qt^T)(A - shift I) x = b, b already orthogonal to Qt,
-    // with preconditioner K^{-1} - Y M Y^T (M = (Qt^T Y)^{-1}, p x p on the device).
-    // Returns the number of steps.  x is left in B.x.
-    int sqmr(double shift, const T *Qt, const T *Y, int p, const double *dM, double rtol, int maxit)
+    void enqueue_init(const T *Qt, const T *Y, int p, const double *dM)
+    {
+        jdmi::launch_sqmr_init<T>(n, B.b, B.r, B.x, B.d, s);
+        jdmi::launch_dot<T>(n, B.r, B.r, B.partial, B.red + 0, s);
+        precond_projected(B.r, B.u, Qt, Y, p, dM, nullptr);  // u = P r
+        jdmi::launch_dot<T>(n, B.r, B.u, B.partial, B.red + 1, s);
+        jdmi::launch_sqmr_scalar_start(B.st, B.red + 0, B.red + 1, s);
+        jdmi::launch_copy<T>(n, B.u, B.q, s);
+    }
+
+    void enqueue_step(const T *Qt, const T *Y, int p, const double *dM)
     {
         const int *skip_a = &B.st->done;
         const int *skip_b = &B.st->done_next;
-        jdmi::launch_sqmr_init<T>(n, B.b, B.r, B.x, B.d, s);
-        jdmi::launch_dot<T>(n, B.r, B.r, B.partial, B.red + 0, s);
-        // u = P r
-        precond_projected(B.r, B.u, Qt, Y, p, dM, nullptr);
-        jdmi::launch_dot<T>(n, B.r, B.u, B.partial, B.red + 1, s);
-        jdmi::launch_sqmr_scalar_start(B.st, B.red + 0, B.red + 1, rtol, s);
-        HIPCHK(hipMemcpyAsync(B.q, B.u, n * sizeof(T), hipMemcpyDeviceToDevice, s));
-        int its = 0;
-        for (int j = 1; j <= maxit; ++j) {
-            // t = (I - Qt Qt^T)(A - shift I) q
-            jdmi::launch_stencil<T>(S.L, eps, shift, B.q, B.t, s, skip_a);
-            if (p > 0) {
-                jdmi::launch_multidot<T>(n, p, Qt, n, B.t, B.partial, B.coef, s, skip_a);
-                jdmi::launch_sub_qc<T>(n, p, Qt, n, B.coef, B.t, s, skip_a);
+        // t = (I - Qt Qt^T)(A - shift I) q
+        jdmi::launch_stencil_state<T>(S.L, eps, B.st, B.q, B.t, s);
+        if (p > 0) {
+            jdmi::launch_multidot<T>(n, p, Qt, n, B.t, B.partial, B.coef, s, skip_a);
+            jdmi::launch_sub_qc<T>(n, p, Qt, n, B.coef, B.t, s, skip_a);
+        }
+        jdmi::launch_dot<T>(n, B.q, B.t, B.partial, B.red + 2, s, skip_a);
+        jdmi::launch_sqmr_scalar_alpha(B.st, B.red + 2, s);
+        jdmi::launch_sqmr_update_r<T>(n, B.st, B.t, B.r, B.partial, B.red + 3, s);
+        jdmi::launch_sqmr_scalar_theta(B.st, B.red + 3, s);
+        jdmi::launch_sqmr_update_xd<T>(n, B.st, B.q, B.d, B.x, s);
+        precond_projected(B.r, B.u, Qt, Y, p, dM, skip_b);
+        jdmi::launch_dot<T>(n, B.r, B.u, B.partial, B.red + 4, s, skip_b);
+        jdmi::launch_sqmr_scalar_beta(B.st, B.red + 4, s);
+        jdmi::launch_sqmr_update_q<T>(n, B.st, B.u, B.q, s);
+    }
+
+    template <typename F>
+    hipGraphExec_t capture(F &&f)
+    {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t e = nullptr;
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+        f();
+        HIPCHK(hipStreamEndCapture(s, &g));
+        HIPCHK(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        return e;
+    }
+
+    // Simplified QMR for (I - Qt Qt^T)(A - shift I) x = b, b already orthogonal to Qt,
+    // with preconditioner K^{-1} - Y M Y^T (M = (Qt^T Y)^{-1}, p x p on the device).
+    // Returns the number of steps; the solution is left in B.x.
+    int sqmr(double shift, const T *Qt, const T *Y, int p, const double *dM, double rtol, int maxit)
+    {
+        jdmi::launch_sqmr_params(B.st, shift, rtol, s);
+        Pair *pr = nullptr;
+        if (graphs) {
+            if (p >= int(cache.size())) throw JdError(JD_EINVAL, "projection too wide");
+            pr = &cache[p];
+            if (pr->init && (pr->Qt != Qt || pr->Y != Y || pr->M != dM)) {
+                (void)hipGraphExecDestroy(pr->init);
+                (void)hipGraphExecDestroy(pr->step);
+                pr->init = pr->step = nullptr;
             }
-            jdmi::launch_dot<T>(n, B.q, B.t, B.partial, B.red + 2, s, skip_a);
-            jdmi::launch_sqmr_scalar_alpha(B.st, B.red + 2, s);
-            jdmi::launch_sqmr_update_r<T>(n, B.st, B.t, B.r, B.partial, B.red + 3, s);
-            jdmi::launch_sqmr_scalar_theta(B.st, B.red + 3, s);
-            jdmi::launch_sqmr_update_xd<T>(n, B.st, B.q, B.d, B.x, s);
-            precond_projected(B.r, B.u, Qt, Y, p, dM, skip_b);
-            jdmi::launch_dot<T>(n, B.r, B.u, B.partial, B.red + 4, s, skip_b);
-            jdmi::launch_sqmr_scalar_beta(B.st, B.red + 4, s);
-            jdmi::launch_sqmr_update_q<T>(n, B.st, B.u, B.q, s);
-            HIPCHK(hipMemcpyAsync(B.done_host, &B.st->done, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            its = j;
-            if (*B.done_host) break;
+            if (!pr->init) {
+                pr->init = capture([&] { enqueue_init(Qt, Y, p, dM); });
+                pr->step = capture([&] { enqueue_step(Qt, Y, p, dM); });
+                pr->Qt = Qt;
+                pr->Y = Y;
+                pr->M = dM;
+            }
+            HIPCHK(hipGraphLaunch(pr->init, s));
+        } else {
+            enqueue_init(Qt, Y, p, dM);
+        }
+        // one step of look-ahead: the host reads the stop flag of step j-1 while step j runs
+        int launched = 0;
+        while (launched < maxit) {
+            if (graphs) HIPCHK(hipGraphLaunch(pr->step, s));
+            else enqueue_step(Qt, Y, p, dM);
+            const int slot = launched & 1;
+            ++launched;
+            HIPCHK(hipMemcpyAsync(&B.flags_host[slot], &B.st->done, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(ev[slot], s));
+            if (launched >= 2) {
+                HIPCHK(hipEventSynchronize(ev[slot ^ 1]));
+                if (B.flags_host[slot ^ 1]) break;
+            }
         }
         HIPCHK(hipGetLastError());
         jdmi::SqmrState hs;
         HIPCHK(hipMemcpyAsync(&hs, B.st, sizeof(hs), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        (void)its;
         return hs.j;
     }
 
@@ -414,7 +514,7 @@ int jd_run(Setup &S, const DevPrecond<T> &pc, const T *eps, int k, double tol, O
     const double anorm = S.anorm;
     const double sigma = S.sigma;
 
-    Solver<T> sv(S, pc, eps);
+    Solver<T> sv(S, pc, eps, (o.flags & JD_FLAG_EAGER) == 0);
     DevMem mem;
     double *V = mem.alloc<double>(size_t(n) * jmax);
     double *AV = mem.alloc<double>(size_t(n) * jmax);
@@ -733,6 +833,16 @@ void jd_problem_free(jd_problem *p)
     if (own) (void)hipStreamDestroy(s);
 }
 
+int jd_problem_set_precision(jd_problem *p, int precision)
+{
+    return guarded([&] {
+        if (!p) throw JdError(JD_EINVAL, "NULL problem");
+        if (precision != JD_FP64 && precision != JD_MIXED) throw JdError(JD_EINVAL, "unknown precision");
+        p->S.opt.precision = precision;
+        return JD_OK;
+    });
+}
+
 int jd_problem_info(const jd_problem *p, jd_info *info)
 {
     return guarded([&] {
@@ -876,7 +986,7 @@ int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int 
         hipStream_t s = S.stream;
         auto run = [&](auto tag, const auto &pc, const auto *eps) {
             using T = decltype(tag);
-            Solver<T> sv(S, pc, eps);
+            Solver<T> sv(S, pc, eps, (S.opt.flags & JD_FLAG_EAGER) == 0);
             DevMem mem;
             const int pc_ = pcols;
             T *Qt = mem.alloc<T>(size_t(n) * std::max(pc_, 1));

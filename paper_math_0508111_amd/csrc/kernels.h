@@ -12,6 +12,7 @@ constexpr int kRedBlocks = 1024;   // fixed grid of the deterministic reductions
 struct SqmrState {
     double rho, sigma, alpha, tau, tau0, theta, theta_old, c1, c2, beta, rr;
     double tol;       // stop when tau * sqrt(j+1) <= tol * tau0
+    double shift;     // operator (A - shift I)
     int j;
     int done;         // set before this step: every kernel of the step is skipped
     int done_next;    // set during this step: the rest of the step is skipped
@@ -43,6 +44,15 @@ void launch_up(const DevLevel<T> &lv, const T *w, T *x, hipStream_t s, const int
 template <typename T>
 void launch_coarse(int nc, int off, const T *cinv, const T *w, T *x, hipStream_t s, const int *skip);
 
+// explicit inverse factor apply: y = Z w (16 lanes per row); optional output permutation
+// out[perm[r]] = (Z w)[r]
+template <typename T>
+void launch_zspmv(int n, const int64_t *ptr, const int *col, const T *val, const T *w, T *y, const int *out_perm,
+                  hipStream_t s, const int *skip);
+// z[j] = dd[j] y[j] + dof[j] y[dp[j]] for j < m
+template <typename T>
+void launch_dinv(int m, const T *dd, const T *dof, const int *dp, const T *y, T *z, hipStream_t s, const int *skip);
+
 // ---- reductions (deterministic two-stage; results stay on the device) ---------------
 // partial[c * kRedBlocks + b] for c < ncols; out[c] = sum
 template <typename T>
@@ -72,7 +82,13 @@ void launch_random_vector(int n, uint64_t seed, double *x, hipStream_t s);
 // ---- simplified QMR pieces (scalars read from SqmrState on the device) -----------------
 template <typename T>
 void launch_sqmr_init(int n, const T *b, T *r, T *x, T *d, hipStream_t s);
-void launch_sqmr_scalar_start(SqmrState *st, const double *rr, const double *rho, double tol, hipStream_t s);
+void launch_sqmr_params(SqmrState *st, double shift, double tol, hipStream_t s);
+void launch_sqmr_scalar_start(SqmrState *st, const double *rr, const double *rho, hipStream_t s);
+// t = (A - st->shift I) q, skipped when st->done
+template <typename T>
+void launch_stencil_state(int L, const T *eps, const SqmrState *st, const T *x, T *y, hipStream_t s);
+template <typename T>
+void launch_copy(int n, const T *x, T *y, hipStream_t s);
 void launch_sqmr_scalar_alpha(SqmrState *st, const double *sigma, hipStream_t s);
 void launch_sqmr_scalar_theta(SqmrState *st, const double *rr, hipStream_t s);
 void launch_sqmr_scalar_beta(SqmrState *st, const double *rho, hipStream_t s);

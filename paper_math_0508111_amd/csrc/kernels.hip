@@ -99,6 +99,47 @@ void launch_stencil(int L, const T *eps, double shift, const T *x, T *y, hipStre
     hipLaunchKernelGGL(k_stencil<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, L, n, eps, T(shift), x, y, skip);
 }
 
+// the same product with the shift read from the solver state (graph-replayable)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_stencil_state(int L, int n, const T *__restrict__ eps,
+                                                          const SqmrState *st, const T *__restrict__ x,
+                                                          T *__restrict__ y)
+{
+    if (st->done) return;
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const T shift = T(st->shift);
+    const int LL = L * L;
+    const int i = s % L, jk = s / L, j = jk % L, k = jk / L;
+    const int xm = (i == 0) ? s + L - 1 : s - 1;
+    const int xp = (i == L - 1) ? s - L + 1 : s + 1;
+    const int ym = (j == 0) ? s + LL - L : s - L;
+    const int yp = (j == L - 1) ? s - LL + L : s + L;
+    const int zm = (k == 0) ? s + n - LL : s - LL;
+    const int zp = (k == L - 1) ? s - n + LL : s + LL;
+    const T nb = ((x[xm] + x[xp]) + (x[ym] + x[yp])) + (x[zm] + x[zp]);
+    y[s] = (eps[s] - shift) * x[s] - nb;
+}
+
+template <typename T>
+void launch_stencil_state(int L, const T *eps, const SqmrState *st, const T *x, T *y, hipStream_t s)
+{
+    const int n = L * L * L;
+    hipLaunchKernelGGL(k_stencil_state<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, L, n, eps, st, x, y);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_copy(int n, const T *__restrict__ x, T *__restrict__ y)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+template <typename T>
+void launch_copy(int n, const T *x, T *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, x, y);
+}
+
 // ---------------------------------------------------------------------------------
 // Multilevel preconditioner apply (global permuted positions, scalings folded in).
 // ---------------------------------------------------------------------------------
@@ -198,6 +239,55 @@ void launch_coarse(int nc, int off, const T *cinv, const T *w, T *x, hipStream_t
 {
     if (nc <= 0) return;
     hipLaunchKernelGGL(k_coarse<T>, dim3(nblocks(nc, kBlock / 64)), dim3(kBlock), 0, s, nc, off, cinv, w, x, skip);
+}
+
+// ---------------------------------------------------------------------------------
+// Explicit inverse factor: 16 lanes per row stride over the row's entries (coalesced
+// column/value reads), then a fixed-order shuffle tree inside the 16-lane segment.
+// ---------------------------------------------------------------------------------
+constexpr int kZLanes = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_zspmv(int n, const int64_t *__restrict__ ptr, const int *__restrict__ col,
+                                                  const T *__restrict__ val, const T *__restrict__ w,
+                                                  T *__restrict__ y, const int *__restrict__ out_perm,
+                                                  const int *skip)
+{
+    if (skip && *skip) return;
+    const int lane = threadIdx.x & (kZLanes - 1);
+    const int r = blockIdx.x * (kBlock / kZLanes) + (threadIdx.x / kZLanes);
+    if (r >= n) return;  // the whole 16-lane segment leaves together
+    T acc = T(0);
+    for (int64_t p = ptr[r] + lane, e = ptr[r + 1]; p < e; p += kZLanes) acc += val[p] * w[col[p]];
+#pragma unroll
+    for (int o = kZLanes / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kZLanes);
+    if (lane == 0) y[out_perm ? out_perm[r] : r] = acc;
+}
+
+template <typename T>
+void launch_zspmv(int n, const int64_t *ptr, const int *col, const T *val, const T *w, T *y, const int *out_perm,
+                  hipStream_t s, const int *skip)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zspmv<T>, dim3(nblocks(n, kBlock / kZLanes)), dim3(kBlock), 0, s, n, ptr, col, val, w, y,
+                       out_perm, skip);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dinv(int m, const T *__restrict__ dd, const T *__restrict__ dof,
+                                                 const int *__restrict__ dp, const T *__restrict__ y,
+                                                 T *__restrict__ z, const int *skip)
+{
+    if (skip && *skip) return;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j < m) z[j] = dd[j] * y[j] + dof[j] * y[dp[j]];
+}
+
+template <typename T>
+void launch_dinv(int m, const T *dd, const T *dof, const int *dp, const T *y, T *z, hipStream_t s, const int *skip)
+{
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_dinv<T>, dim3(nblocks(m)), dim3(kBlock), 0, s, m, dd, dof, dp, y, z, skip);
 }
 
 // ---------------------------------------------------------------------------------
@@ -413,7 +503,18 @@ void launch_sqmr_init(int n, const T *b, T *r, T *x, T *d, hipStream_t s)
     hipLaunchKernelGGL(k_sqmr_init<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, b, r, x, d);
 }
 
-__global__ void k_sqmr_start(SqmrState *st, const double *rr, const double *rho, double tol)
+__global__ void k_sqmr_params(SqmrState *st, double shift, double tol)
+{
+    if (threadIdx.x != 0) return;
+    st->shift = shift;
+    st->tol = tol;
+}
+void launch_sqmr_params(SqmrState *st, double shift, double tol, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sqmr_params, dim3(1), dim3(64), 0, s, st, shift, tol);
+}
+
+__global__ void k_sqmr_start(SqmrState *st, const double *rr, const double *rho)
 {
     if (threadIdx.x != 0) return;
     st->tau = sqrt(*rr);
@@ -421,14 +522,13 @@ __global__ void k_sqmr_start(SqmrState *st, const double *rr, const double *rho,
     st->rho = *rho;
     st->theta_old = 0.0;
     st->j = 0;
-    st->tol = tol;
     st->breakdown = 0;
     st->done = (st->tau == 0.0 || st->rho == 0.0 || !isfinite(st->rho)) ? 1 : 0;
     st->done_next = st->done;
 }
-void launch_sqmr_scalar_start(SqmrState *st, const double *rr, const double *rho, double tol, hipStream_t s)
+void launch_sqmr_scalar_start(SqmrState *st, const double *rr, const double *rho, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sqmr_start, dim3(1), dim3(64), 0, s, st, rr, rho, tol);
+    hipLaunchKernelGGL(k_sqmr_start, dim3(1), dim3(64), 0, s, st, rr, rho);
 }
 
 __global__ void k_sqmr_alpha(SqmrState *st, const double *sigma)
@@ -565,11 +665,17 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
 // ---- explicit instantiations ------------------------------------------------------
 #define JD_INST(T)                                                                                        \
     template void launch_stencil<T>(int, const T *, double, const T *, T *, hipStream_t, const int *);    \
+    template void launch_stencil_state<T>(int, const T *, const SqmrState *, const T *, T *, hipStream_t); \
+    template void launch_copy<T>(int, const T *, T *, hipStream_t);                                       \
     template void launch_gather<T>(int, const int *, const T *, T *, hipStream_t, const int *);            \
     template void launch_scatter<T>(int, const int *, const T *, T *, hipStream_t, const int *);           \
     template void launch_down<T>(const DevLevel<T> &, T *, hipStream_t, const int *);                      \
     template void launch_up<T>(const DevLevel<T> &, const T *, T *, hipStream_t, const int *);             \
     template void launch_coarse<T>(int, int, const T *, const T *, T *, hipStream_t, const int *);         \
+    template void launch_zspmv<T>(int, const int64_t *, const int *, const T *, const T *, T *, const int *,\
+                                  hipStream_t, const int *);                                               \
+    template void launch_dinv<T>(int, const T *, const T *, const int *, const T *, T *, hipStream_t,      \
+                                 const int *);                                                             \
     template void launch_multidot<T>(int, int, const T *, int64_t, const T *, double *, double *,          \
                                      hipStream_t, const int *);                                            \
     template void launch_dot<T>(int, const T *, const T *, double *, double *, hipStream_t, const int *);  \

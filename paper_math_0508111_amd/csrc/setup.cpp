@@ -20,6 +20,8 @@
 #include <numeric>
 #include <queue>
 #include <utility>
+#include <cstdio>
+#include <cstdlib>
 
 #ifdef _OPENMP
 #include <omp.h>
@@ -621,16 +623,29 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
     // level-local -> original sites of B members, per level, to build the permutation
     std::vector<std::vector<int>> level_orig;
     int off = 0;
+    const bool verbose = std::getenv("JDMI_VERBOSE") != nullptr;
+    double t_match = 0, t_split = 0, t_fact = 0;
     while (S.n > prm.coarse_max && int(pend.size()) < prm.max_levels) {
+        double ta = now_s();
         MatchResult mr = max_product_matching(S);
+        double tb = now_s();
         auto blocks = split_cycles(S, mr.match, mr.logd);
+        double tc = now_s();
         std::vector<double> d(S.n);
         for (int i = 0; i < S.n; ++i) d[i] = std::exp(mr.logd[i]);
         Pending pl;
         Csr Snext;
         std::string err = factor_level(S, prm, d, blocks, pl.lv, Snext);
+        double td = now_s();
+        t_match += tb - ta; t_split += tc - tb; t_fact += td - tc;
+        if (verbose)
+            fprintf(stderr, "level %zu: n %d nnz %lld nB %zu 2x2 %d rej %d | match %.3fs split %.3fs factor %.3fs\n",
+                    pend.size(), S.n, (long long)S.col.size(), pl.lv.B.size(), pl.lv.n2x2, pl.lv.rejected,
+                    tb - ta, tc - tb, td - tc);
         if (!err.empty()) return err;
-        if (pl.lv.B.empty()) break;  // no acceptable pivot: the rest is the last level
+        // no acceptable pivot, or the level barely shrinks and the rest fits the
+        // exactly inverted last level: stop the recursion here
+        if (pl.lv.B.empty() || (int64_t(pl.lv.B.size()) * 100 < S.n && S.n <= 8192)) break;
         pl.cum.resize(S.n);
         for (int i = 0; i < S.n; ++i) pl.cum[i] = cum_prev[i] * d[i];
         pl.off = off;
@@ -656,6 +671,13 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
     }
     out.coarse_off = off;
     out.coarse_n = S.n;
+    out.pos_scale.assign(n, 1.0);
+    {
+        int p = 0;
+        for (auto &pl : pend)
+            for (int b : pl.lv.B) out.pos_scale[p++] = pl.cum[b];
+        for (int i = 0; i < S.n; ++i) out.pos_scale[p++] = cum_prev[i];
+    }
     // global position of each level-local unknown, computed from the last level back
     // gpos for the current (last) level: coarse positions
     std::vector<int> gpos(S.n);
@@ -741,8 +763,94 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
     }
     nnz_fact += (long long)out.coarse_n * (out.coarse_n + 1) / 2;
     out.fill = double(nnz_fact) / double(std::max<long long>(out.nnz_lower_A, 1));
+    if (verbose)
+        fprintf(stderr, "levels %zu coarse %d: match %.2fs split %.2fs factor %.2fs total %.2fs\n", out.levels.size(),
+                out.coarse_n, t_match, t_split, t_fact, now_s() - t0);
+    if (prm.inverse_factor) build_inverse_factor(out, prm.z_drop);
     out.seconds = now_s() - t0;
     return "";
+}
+
+// ---------------------------------------------------------------------------------
+// Explicit inverse factor.  Applying the levels one after the other needs one
+// dependent pass per level and direction; the product of those passes is itself a
+// unit lower triangular matrix Z = L^{-1}, which is formed here (with dropping in the
+// scaled domain) so that the device applies the whole preconditioner as
+// P^T Z^T D^{-1} Z P: two sparse products and a block-diagonal solve.
+// ---------------------------------------------------------------------------------
+void build_inverse_factor(Multilevel &ml, double z_drop)
+{
+    const double t0 = now_s();
+    const int n = ml.n;
+    const int nl = int(ml.levels.size());
+    InverseFactor &Z = ml.z;
+    std::vector<std::vector<std::pair<int, double>>> rows(n);
+    const std::vector<double> &sc = ml.pos_scale;
+#pragma omp parallel
+    {
+        std::vector<double> acc(n, 0.0);
+        std::vector<int> mark(n, -1), list;
+        for (int m = 0; m <= nl; ++m) {
+            const int r0 = (m < nl) ? ml.levels[m].off : ml.coarse_off;
+            const int r1 = (m < nl) ? ml.levels[m].off + ml.levels[m].nB : n;
+#pragma omp for schedule(dynamic, 256)
+            for (int r = r0; r < r1; ++r) {
+                list.clear();
+                auto put = [&](int c, double v) {
+                    if (mark[c] != r) { mark[c] = r; acc[c] = 0.0; list.push_back(c); }
+                    acc[c] += v;
+                };
+                put(r, 1.0);
+                for (int l = 0; l < m; ++l) {
+                    const Level &Lv = ml.levels[l];
+                    const int q = r - (Lv.off + Lv.nB);
+                    for (int64_t p = Lv.g_ptr[q]; p < Lv.g_ptr[q + 1]; ++p) {
+                        const double g = Lv.g_val[p];
+                        for (const auto &e : rows[Lv.g_col[p]]) put(e.first, -g * e.second);
+                    }
+                }
+                std::sort(list.begin(), list.end());
+                auto &out = rows[r];
+                for (int c : list) {
+                    const double v = acc[c];
+                    if (c == r || z_drop < 0 || std::fabs(v) * sc[r] / sc[c] >= z_drop) out.push_back({c, v});
+                }
+            }
+            // implicit barrier of the worksharing loop: level m is complete
+        }
+    }
+    Z.ptr.assign(n + 1, 0);
+    for (int r = 0; r < n; ++r) Z.ptr[r + 1] = Z.ptr[r] + int64_t(rows[r].size());
+    Z.col.resize(Z.ptr[n]);
+    Z.val.resize(Z.ptr[n]);
+    Z.tptr.assign(n + 1, 0);
+    for (int r = 0; r < n; ++r) {
+        int64_t p = Z.ptr[r];
+        for (auto &e : rows[r]) { Z.col[p] = e.first; Z.val[p] = e.second; ++p; ++Z.tptr[e.first + 1]; }
+        std::vector<std::pair<int, double>>().swap(rows[r]);
+    }
+    for (int r = 0; r < n; ++r) Z.tptr[r + 1] += Z.tptr[r];
+    Z.tcol.resize(Z.tptr[n]);
+    Z.tval.resize(Z.tptr[n]);
+    {
+        std::vector<int64_t> fp(Z.tptr.begin(), Z.tptr.end() - 1);
+        for (int r = 0; r < n; ++r)
+            for (int64_t p = Z.ptr[r]; p < Z.ptr[r + 1]; ++p) {
+                const int c = Z.col[p];
+                Z.tcol[fp[c]] = r;
+                Z.tval[fp[c]++] = Z.val[p];
+            }
+    }
+    Z.dd.assign(ml.coarse_off, 0.0);
+    Z.dof.assign(ml.coarse_off, 0.0);
+    Z.dp.assign(ml.coarse_off, 0);
+    for (const auto &Lv : ml.levels)
+        for (int t = 0; t < Lv.nB; ++t) {
+            Z.dd[Lv.off + t] = Lv.bd[t];
+            Z.dof[Lv.off + t] = Lv.bo[t];
+            Z.dp[Lv.off + t] = Lv.bp[t];
+        }
+    Z.seconds = now_s() - t0;
 }
 
 }  // namespace jdmi

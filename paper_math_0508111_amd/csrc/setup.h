@@ -43,6 +43,19 @@ struct SetupParams {
     double schur_tol = 1e-2;
     int coarse_max = 1536;
     int max_levels = 64;
+    double z_drop = 1e-2;     // relative drop tolerance of the explicit inverse factor (< 0: none)
+    bool inverse_factor = true;
+};
+
+// Explicit inverse of the unit lower triangular factor of all levels, Z ~ L^{-1}
+// (global positions), and the block diagonal D^{-1}: K^{-1} = P^T Z^T D^{-1} Z P.
+struct InverseFactor {
+    std::vector<int64_t> ptr, tptr;   // CSR of Z and of Z^T (n + 1 each)
+    std::vector<int> col, tcol;
+    std::vector<double> val, tval;
+    std::vector<double> dd, dof;      // D^{-1} for positions < coarse_off: dd w[j] + dof w[dp[j]]
+    std::vector<int> dp;
+    double seconds = 0.0;
 };
 
 // One level of the multilevel factorisation in global (permuted) positions, with
@@ -67,13 +80,19 @@ struct Level {
 struct Multilevel {
     int n = 0;
     std::vector<int> perm;        // perm[position] = original site index
+    std::vector<double> pos_scale;  // cumulative symmetric scaling of each position (pivots ~ +-1)
     std::vector<Level> levels;
     int coarse_off = 0, coarse_n = 0;
     std::vector<double> coarse_inv;  // coarse_n x coarse_n row-major, scalings folded in
     long long nnz_lower_A = 0;
     double fill = 0.0;
     double seconds = 0.0;
+    InverseFactor z;               // filled when SetupParams::inverse_factor
 };
+
+// Z = L^{-1} row by row (row r = e_r - sum over earlier levels of G[r, c] z_c), dropping
+// entries with |z_rc| s_r / s_c < z_drop (s = pos_scale), and its transpose.
+void build_inverse_factor(Multilevel &ml, double z_drop);
 
 // Build the multilevel factorisation of the symmetric matrix A.
 // Returns an empty string on success, else a message.

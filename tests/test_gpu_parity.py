@@ -64,12 +64,13 @@ def test_stencil_parity(L, shift):
 
 # --- multilevel preconditioner -------------------------------------------------------------
 
-@pytest.mark.parametrize("L,cmax,sigma", [(4, 8, 0.0), (6, 16, 0.0), (8, 40, 0.37), (10, 60, -0.2)])
-def test_precond_exact_without_dropping(L, cmax, sigma):
+@pytest.mark.parametrize("L,cmax,sigma,flags", [(4, 8, 0.0, 0), (6, 16, 0.0, 0), (8, 40, 0.37, 0), (10, 60, -0.2, 0),
+                                               (6, 16, 0.0, jd.JD_FLAG_LEVELS), (10, 60, -0.2, jd.JD_FLAG_LEVELS)])
+def test_precond_exact_without_dropping(L, cmax, sigma, flags):
     # nothing dropped and every pivot accepted: the multilevel factorisation is exact,
-    # so K^{-1} (A - sigma I) x = x
+    # so K^{-1} (A - sigma I) x = x, both through the explicit inverse factor and level by level
     W, seed = 16.5, 2
-    P = jd.Precond(L, W, seed, sigma, drop_tol=-1.0, coarse_max=cmax)
+    P = jd.Precond(L, W, seed, sigma, drop_tol=-1.0, coarse_max=cmax, flags=flags)
     lv = P.levels()
     assert lv["levels"] >= 1
     eps = generator.disorder(L, W, seed)
@@ -80,6 +81,25 @@ def test_precond_exact_without_dropping(L, cmax, sigma):
     torch.cuda.synchronize()
     assert np.linalg.norm(y.cpu().numpy() - x) <= 1e-9 * np.linalg.norm(x)
     P.close()
+
+
+@pytest.mark.parametrize("L", [16, 24])
+def test_inverse_factor_matches_level_by_level(L):
+    # with nothing dropped from Z, P^T Z^T D^{-1} Z P is the level-by-level apply of the
+    # same (incomplete) factorisation
+    n = L ** 3
+    Pz = jd.Precond(L, 16.5, 0, 0.0, z_drop=-1.0)
+    Pl = jd.Precond(L, 16.5, 0, 0.0, flags=jd.JD_FLAG_LEVELS)
+    assert Pz.levels() == Pl.levels()
+    b = seeded_inputs.vector(n, 4)
+    yz = torch.empty(n, dtype=torch.float64, device="cuda")
+    yl = torch.empty(n, dtype=torch.float64, device="cuda")
+    Pz.apply(dev(b), yz, stream=stream())
+    Pl.apply(dev(b), yl, stream=stream())
+    torch.cuda.synchronize()
+    assert torch.linalg.norm(yz - yl).item() <= 1e-10 * torch.linalg.norm(yl).item()
+    Pz.close()
+    Pl.close()
 
 
 @pytest.mark.parametrize("L", [16, 30])
