@@ -35,9 +35,9 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_roofline(jd, torch, L, W, seed, prob_info, reps=50):
-    """Achieved HBM bandwidth of the binary32 stencil product, timed with events on
-    the stream it is launched on; algorithmic bytes 3 n 4 (x, eps read, y written)."""
+def stencil_bandwidth(jd, torch, L, W, seed, reps=50):
+    """Achieved bandwidth of the binary32 stencil product (secondary kernel), timed with
+    events on its stream; algorithmic bytes 3 n 4 (x and eps read, y written)."""
     n = L ** 3
     s = torch.cuda.current_stream()
     eps64 = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -57,11 +57,37 @@ def kernel_roofline(jd, torch, L, W, seed, prob_info, reps=50):
     e1.record(s)
     torch.cuda.synchronize()
     us = e0.elapsed_time(e1) * 1e3 / reps
-    bytes_ = 3 * n * 4
-    achieved = bytes_ / (us * 1e-6) / 1e9
-    return {"kernel": "k_stencil<float>", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+    b = 3 * n * 4
+    return {"kernel": "k_stencil<float>", "bytes_per_launch": b, "avg_us": round(us, 2),
+            "achieved_GBs": round(b / (us * 1e-6) / 1e9, 1)}
+
+
+def factor_roofline(torch, prob, n, reps=40):
+    """Roofline of the dominant kernel, the binary32 product with the explicit inverse
+    factor Z (k_zspmv<float>; two launches per preconditioner apply, Z and Z^T).
+    Algorithmic bytes per launch: nnz (4 value + 4 index) + (n + 1) 8 row pointers +
+    n 4 input + n 4 output (+ n 4 output permutation for Z^T), averaged over the two."""
+    pc = prob.precond()
+    nnz = pc.factor_nnz()
+    s = torch.cuda.current_stream()
+    x = torch.randn(n, dtype=torch.float32, device="cuda")
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    for t in (0, 1):
+        pc.factor_product(x, y, transpose=t, stream=s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for r in range(reps):
+        pc.factor_product(x, y, transpose=r % 2, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    b = nnz * 8 + (n + 1) * 8 + n * 8 + n * 2  # the n*4 permutation read of every other launch
+    achieved = b / (us * 1e-6) / 1e9
+    pc.close()
+    return {"kernel": "k_zspmv<float>", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "bytes_per_launch": bytes_, "avg_us": round(us, 2), "reps": reps}
+            "bytes_per_launch": int(b), "nnz": int(nnz), "avg_us": round(us, 2), "reps": reps}
 
 
 def cpu_baseline(k):
@@ -134,14 +160,21 @@ def main():
         "evals": [float(v) for v in ev],
     }
     if not a.no_fp64:
-        prob.set_precision("fp64")  # same setup, binary64 throughout
-        ev64, _, res64, i64 = prob.solve(k, tol)
-        out["fp64"] = {"value": round(i64["n_converged"] / i64["solve_s"], 4), "solve_s": round(i64["solve_s"], 3),
-                       "outer_its": i64["outer_its"], "inner_its": i64["inner_its"],
-                       "max_abs_eval_diff_vs_mixed": float(np.max(np.abs(ev64 - ev)))}
-        print(f"# fp64 solve {i64['solve_s']:.3f} s", file=sys.stderr, flush=True)
+        # the same setup, other precision splits: binary64 throughout, and binary32
+        # preconditioner factors with binary64 vectors
+        for name in ("fp64", "mixed_factors"):
+            prob.set_precision(name)
+            e2, _, r2, i2 = prob.solve(k, tol)
+            out[name] = {"value": round(i2["n_converged"] / i2["solve_s"], 4), "solve_s": round(i2["solve_s"], 3),
+                         "outer_its": i2["outer_its"], "inner_its": i2["inner_its"],
+                         "converged": i2["n_converged"],
+                         "max_abs_eval_diff_vs_mixed": float(np.nanmax(np.abs(e2 - ev)))}
+            print(f"# {name} solve {i2['solve_s']:.3f} s, outer {i2['outer_its']}, inner {i2['inner_its']}",
+                  file=sys.stderr, flush=True)
+    prob.set_precision("mixed")
+    out["roofline"] = factor_roofline(torch, prob, L ** 3)
+    out["stencil"] = stencil_bandwidth(jd, torch, L, W, seed)
     prob.close()
-    out["roofline"] = kernel_roofline(jd, torch, L, W, seed, pinfo)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(k)
     print(json.dumps(out), flush=True)

@@ -46,14 +46,16 @@ enum {
     JD_ENOTIMPL = -5   /* option combination not provided */
 };
 
-enum { JD_FP64 = 0, JD_MIXED = 1 };
+enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
 
 /*
  * Options; a zero-initialised struct selects every default.
  *  precision  JD_FP64: every step in binary64.  JD_MIXED: stencil SpMV,
  *             preconditioner factors and the inner SQMR iteration in binary32
  *             (binary32 accumulation); Gram-Schmidt, Rayleigh-Ritz, residual
- *             norms and acceptance in binary64.
+ *             norms and acceptance in binary64.  JD_MIXED_FACTORS: only the
+ *             preconditioner factors (and their application) in binary32; stencil
+ *             product and SQMR vectors in binary64.
  *  drop_tol   epsilon of section 7.2: an entry of a factor column is dropped when
  *             its modulus is below drop_tol / kappa (0 -> 1/sqrt(n), the paper's
  *             choice in section 8.2; < 0 -> nothing dropped, exact factorisation).
@@ -180,7 +182,18 @@ int jd_precond_apply(jd_precond *p, int precision, const void *d_in, void *d_out
  * coarse size; nB[l] = pivots accepted at level l; nnzG[l] = stored coupling entries.
  * Arrays of length cap (host); returns the number of levels. */
 int jd_precond_levels(const jd_precond *p, int cap, int *sizes, int *nB, long long *nnzG);
+/* Release a preconditioner (a view obtained from jd_problem_precond leaves the
+ * problem's factors alone). */
 void jd_precond_free(jd_precond *p);
+/* A view of the preconditioner held by a problem (valid while the problem lives;
+ * release the view with jd_precond_free). */
+int jd_problem_precond(jd_problem *p, jd_precond **out);
+/* Number of stored entries of the explicit inverse factor Z (and n). */
+int jd_precond_factor_nnz(const jd_precond *p, long long *nnz, int *n);
+/* The dominant kernel of the apply on its own: y = Z x (transpose = 0, positions order)
+ * or y[perm[r]] = (Z^T x)[r] (transpose = 1).  Device vectors of length n. */
+int jd_precond_factor_product(jd_precond *p, int precision, int transpose, const void *d_x, void *d_y,
+                              void *stream);
 
 /*
  * jd_problem_linear_solve -- the inner iteration on its own: simplified QMR with

@@ -16,10 +16,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libjdmi.so")
 
 JD_OK, JD_ENOCONV, JD_EINVAL, JD_ENOMEM, JD_EDEVICE, JD_ESETUP, JD_ENOTIMPL = 0, 1, -1, -2, -3, -4, -5
-JD_FP64, JD_MIXED = 0, 1
+JD_FP64, JD_MIXED, JD_MIXED_FACTORS = 0, 1, 2
 JD_FLAG_EAGER = 1
 JD_FLAG_LEVELS = 2
-_PREC = {"fp64": JD_FP64, "mixed": JD_MIXED, JD_FP64: JD_FP64, JD_MIXED: JD_MIXED}
+_PREC = {"fp64": JD_FP64, "mixed": JD_MIXED, "mixed_factors": JD_MIXED_FACTORS, JD_FP64: JD_FP64,
+         JD_MIXED: JD_MIXED, JD_MIXED_FACTORS: JD_MIXED_FACTORS}
 
 
 class JdError(RuntimeError):
@@ -47,7 +48,8 @@ class Info(ctypes.Structure):
 
 
 EXPORTS = ["jd_solve", "jd_setup", "jd_problem_solve", "jd_problem_info", "jd_problem_set_precision", "jd_problem_free", "jd_gen_diag",
-           "jd_stencil_spmv", "jd_precond_create", "jd_precond_apply", "jd_precond_levels", "jd_precond_free",
+           "jd_stencil_spmv", "jd_precond_create", "jd_precond_apply", "jd_precond_levels", "jd_precond_free", "jd_problem_precond", "jd_precond_factor_nnz",
+           "jd_precond_factor_product",
            "jd_problem_linear_solve", "jd_last_error", "jd_version"]
 
 _lib = None
@@ -76,6 +78,9 @@ def lib():
         "jd_precond_apply": (I, [P, I, P, P, P]),
         "jd_precond_levels": (I, [P, I, P, P, P]),
         "jd_precond_free": (None, [P]),
+        "jd_problem_precond": (I, [P, ctypes.POINTER(P)]),
+        "jd_precond_factor_nnz": (I, [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I)]),
+        "jd_precond_factor_product": (I, [P, I, I, P, P, P]),
         "jd_problem_linear_solve": (I, [P, D, P, I, P, P, D, I, ctypes.POINTER(I)]),
         "jd_last_error": (ctypes.c_char_p, []),
         "jd_version": (ctypes.c_char_p, []),
@@ -148,6 +153,12 @@ class Problem:
     def set_precision(self, precision):
         _check(lib().jd_problem_set_precision(self._h, _PREC[precision]))
 
+    def precond(self):
+        """A view of the problem's preconditioner (keep the problem alive while using it)."""
+        h = ctypes.c_void_p()
+        _check(lib().jd_problem_precond(self._h, ctypes.byref(h)))
+        return Precond(self.L, 0.0, 0, 0.0, _handle=h)
+
     def info(self):
         i = Info()
         _check(lib().jd_problem_info(self._h, ctypes.byref(i)))
@@ -188,12 +199,24 @@ class Problem:
 class Precond:
     """jd_precond_create / jd_precond_apply: the multilevel ILDL^T preconditioner alone."""
 
-    def __init__(self, L, W, seed, sigma, **opts):
+    def __init__(self, L, W, seed, sigma, _handle=None, **opts):
         self.L, self.n = L, L ** 3
+        if _handle is not None:
+            self._h = _handle
+            return
         self._opts = make_options("fp64", **opts)
         h = ctypes.c_void_p()
         _check(lib().jd_precond_create(L, float(W), seed, float(sigma), ctypes.byref(self._opts), ctypes.byref(h)))
         self._h = h
+
+    def factor_nnz(self):
+        nnz = ctypes.c_longlong()
+        _check(lib().jd_precond_factor_nnz(self._h, ctypes.byref(nnz), None))
+        return nnz.value
+
+    def factor_product(self, x, y, transpose=False, precision="mixed", stream=None):
+        _check(lib().jd_precond_factor_product(self._h, _PREC[precision], int(transpose), _ptr(x), _ptr(y),
+                                               _stream_ptr(stream)))
 
     def apply(self, x, y, precision="fp64", stream=None):
         _check(lib().jd_precond_apply(self._h, _PREC[precision], _ptr(x), _ptr(y), _stream_ptr(stream)))

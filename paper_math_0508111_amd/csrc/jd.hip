@@ -19,6 +19,7 @@
 #include <memory>
 #include <numeric>
 #include <stdexcept>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -85,6 +86,79 @@ std::vector<To> cast_vec(const std::vector<double> &v)
     return std::vector<To>(v.begin(), v.end());
 }
 
+// CSR -> sliced ELL: rows ordered by decreasing length (stable), 64 rows per slice,
+// slice j-th entries of its 64 rows stored contiguously; padding has value 0, index 0.
+struct SellHost {
+    std::vector<int64_t> slice_ptr;
+    std::vector<int> rowidx, col;
+    std::vector<double> val;
+};
+struct HybHost {
+    std::vector<int> long_row;
+    std::vector<int64_t> long_ptr;
+    std::vector<int> long_col;
+    std::vector<double> long_val;
+    SellHost sell;
+};
+constexpr int64_t kLongRow = 96;  // rows with more entries than this are reduced by a whole wave
+
+SellHost to_sell(int n, const std::vector<int64_t> &ptr, const std::vector<int> &col, const std::vector<double> &val,
+                 std::vector<int> *only_rows = nullptr)
+{
+    SellHost h;
+    std::vector<int> order;
+    if (only_rows) order = *only_rows;
+    else { order.resize(n); std::iota(order.begin(), order.end(), 0); }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b]; });
+    n = int(order.size());
+    const int ns = (n + 63) / 64;
+    h.slice_ptr.assign(ns + 1, 0);
+    h.rowidx.assign(size_t(ns) * 64, -1);
+    for (int sl = 0; sl < ns; ++sl) {
+        int64_t w = 0;
+        for (int l = 0; l < 64 && sl * 64 + l < n; ++l) {
+            const int r = order[sl * 64 + l];
+            h.rowidx[size_t(sl) * 64 + l] = r;
+            w = std::max(w, ptr[r + 1] - ptr[r]);
+        }
+        h.slice_ptr[sl + 1] = h.slice_ptr[sl] + w * 64;
+    }
+    h.col.assign(h.slice_ptr[ns], 0);
+    h.val.assign(h.slice_ptr[ns], 0.0);
+    for (int sl = 0; sl < ns; ++sl)
+        for (int l = 0; l < 64 && sl * 64 + l < n; ++l) {
+            const int r = order[sl * 64 + l];
+            int64_t j = 0;
+            for (int64_t p = ptr[r]; p < ptr[r + 1]; ++p, ++j) {
+                h.col[h.slice_ptr[sl] + j * 64 + l] = col[p];
+                h.val[h.slice_ptr[sl] + j * 64 + l] = val[p];
+            }
+        }
+    return h;
+}
+
+HybHost to_hyb(int n, const std::vector<int64_t> &ptr, const std::vector<int> &col, const std::vector<double> &val)
+{
+    HybHost h;
+    std::vector<int> shortr;
+    for (int r = 0; r < n; ++r) {
+        if (ptr[r + 1] - ptr[r] > kLongRow) h.long_row.push_back(r);
+        else shortr.push_back(r);
+    }
+    std::stable_sort(h.long_row.begin(), h.long_row.end(),
+                     [&](int a, int b) { return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b]; });
+    h.long_ptr.assign(h.long_row.size() + 1, 0);
+    for (size_t i = 0; i < h.long_row.size(); ++i) {
+        const int r = h.long_row[i];
+        h.long_ptr[i + 1] = h.long_ptr[i] + (ptr[r + 1] - ptr[r]);
+        h.long_col.insert(h.long_col.end(), col.begin() + ptr[r], col.begin() + ptr[r + 1]);
+        h.long_val.insert(h.long_val.end(), val.begin() + ptr[r], val.begin() + ptr[r + 1]);
+    }
+    h.sell = to_sell(n, ptr, col, val, &shortr);
+    return h;
+}
+
 // The multilevel factors on the device in one precision.
 template <typename T>
 struct DevPrecond {
@@ -99,8 +173,34 @@ struct DevPrecond {
     const int64_t *zptr = nullptr, *ztptr = nullptr;
     const int *zcol = nullptr, *ztcol = nullptr, *dp = nullptr;
     const T *zval = nullptr, *ztval = nullptr, *dd = nullptr, *dof = nullptr;
+    jdmi::Sell<T> zs, zts;  // the same two factors in sliced-ELL layout
+    jdmi::Hyb<T> zh, zth;   // hybrid layout (long rows per wave + sliced ELL)
 
-    void upload(const jdmi::Multilevel &ml, const int *dperm, DevMem &mem, hipStream_t s)
+    static jdmi::Hyb<T> upload_hyb(const HybHost &h, DevMem &mem, hipStream_t s)
+    {
+        jdmi::Hyb<T> d;
+        d.nlong = int(h.long_row.size());
+        d.long_row = mem.upload(h.long_row, s);
+        d.long_ptr = mem.upload(h.long_ptr, s);
+        d.long_col = mem.upload(h.long_col, s);
+        d.long_val = mem.upload(cast_vec<T>(h.long_val), s);
+        d.sell = upload_sell(h.sell, mem, s);
+        return d;
+    }
+
+    static jdmi::Sell<T> upload_sell(const SellHost &h, DevMem &mem, hipStream_t s)
+    {
+        jdmi::Sell<T> d;
+        d.nslices = int(h.slice_ptr.size()) - 1;
+        d.slice_ptr = mem.upload(h.slice_ptr, s);
+        d.rowidx = mem.upload(h.rowidx, s);
+        d.col = mem.upload(h.col, s);
+        d.val = mem.upload(cast_vec<T>(h.val), s);
+        return d;
+    }
+
+    void upload(const jdmi::Multilevel &ml, const int *dperm, DevMem &mem, hipStream_t s,
+                const HybHost *zsh = nullptr, const HybHost *ztsh = nullptr)
     {
         n = ml.n;
         perm = const_cast<int *>(dperm);
@@ -128,15 +228,11 @@ struct DevPrecond {
         x = mem.alloc<T>(n);
         inv = !ml.z.ptr.empty();
         if (inv) {
-            zptr = mem.upload(ml.z.ptr, s);
-            zcol = mem.upload(ml.z.col, s);
-            zval = mem.upload(cast_vec<T>(ml.z.val), s);
-            ztptr = mem.upload(ml.z.tptr, s);
-            ztcol = mem.upload(ml.z.tcol, s);
-            ztval = mem.upload(cast_vec<T>(ml.z.tval), s);
             dd = mem.upload(cast_vec<T>(ml.z.dd), s);
             dof = mem.upload(cast_vec<T>(ml.z.dof), s);
             dp = mem.upload(ml.z.dp, s);
+            zh = upload_hyb(*zsh, mem, s);
+            zth = upload_hyb(*ztsh, mem, s);
         }
         // keep the converted host vectors alive until the copies are done
         HIPCHK(hipStreamSynchronize(s));
@@ -149,10 +245,10 @@ struct DevPrecond {
             // P^T Z^T D^{-1} Z P in: gather, sparse product, block diagonal (+ exact last
             // level), transposed sparse product with the inverse permutation on output
             jdmi::launch_gather<T>(n, perm, in, w, s, skip);
-            jdmi::launch_zspmv<T>(n, zptr, zcol, zval, w, x, nullptr, s, skip);
+            jdmi::launch_hyb_spmv<T, T>(zh, w, x, nullptr, s, skip);
             jdmi::launch_dinv<T>(coarse_off, dd, dof, dp, x, w, s, skip);
             jdmi::launch_coarse<T>(coarse_n, coarse_off, cinv, x, w, s, skip);
-            jdmi::launch_zspmv<T>(n, ztptr, ztcol, ztval, w, out, perm, s, skip);
+            jdmi::launch_hyb_spmv<T, T>(zth, w, out, perm, s, skip);
             return;
         }
         jdmi::launch_gather<T>(n, perm, in, w, s, skip);
@@ -160,6 +256,24 @@ struct DevPrecond {
         jdmi::launch_coarse<T>(coarse_n, coarse_off, cinv, w, x, s, skip);
         for (int l = int(levels.size()) - 1; l >= 0; --l) jdmi::launch_up<T>(levels[l], w, x, s, skip);
         jdmi::launch_scatter<T>(n, perm, x, out, s, skip);
+    }
+};
+
+// binary32 factors applied to binary64 vectors: converted on the way in (fused into
+// the gather) and on the way out (fused into the last sparse product)
+// (stored factors rounded to binary32, products accumulated in binary64, so the
+// operator stays symmetric to binary64 accuracy)
+struct MixedPrecond {
+    const DevPrecond<float> &pc;   // binary32 inverse factor
+    const DevPrecond<double> &pd;  // binary64 block diagonal, last level and workspaces
+    void apply(const double *in, double *out, hipStream_t s, const int *skip = nullptr) const
+    {
+        if (!pc.inv) throw JdError(JD_ENOTIMPL, "binary32 factors with binary64 vectors need the inverse factor form");
+        jdmi::launch_gather_cvt<double, double>(pd.n, pd.perm, in, pd.w, s, skip);
+        jdmi::launch_hyb_spmv<float, double>(pc.zh, pd.w, pd.x, nullptr, s, skip);
+        jdmi::launch_dinv<double>(pd.coarse_off, pd.dd, pd.dof, pd.dp, pd.x, pd.w, s, skip);
+        jdmi::launch_coarse<double>(pd.coarse_n, pd.coarse_off, pd.cinv, pd.x, pd.w, s, skip);
+        jdmi::launch_hyb_spmv<float, double>(pc.zth, pd.w, out, pd.perm, s, skip);
     }
 };
 
@@ -200,7 +314,8 @@ void check_problem_args(int L, double W, double sigma, const jd_options *opt)
     if (!(W >= 0) || !std::isfinite(W)) throw JdError(JD_EINVAL, "W must be finite and >= 0");
     if (!std::isfinite(sigma)) throw JdError(JD_EINVAL, "sigma must be finite");
     if (opt) {
-        if (opt->precision != JD_FP64 && opt->precision != JD_MIXED) throw JdError(JD_EINVAL, "unknown precision");
+        if (opt->precision != JD_FP64 && opt->precision != JD_MIXED && opt->precision != JD_MIXED_FACTORS)
+            throw JdError(JD_EINVAL, "unknown precision");
         if (opt->coarse_max < 0 || opt->coarse_max > 8192) throw JdError(JD_EINVAL, "coarse_max must be in [0, 8192]");
         if (opt->jmin < 0 || opt->jmax < 0 || opt->jmax > 120) throw JdError(JD_EINVAL, "jmin/jmax out of range");
         if (opt->max_inner < 0 || opt->max_outer < 0 || opt->max_levels < 0) throw JdError(JD_EINVAL, "negative iteration cap");
@@ -257,8 +372,13 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
     S.n2x2 = 0;
     for (auto &lv : S.ml.levels) S.n2x2 += lv.n2x2;
     int *dperm = S.mem.upload(S.ml.perm, S.stream);
-    S.pc64.upload(S.ml, dperm, S.mem, S.stream);
-    S.pc32.upload(S.ml, dperm, S.mem, S.stream);
+    HybHost zsh, ztsh;
+    if (!S.ml.z.ptr.empty()) {
+        zsh = to_hyb(S.n, S.ml.z.ptr, S.ml.z.col, S.ml.z.val);
+        ztsh = to_hyb(S.n, S.ml.z.tptr, S.ml.z.tcol, S.ml.z.tval);
+    }
+    S.pc64.upload(S.ml, dperm, S.mem, S.stream, &zsh, &ztsh);
+    S.pc32.upload(S.ml, dperm, S.mem, S.stream, &zsh, &ztsh);
     HIPCHK(hipStreamSynchronize(S.stream));
     S.setup_s = now_s() - t0;
 }
@@ -348,10 +468,10 @@ struct SqmrBufs {
 // projection width p into a HIP graph and replayed; every scalar (alpha, theta, c,
 // tau, beta, the shift and the stop flag) lives in device memory, and the host reads
 // only the stop flag, one step behind the device.
-template <typename T>
+template <typename T, typename P>
 struct Solver {
     Setup &S;
-    const DevPrecond<T> &pc;
+    const P &pc;
     const T *eps;
     hipStream_t s;
     int n;
@@ -362,7 +482,7 @@ struct Solver {
     struct Pair { hipGraphExec_t init = nullptr, step = nullptr; const T *Qt = nullptr, *Y = nullptr; const double *M = nullptr; };
     std::vector<Pair> cache;
 
-    Solver(Setup &S_, const DevPrecond<T> &pc_, const T *eps_, bool graphs_)
+    Solver(Setup &S_, const P &pc_, const T *eps_, bool graphs_)
         : S(S_), pc(pc_), eps(eps_), s(S_.stream), n(S_.n), graphs(graphs_)
     {
         B.r = mem.alloc<T>(n);
@@ -500,8 +620,8 @@ struct Outputs {
     void *evecs_device;
 };
 
-template <typename T>
-int jd_run(Setup &S, const DevPrecond<T> &pc, const T *eps, int k, double tol, Outputs out, jd_info *info)
+template <typename T, typename P>
+int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, jd_info *info)
 {
     const double t0 = now_s();
     const int n = S.n;
@@ -514,7 +634,7 @@ int jd_run(Setup &S, const DevPrecond<T> &pc, const T *eps, int k, double tol, O
     const double anorm = S.anorm;
     const double sigma = S.sigma;
 
-    Solver<T> sv(S, pc, eps, (o.flags & JD_FLAG_EAGER) == 0);
+    Solver<T, P> sv(S, pc, eps, (o.flags & JD_FLAG_EAGER) == 0);
     DevMem mem;
     double *V = mem.alloc<double>(size_t(n) * jmax);
     double *AV = mem.alloc<double>(size_t(n) * jmax);
@@ -803,7 +923,8 @@ struct jd_problem {
     Setup S;
 };
 struct jd_precond {
-    Setup S;
+    std::unique_ptr<Setup> own;  // null for a view of a problem's preconditioner
+    Setup *S = nullptr;
 };
 
 extern "C" {
@@ -837,7 +958,8 @@ int jd_problem_set_precision(jd_problem *p, int precision)
 {
     return guarded([&] {
         if (!p) throw JdError(JD_EINVAL, "NULL problem");
-        if (precision != JD_FP64 && precision != JD_MIXED) throw JdError(JD_EINVAL, "unknown precision");
+        if (precision != JD_FP64 && precision != JD_MIXED && precision != JD_MIXED_FACTORS)
+            throw JdError(JD_EINVAL, "unknown precision");
         p->S.opt.precision = precision;
         return JD_OK;
     });
@@ -867,6 +989,10 @@ int jd_problem_solve(jd_problem *p, int k, double tol, double *evals, double *ev
         check_solve_args(p->S.n, k, tol, evals);
         Outputs o{evals, evecs_host, resid, evecs_device};
         if (p->S.opt.precision == JD_MIXED) return jd_run<float>(p->S, p->S.pc32, p->S.eps32, k, tol, o, info);
+        if (p->S.opt.precision == JD_MIXED_FACTORS) {
+            MixedPrecond mp{p->S.pc32, p->S.pc64};
+            return jd_run<double>(p->S, mp, p->S.eps64, k, tol, o, info);
+        }
         return jd_run<double>(p->S, p->S.pc64, p->S.eps64, k, tol, o, info);
     });
 }
@@ -927,7 +1053,9 @@ int jd_precond_create(int L, double W, uint64_t seed, double sigma, const jd_opt
         if (!out) throw JdError(JD_EINVAL, "out must not be NULL");
         *out = nullptr;
         auto p = std::make_unique<jd_precond>();
-        build_setup(p->S, L, W, seed, sigma, opt);
+        p->own = std::make_unique<Setup>();
+        p->S = p->own.get();
+        build_setup(*p->S, L, W, seed, sigma, opt);
         *out = p.release();
         return JD_OK;
     });
@@ -940,9 +1068,9 @@ int jd_precond_apply(jd_precond *p, int precision, const void *d_in, void *d_out
         if (d_in == d_out) throw JdError(JD_EINVAL, "in and out must not overlap");
         hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the legacy default stream
         if (precision == JD_FP64)
-            p->S.pc64.apply(static_cast<const double *>(d_in), static_cast<double *>(d_out), s);
+            p->S->pc64.apply(static_cast<const double *>(d_in), static_cast<double *>(d_out), s);
         else if (precision == JD_MIXED)
-            p->S.pc32.apply(static_cast<const float *>(d_in), static_cast<float *>(d_out), s);
+            p->S->pc32.apply(static_cast<const float *>(d_in), static_cast<float *>(d_out), s);
         else
             throw JdError(JD_EINVAL, "unknown precision");
         HIPCHK(hipGetLastError());
@@ -953,7 +1081,7 @@ int jd_precond_apply(jd_precond *p, int precision, const void *d_in, void *d_out
 int jd_precond_levels(const jd_precond *p, int cap, int *sizes, int *nB, long long *nnzG)
 {
     if (!p) { g_err = "NULL precond"; return JD_EINVAL; }
-    const auto &ml = p->S.ml;
+    const auto &ml = p->S->ml;
     const int nl = int(ml.levels.size());
     for (int l = 0; l <= nl && l < cap; ++l) {
         if (sizes) sizes[l] = (l < nl) ? ml.levels[l].nB + ml.levels[l].n_after : ml.coarse_n;
@@ -966,11 +1094,53 @@ int jd_precond_levels(const jd_precond *p, int cap, int *sizes, int *nB, long lo
 void jd_precond_free(jd_precond *p)
 {
     if (!p) return;
-    const bool own = p->S.own_stream;
-    hipStream_t s = p->S.stream;
-    p->S.mem.release();
-    delete p;
-    if (own) (void)hipStreamDestroy(s);
+    if (p->own) {
+        const bool own = p->S->own_stream;
+        hipStream_t s = p->S->stream;
+        p->S->mem.release();
+        delete p;
+        if (own) (void)hipStreamDestroy(s);
+    } else {
+        delete p;
+    }
+}
+
+int jd_problem_precond(jd_problem *p, jd_precond **out)
+{
+    return guarded([&] {
+        if (!p || !out) throw JdError(JD_EINVAL, "NULL argument");
+        auto v = std::make_unique<jd_precond>();
+        v->S = &p->S;
+        *out = v.release();
+        return JD_OK;
+    });
+}
+
+int jd_precond_factor_nnz(const jd_precond *p, long long *nnz, int *n)
+{
+    if (!p || !nnz) { g_err = "NULL argument"; return JD_EINVAL; }
+    *nnz = (long long)p->S->ml.z.col.size();
+    if (n) *n = p->S->n;
+    return JD_OK;
+}
+
+int jd_precond_factor_product(jd_precond *p, int precision, int transpose, const void *d_x, void *d_y, void *stream)
+{
+    return guarded([&] {
+        if (!p || !d_x || !d_y) throw JdError(JD_EINVAL, "NULL argument");
+        if (d_x == d_y) throw JdError(JD_EINVAL, "x and y must not overlap");
+        if (p->S->ml.z.ptr.empty()) throw JdError(JD_EINVAL, "the factorisation has no explicit inverse factor");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        auto go = [&](const auto &pc, auto *x, auto *y) {
+            if (transpose) jdmi::launch_hyb_spmv(pc.zth, x, y, pc.perm, s, nullptr);
+            else jdmi::launch_hyb_spmv(pc.zh, x, y, static_cast<const int *>(nullptr), s, nullptr);
+        };
+        if (precision == JD_FP64) go(p->S->pc64, static_cast<const double *>(d_x), static_cast<double *>(d_y));
+        else if (precision == JD_MIXED) go(p->S->pc32, static_cast<const float *>(d_x), static_cast<float *>(d_y));
+        else throw JdError(JD_EINVAL, "unknown precision");
+        HIPCHK(hipGetLastError());
+        return JD_OK;
+    });
 }
 
 int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int pcols, const double *d_b, double *d_x,
@@ -986,7 +1156,8 @@ int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int 
         hipStream_t s = S.stream;
         auto run = [&](auto tag, const auto &pc, const auto *eps) {
             using T = decltype(tag);
-            Solver<T> sv(S, pc, eps, (S.opt.flags & JD_FLAG_EAGER) == 0);
+            using PC = std::decay_t<decltype(pc)>;
+            Solver<T, PC> sv(S, pc, eps, (S.opt.flags & JD_FLAG_EAGER) == 0);
             DevMem mem;
             const int pc_ = pcols;
             T *Qt = mem.alloc<T>(size_t(n) * std::max(pc_, 1));
@@ -1019,6 +1190,7 @@ int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int 
             if (its) *its = k_;
         };
         if (S.opt.precision == JD_MIXED) run(float(0), S.pc32, S.eps32);
+        else if (S.opt.precision == JD_MIXED_FACTORS) run(double(0), MixedPrecond{S.pc32, S.pc64}, S.eps64);
         else run(double(0), S.pc64, S.eps64);
         return JD_OK;
     });

@@ -49,6 +49,38 @@ void launch_coarse(int nc, int off, const T *cinv, const T *w, T *x, hipStream_t
 template <typename T>
 void launch_zspmv(int n, const int64_t *ptr, const int *col, const T *val, const T *w, T *y, const int *out_perm,
                   hipStream_t s, const int *skip);
+// The same product in a sliced-ELL layout (rows sorted by length, 64 rows per slice,
+// each slice stored column-major): one wave per slice, one row per lane, every value
+// and index load a contiguous 256-byte segment.
+template <typename T>
+struct Sell {
+    int nslices = 0;
+    const int64_t *slice_ptr = nullptr;  // nslices + 1, in entries (multiples of 64)
+    const int *rowidx = nullptr;         // nslices * 64, -1 for padding lanes
+    const int *col = nullptr;
+    const T *val = nullptr;
+};
+template <typename T, typename To = T>
+void launch_sell_spmv(const Sell<T> &A, const T *x, To *y, const int *out_perm, hipStream_t s, const int *skip);
+
+// Hybrid layout for skewed row lengths: rows longer than a threshold are kept in CSR
+// and reduced by a whole wave each (longest first); the rest form sliced-ELL slices.
+// Values are stored in Tv, vectors and accumulation are in Tx.
+template <typename Tv>
+struct Hyb {
+    int nlong = 0;
+    const int *long_row = nullptr;     // original row of each long row
+    const int64_t *long_ptr = nullptr; // nlong + 1
+    const int *long_col = nullptr;
+    const Tv *long_val = nullptr;
+    Sell<Tv> sell;
+};
+template <typename Tv, typename Tx>
+void launch_hyb_spmv(const Hyb<Tv> &A, const Tx *x, Tx *y, const int *out_perm, hipStream_t s, const int *skip);
+// w[p] = Tout(b[perm[p]])
+template <typename Tin, typename Tout>
+void launch_gather_cvt(int n, const int *perm, const Tin *b, Tout *w, hipStream_t s, const int *skip);
+
 // z[j] = dd[j] y[j] + dof[j] y[dp[j]] for j < m
 template <typename T>
 void launch_dinv(int m, const T *dd, const T *dof, const int *dp, const T *y, T *z, hipStream_t s, const int *skip);

@@ -273,6 +273,123 @@ void launch_zspmv(int n, const int64_t *ptr, const int *col, const T *val, const
                        out_perm, skip);
 }
 
+template <typename T, typename To>
+__global__ void __launch_bounds__(kBlock) k_sell_spmv(int nslices, const int64_t *__restrict__ slice_ptr,
+                                                      const int *__restrict__ rowidx, const int *__restrict__ col,
+                                                      const T *__restrict__ val, const T *__restrict__ x,
+                                                      To *__restrict__ y, const int *__restrict__ out_perm,
+                                                      const int *skip)
+{
+    if (skip && *skip) return;
+    const int slice = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (slice >= nslices) return;
+    const int64_t b = slice_ptr[slice];
+    const int w = int((slice_ptr[slice + 1] - b) >> 6);
+    const int *c = col + b + lane;
+    const T *v = val + b + lane;
+    T a0 = T(0), a1 = T(0);
+    int j = 0;
+    for (; j + 1 < w; j += 2) {
+        a0 += v[int64_t(j) * 64] * x[c[int64_t(j) * 64]];
+        a1 += v[int64_t(j + 1) * 64] * x[c[int64_t(j + 1) * 64]];
+    }
+    if (j < w) a0 += v[int64_t(j) * 64] * x[c[int64_t(j) * 64]];
+    const int r = rowidx[int64_t(slice) * 64 + lane];
+    if (r >= 0) y[out_perm ? out_perm[r] : r] = To(a0 + a1);
+}
+
+template <typename T, typename To>
+void launch_sell_spmv(const Sell<T> &A, const T *x, To *y, const int *out_perm, hipStream_t s, const int *skip)
+{
+    if (A.nslices <= 0) return;
+    hipLaunchKernelGGL((k_sell_spmv<T, To>), dim3(nblocks(A.nslices, kBlock / 64)), dim3(kBlock), 0, s, A.nslices,
+                       A.slice_ptr, A.rowidx, A.col, A.val, x, y, out_perm, skip);
+}
+
+template <typename Tv, typename Tx>
+__global__ void __launch_bounds__(kBlock) k_hyb_spmv(int nlong, const int *__restrict__ long_row,
+                                                     const int64_t *__restrict__ long_ptr,
+                                                     const int *__restrict__ long_col, const Tv *__restrict__ long_val,
+                                                     int nslices, const int64_t *__restrict__ slice_ptr,
+                                                     const int *__restrict__ rowidx, const int *__restrict__ col,
+                                                     const Tv *__restrict__ val, const Tx *__restrict__ x,
+                                                     Tx *__restrict__ y, const int *__restrict__ out_perm,
+                                                     const int *skip)
+{
+    if (skip && *skip) return;
+    const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wave < nlong) {
+        // one long row per wave: lanes stride over the row, fixed-order shuffle tree
+        const int64_t b = long_ptr[wave], e = long_ptr[wave + 1];
+        Tx a0 = Tx(0), a1 = Tx(0);
+        int64_t p = b + lane;
+        for (; p + 64 < e; p += 128) {
+            a0 += Tx(long_val[p]) * x[long_col[p]];
+            a1 += Tx(long_val[p + 64]) * x[long_col[p + 64]];
+        }
+        if (p < e) a0 += Tx(long_val[p]) * x[long_col[p]];
+        Tx a = a0 + a1;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+        if (lane == 0) {
+            const int r = long_row[wave];
+            y[out_perm ? out_perm[r] : r] = a;
+        }
+        return;
+    }
+    const int slice = wave - nlong;
+    if (slice >= nslices) return;
+    const int64_t b = slice_ptr[slice];
+    const int w = int((slice_ptr[slice + 1] - b) >> 6);
+    const int *c = col + b + lane;
+    const Tv *v = val + b + lane;
+    Tx a0 = Tx(0), a1 = Tx(0);
+    int j = 0;
+    for (; j + 1 < w; j += 2) {
+        a0 += Tx(v[int64_t(j) * 64]) * x[c[int64_t(j) * 64]];
+        a1 += Tx(v[int64_t(j + 1) * 64]) * x[c[int64_t(j + 1) * 64]];
+    }
+    if (j < w) a0 += Tx(v[int64_t(j) * 64]) * x[c[int64_t(j) * 64]];
+    const int r = rowidx[int64_t(slice) * 64 + lane];
+    if (r >= 0) y[out_perm ? out_perm[r] : r] = a0 + a1;
+}
+
+template <typename Tv, typename Tx>
+void launch_hyb_spmv(const Hyb<Tv> &A, const Tx *x, Tx *y, const int *out_perm, hipStream_t s, const int *skip)
+{
+    const int waves = A.nlong + A.sell.nslices;
+    if (waves <= 0) return;
+    hipLaunchKernelGGL((k_hyb_spmv<Tv, Tx>), dim3(nblocks(waves, kBlock / 64)), dim3(kBlock), 0, s, A.nlong,
+                       A.long_row, A.long_ptr, A.long_col, A.long_val, A.sell.nslices, A.sell.slice_ptr,
+                       A.sell.rowidx, A.sell.col, A.sell.val, x, y, out_perm, skip);
+}
+template void launch_hyb_spmv<float, float>(const Hyb<float> &, const float *, float *, const int *, hipStream_t,
+                                            const int *);
+template void launch_hyb_spmv<double, double>(const Hyb<double> &, const double *, double *, const int *,
+                                              hipStream_t, const int *);
+template void launch_hyb_spmv<float, double>(const Hyb<float> &, const double *, double *, const int *, hipStream_t,
+                                             const int *);
+
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(kBlock) k_gather_cvt(int n, const int *__restrict__ perm, const Tin *__restrict__ b,
+                                                       Tout *__restrict__ w, const int *skip)
+{
+    if (skip && *skip) return;
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) w[p] = Tout(b[perm[p]]);
+}
+template <typename Tin, typename Tout>
+void launch_gather_cvt(int n, const int *perm, const Tin *b, Tout *w, hipStream_t s, const int *skip)
+{
+    hipLaunchKernelGGL((k_gather_cvt<Tin, Tout>), dim3(nblocks(n)), dim3(kBlock), 0, s, n, perm, b, w, skip);
+}
+template void launch_gather_cvt<double, float>(int, const int *, const double *, float *, hipStream_t, const int *);
+template void launch_gather_cvt<double, double>(int, const int *, const double *, double *, hipStream_t, const int *);
+template void launch_sell_spmv<float, double>(const Sell<float> &, const float *, double *, const int *, hipStream_t,
+                                              const int *);
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dinv(int m, const T *__restrict__ dd, const T *__restrict__ dof,
                                                  const int *__restrict__ dp, const T *__restrict__ y,
@@ -674,6 +791,8 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
     template void launch_coarse<T>(int, int, const T *, const T *, T *, hipStream_t, const int *);         \
     template void launch_zspmv<T>(int, const int64_t *, const int *, const T *, const T *, T *, const int *,\
                                   hipStream_t, const int *);                                               \
+    template void launch_sell_spmv<T, T>(const Sell<T> &, const T *, T *, const int *, hipStream_t,       \
+                                      const int *);                                                        \
     template void launch_dinv<T>(int, const T *, const T *, const int *, const T *, T *, hipStream_t,      \
                                  const int *);                                                             \
     template void launch_multidot<T>(int, int, const T *, int64_t, const T *, double *, double *,          \

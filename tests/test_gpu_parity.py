@@ -136,7 +136,8 @@ def test_linear_solve_exact_preconditioner_one_step():
     p.close()
 
 
-@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-10, 1e-9), ("mixed", 1e-5, 1e-4)])
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-10, 1e-9), ("mixed", 1e-5, 1e-4),
+                                                ("mixed_factors", 1e-10, 1e-9)])
 def test_linear_solve_projected(precision, rtol, tol):
     L, sigma = 16, 0.05
     n = L ** 3
@@ -176,7 +177,7 @@ def _check_pairs(L, W, seed, sigma, k, lams_ref, evals, evecs, resid, info, tol=
             assert abs(abs(evecs[:, c] @ vec_ref[:, c]) - 1.0) <= 1e-8
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_factors"])
 def test_solve_small_live_oracle(precision):
     L, W, seed, sigma, k = 8, 16.5, 3, 0.0, 5
     ref, X, _, _ = eig.anderson_nearest(L, W, seed, sigma, k, method="dense")
