@@ -206,6 +206,38 @@ int jd_precond_factor_product(jd_precond *p, int precision, int transpose, const
 int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int pcols,
                             const double *d_b, double *d_x, double rtol, int maxit, int *its);
 
+/*
+ * Host setup steps on their own (no GPU involved), for checks of the setup logic.
+ * The matrix is symmetric, CSR with sorted column indices and a diagonal entry in
+ * every row (n rows, ptr[n + 1], col/val[ptr[n]]).
+ *
+ * jd_host_matching -- maximum-product transversal (section 6.1, eq. (1)-(2)):
+ *   match[i] = column matched to row i; logd[i] = log of the symmetric scaling
+ *   d_i (|d_i a_ij d_j| <= 1, = 1 on matched entries).  Returns the number of
+ *   unmatched rows (0 for a structurally nonsingular matrix) or a negative code.
+ */
+int jd_host_matching(int n, const int64_t *ptr, const int *col, const double *val, int *match, double *logd);
+/*
+ * jd_host_split_cycles -- 1x1 / 2x2 blocks from the cycles of the matching
+ * (section 6.2, figures 3-4): pairs[2 b], pairs[2 b + 1] are the members of block b
+ * (second = -1 for a 1x1 block); *nblocks receives the count (<= n).
+ */
+int jd_host_split_cycles(int n, const int64_t *ptr, const int *col, const double *val, const int *match,
+                         const double *logd, int *pairs, int *nblocks);
+/*
+ * jd_host_factor -- the multilevel factorisation of A (sections 6-7) on the host.
+ * Fills, when non-NULL: perm[n] (position -> row), scale[n] (cumulative scaling of
+ * each position), level_off/level_nb/level_n2x2[cap] per level; returns the number
+ * of levels (or a negative code) and *coarse_n.  g_nnz[cap] receives the stored
+ * coupling entries per level; g_min_scaled[cap] the smallest |entry| of each level's
+ * coupling block in the scaled domain, g_max_colsum[cap] the largest 1 + column sum
+ * of |entries| of a pivot's coupling column in the scaled domain (the ||L^{-1}||_1
+ * bound of inverse-based pivoting).
+ */
+int jd_host_factor(int n, const int64_t *ptr, const int *col, const double *val, const jd_options *opt,
+                   int *perm, double *scale, int cap, int *level_off, int *level_nb, int *level_n2x2,
+                   long long *g_nnz, double *g_min_scaled, double *g_max_colsum, int *coarse_n);
+
 const char *jd_last_error(void);
 /* Library version string. */
 const char *jd_version(void);

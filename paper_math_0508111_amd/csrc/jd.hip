@@ -20,6 +20,7 @@
 #include <numeric>
 #include <stdexcept>
 #include <type_traits>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -109,8 +110,14 @@ SellHost to_sell(int n, const std::vector<int64_t> &ptr, const std::vector<int> 
     std::vector<int> order;
     if (only_rows) order = *only_rows;
     else { order.resize(n); std::iota(order.begin(), order.end(), 0); }
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b]; });
+    // sort by decreasing length only inside windows of consecutive rows, so that a
+    // slice holds rows of similar length that are also neighbours in position order
+    // (their gathers then share cache lines)
+    constexpr size_t kWindow = 2048;
+    for (size_t w0 = 0; w0 < order.size(); w0 += kWindow) {
+        auto b = order.begin() + w0, e = order.begin() + std::min(order.size(), w0 + kWindow);
+        std::stable_sort(b, e, [&](int a, int c) { return ptr[a + 1] - ptr[a] > ptr[c + 1] - ptr[c]; });
+    }
     n = int(order.size());
     const int ns = (n + 63) / 64;
     h.slice_ptr.assign(ns + 1, 0);
@@ -170,9 +177,9 @@ struct DevPrecond {
     T *w = nullptr, *x = nullptr;  // workspaces
     // explicit inverse factor form
     bool inv = false;
-    const int64_t *zptr = nullptr, *ztptr = nullptr;
-    const int *zcol = nullptr, *ztcol = nullptr, *dp = nullptr;
-    const T *zval = nullptr, *ztval = nullptr, *dd = nullptr, *dof = nullptr;
+    const int *site_of = nullptr, *cidx = nullptr, *dp = nullptr;
+    const T *dd = nullptr, *dof = nullptr;
+    T *yc = nullptr;
     jdmi::Sell<T> zs, zts;  // the same two factors in sliced-ELL layout
     jdmi::Hyb<T> zh, zth;   // hybrid layout (long rows per wave + sliced ELL)
 
@@ -228,6 +235,9 @@ struct DevPrecond {
         x = mem.alloc<T>(n);
         inv = !ml.z.ptr.empty();
         if (inv) {
+            site_of = mem.upload(ml.z.site_of, s);
+            cidx = mem.upload(ml.z.coarse_idx, s);
+            yc = mem.alloc<T>(std::max(ml.coarse_n, 1));
             dd = mem.upload(cast_vec<T>(ml.z.dd), s);
             dof = mem.upload(cast_vec<T>(ml.z.dof), s);
             dp = mem.upload(ml.z.dp, s);
@@ -244,11 +254,11 @@ struct DevPrecond {
         if (inv) {
             // P^T Z^T D^{-1} Z P in: gather, sparse product, block diagonal (+ exact last
             // level), transposed sparse product with the inverse permutation on output
-            jdmi::launch_gather<T>(n, perm, in, w, s, skip);
+            jdmi::launch_gather<T>(n, site_of, in, w, s, skip);
             jdmi::launch_hyb_spmv<T, T>(zh, w, x, nullptr, s, skip);
-            jdmi::launch_dinv<T>(coarse_off, dd, dof, dp, x, w, s, skip);
-            jdmi::launch_coarse<T>(coarse_n, coarse_off, cinv, x, w, s, skip);
-            jdmi::launch_hyb_spmv<T, T>(zth, w, out, perm, s, skip);
+            jdmi::launch_dinv<T>(n, dd, dof, dp, x, w, s, skip);
+            jdmi::launch_coarse_idx<T>(coarse_n, cidx, cinv, x, yc, w, s, skip);
+            jdmi::launch_hyb_spmv<T, T>(zth, w, out, site_of, s, skip);
             return;
         }
         jdmi::launch_gather<T>(n, perm, in, w, s, skip);
@@ -269,11 +279,11 @@ struct MixedPrecond {
     void apply(const double *in, double *out, hipStream_t s, const int *skip = nullptr) const
     {
         if (!pc.inv) throw JdError(JD_ENOTIMPL, "binary32 factors with binary64 vectors need the inverse factor form");
-        jdmi::launch_gather_cvt<double, double>(pd.n, pd.perm, in, pd.w, s, skip);
+        jdmi::launch_gather<double>(pd.n, pd.site_of, in, pd.w, s, skip);
         jdmi::launch_hyb_spmv<float, double>(pc.zh, pd.w, pd.x, nullptr, s, skip);
-        jdmi::launch_dinv<double>(pd.coarse_off, pd.dd, pd.dof, pd.dp, pd.x, pd.w, s, skip);
-        jdmi::launch_coarse<double>(pd.coarse_n, pd.coarse_off, pd.cinv, pd.x, pd.w, s, skip);
-        jdmi::launch_hyb_spmv<float, double>(pc.zth, pd.w, out, pd.perm, s, skip);
+        jdmi::launch_dinv<double>(pd.n, pd.dd, pd.dof, pd.dp, pd.x, pd.w, s, skip);
+        jdmi::launch_coarse_idx<double>(pd.coarse_n, pd.cidx, pd.cinv, pd.x, pd.yc, pd.w, s, skip);
+        jdmi::launch_hyb_spmv<float, double>(pc.zth, pd.w, out, pd.site_of, s, skip);
     }
 };
 
@@ -1132,7 +1142,7 @@ int jd_precond_factor_product(jd_precond *p, int precision, int transpose, const
         if (p->S->ml.z.ptr.empty()) throw JdError(JD_EINVAL, "the factorisation has no explicit inverse factor");
         hipStream_t s = static_cast<hipStream_t>(stream);
         auto go = [&](const auto &pc, auto *x, auto *y) {
-            if (transpose) jdmi::launch_hyb_spmv(pc.zth, x, y, pc.perm, s, nullptr);
+            if (transpose) jdmi::launch_hyb_spmv(pc.zth, x, y, pc.site_of, s, nullptr);
             else jdmi::launch_hyb_spmv(pc.zh, x, y, static_cast<const int *>(nullptr), s, nullptr);
         };
         if (precision == JD_FP64) go(p->S->pc64, static_cast<const double *>(d_x), static_cast<double *>(d_y));
@@ -1140,6 +1150,95 @@ int jd_precond_factor_product(jd_precond *p, int precision, int transpose, const
         else throw JdError(JD_EINVAL, "unknown precision");
         HIPCHK(hipGetLastError());
         return JD_OK;
+    });
+}
+
+static jdmi::Csr host_csr(int n, const int64_t *ptr, const int *col, const double *val)
+{
+    if (n < 1 || !ptr || !col || !val) throw JdError(JD_EINVAL, "bad CSR arguments");
+    jdmi::Csr A;
+    A.n = n;
+    A.ptr.assign(ptr, ptr + n + 1);
+    if (A.ptr[0] != 0) throw JdError(JD_EINVAL, "ptr[0] must be 0");
+    for (int i = 0; i < n; ++i) {
+        if (A.ptr[i + 1] < A.ptr[i]) throw JdError(JD_EINVAL, "ptr not monotone");
+        bool diag = false;
+        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+            if (col[p] < 0 || col[p] >= n) throw JdError(JD_EINVAL, "column index out of range");
+            if (p > A.ptr[i] && col[p] <= col[p - 1]) throw JdError(JD_EINVAL, "columns not sorted/unique");
+            if (!std::isfinite(val[p])) throw JdError(JD_EINVAL, "non-finite value");
+            diag |= col[p] == i;
+        }
+        if (!diag) throw JdError(JD_EINVAL, "missing diagonal entry");
+    }
+    A.col.assign(col, col + A.ptr[n]);
+    A.val.assign(val, val + A.ptr[n]);
+    return A;
+}
+
+int jd_host_matching(int n, const int64_t *ptr, const int *col, const double *val, int *match, double *logd)
+{
+    return guarded([&] {
+        jdmi::Csr A = host_csr(n, ptr, col, val);
+        jdmi::MatchResult r = jdmi::max_product_matching(A);
+        if (match) std::copy(r.match.begin(), r.match.end(), match);
+        if (logd) std::copy(r.logd.begin(), r.logd.end(), logd);
+        return r.unmatched;
+    });
+}
+
+int jd_host_split_cycles(int n, const int64_t *ptr, const int *col, const double *val, const int *match,
+                         const double *logd, int *pairs, int *nblocks)
+{
+    return guarded([&] {
+        jdmi::Csr A = host_csr(n, ptr, col, val);
+        if (!match || !logd || !pairs || !nblocks) throw JdError(JD_EINVAL, "NULL argument");
+        std::vector<int> m(match, match + n);
+        for (int v : m)
+            if (v < -1 || v >= n) throw JdError(JD_EINVAL, "match entry out of range");
+        std::vector<double> ld(logd, logd + n);
+        auto b = jdmi::split_cycles(A, m, ld);
+        for (size_t i = 0; i < b.size(); ++i) { pairs[2 * i] = b[i].first; pairs[2 * i + 1] = b[i].second; }
+        *nblocks = int(b.size());
+        return JD_OK;
+    });
+}
+
+int jd_host_factor(int n, const int64_t *ptr, const int *col, const double *val, const jd_options *opt,
+                   int *perm, double *scale, int cap, int *level_off, int *level_nb, int *level_n2x2,
+                   long long *g_nnz, double *g_min_scaled, double *g_max_colsum, int *coarse_n)
+{
+    return guarded([&] {
+        jdmi::Csr A = host_csr(n, ptr, col, val);
+        jd_options o{};
+        if (opt) o = *opt;
+        fill_defaults(o, n);
+        jdmi::SetupParams prm;
+        prm.drop_tol = o.drop_tol;
+        prm.kappa = o.kappa;
+        prm.agg_tau = o.agg_tau;
+        prm.schur_tol = o.schur_tol;
+        prm.coarse_max = o.coarse_max;
+        prm.max_levels = o.max_levels;
+        prm.z_drop = o.z_drop;
+        prm.inverse_factor = false;
+        jdmi::Multilevel ml;
+        std::string err = jdmi::build_multilevel(A, prm, ml);
+        if (!err.empty()) throw JdError(JD_ESETUP, err);
+        if (perm) std::copy(ml.perm.begin(), ml.perm.end(), perm);
+        if (scale) std::copy(ml.pos_scale.begin(), ml.pos_scale.end(), scale);
+        const int nl = int(ml.levels.size());
+        for (int l = 0; l < nl && l < cap; ++l) {
+            const auto &Lv = ml.levels[l];
+            if (level_off) level_off[l] = Lv.off;
+            if (level_nb) level_nb[l] = Lv.nB;
+            if (level_n2x2) level_n2x2[l] = Lv.n2x2;
+            if (g_nnz) g_nnz[l] = (long long)Lv.g_col.size();
+            if (g_min_scaled) g_min_scaled[l] = Lv.g_min_scaled;
+            if (g_max_colsum) g_max_colsum[l] = Lv.g_max_colsum;
+        }
+        if (coarse_n) *coarse_n = ml.coarse_n;
+        return nl;
     });
 }
 

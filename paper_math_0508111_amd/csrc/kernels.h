@@ -43,6 +43,10 @@ template <typename T>
 void launch_up(const DevLevel<T> &lv, const T *w, T *x, hipStream_t s, const int *skip);
 template <typename T>
 void launch_coarse(int nc, int off, const T *cinv, const T *w, T *x, hipStream_t s, const int *skip);
+// last level with scattered unknowns: yc[i] = y[idx[i]], then z[idx[i]] = sum_j Cinv[i, j] yc[j]
+template <typename T>
+void launch_coarse_idx(int nc, const int *idx, const T *cinv, const T *y, T *yc, T *z, hipStream_t s,
+                       const int *skip);
 
 // explicit inverse factor apply: y = Z w (16 lanes per row); optional output permutation
 // out[perm[r]] = (Z w)[r]

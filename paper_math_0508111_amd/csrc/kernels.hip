@@ -211,6 +211,32 @@ __global__ void __launch_bounds__(kBlock) k_coarse(int nc, int off, const T *__r
 }
 
 template <typename T>
+__global__ void __launch_bounds__(kBlock) k_coarse_rows(int nc, const int *__restrict__ idx,
+                                                        const T *__restrict__ cinv, const T *__restrict__ yc,
+                                                        T *__restrict__ z, const int *skip)
+{
+    if (skip && *skip) return;
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= nc) return;
+    const T *a = cinv + int64_t(row) * nc;
+    double acc = 0.0;
+    for (int c = lane; c < nc; c += 64) acc += double(a[c]) * double(yc[c]);
+    acc = wave_sum(acc);
+    if (lane == 0) z[idx[row]] = T(acc);
+}
+
+template <typename T>
+void launch_coarse_idx(int nc, const int *idx, const T *cinv, const T *y, T *yc, T *z, hipStream_t s,
+                       const int *skip)
+{
+    if (nc <= 0) return;
+    hipLaunchKernelGGL(k_gather<T>, dim3(nblocks(nc)), dim3(kBlock), 0, s, nc, idx, y, yc, skip);
+    hipLaunchKernelGGL(k_coarse_rows<T>, dim3(nblocks(nc, kBlock / 64)), dim3(kBlock), 0, s, nc, idx, cinv, yc, z,
+                       skip);
+}
+
+template <typename T>
 void launch_gather(int n, const int *perm, const T *b, T *w, hipStream_t s, const int *skip)
 {
     hipLaunchKernelGGL(k_gather<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, perm, b, w, skip);
@@ -321,16 +347,21 @@ __global__ void __launch_bounds__(kBlock) k_hyb_spmv(int nlong, const int *__res
     const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (wave < nlong) {
-        // one long row per wave: lanes stride over the row, fixed-order shuffle tree
+        // one long row per wave: lanes stride over the row (four entries in flight per
+        // lane: all index and value loads are issued before the dependent gathers)
         const int64_t b = long_ptr[wave], e = long_ptr[wave + 1];
-        Tx a0 = Tx(0), a1 = Tx(0);
+        Tx a0 = Tx(0), a1 = Tx(0), a2 = Tx(0), a3 = Tx(0);
         int64_t p = b + lane;
-        for (; p + 64 < e; p += 128) {
-            a0 += Tx(long_val[p]) * x[long_col[p]];
-            a1 += Tx(long_val[p + 64]) * x[long_col[p + 64]];
+        for (; p + 192 < e; p += 256) {
+            const int c0 = long_col[p], c1 = long_col[p + 64], c2 = long_col[p + 128], c3 = long_col[p + 192];
+            const Tv v0 = long_val[p], v1 = long_val[p + 64], v2 = long_val[p + 128], v3 = long_val[p + 192];
+            a0 += Tx(v0) * x[c0];
+            a1 += Tx(v1) * x[c1];
+            a2 += Tx(v2) * x[c2];
+            a3 += Tx(v3) * x[c3];
         }
-        if (p < e) a0 += Tx(long_val[p]) * x[long_col[p]];
-        Tx a = a0 + a1;
+        for (; p < e; p += 64) a0 += Tx(long_val[p]) * x[long_col[p]];
+        Tx a = (a0 + a1) + (a2 + a3);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
         if (lane == 0) {
@@ -345,15 +376,20 @@ __global__ void __launch_bounds__(kBlock) k_hyb_spmv(int nlong, const int *__res
     const int w = int((slice_ptr[slice + 1] - b) >> 6);
     const int *c = col + b + lane;
     const Tv *v = val + b + lane;
-    Tx a0 = Tx(0), a1 = Tx(0);
+    Tx a0 = Tx(0), a1 = Tx(0), a2 = Tx(0), a3 = Tx(0);
     int j = 0;
-    for (; j + 1 < w; j += 2) {
-        a0 += Tx(v[int64_t(j) * 64]) * x[c[int64_t(j) * 64]];
-        a1 += Tx(v[int64_t(j + 1) * 64]) * x[c[int64_t(j + 1) * 64]];
+    for (; j + 3 < w; j += 4) {
+        const int64_t o = int64_t(j) * 64;
+        const int c0 = c[o], c1 = c[o + 64], c2 = c[o + 128], c3 = c[o + 192];
+        const Tv v0 = v[o], v1 = v[o + 64], v2 = v[o + 128], v3 = v[o + 192];
+        a0 += Tx(v0) * x[c0];
+        a1 += Tx(v1) * x[c1];
+        a2 += Tx(v2) * x[c2];
+        a3 += Tx(v3) * x[c3];
     }
-    if (j < w) a0 += Tx(v[int64_t(j) * 64]) * x[c[int64_t(j) * 64]];
+    for (; j < w; ++j) a0 += Tx(v[int64_t(j) * 64]) * x[c[int64_t(j) * 64]];
     const int r = rowidx[int64_t(slice) * 64 + lane];
-    if (r >= 0) y[out_perm ? out_perm[r] : r] = a0 + a1;
+    if (r >= 0) y[out_perm ? out_perm[r] : r] = (a0 + a1) + (a2 + a3);
 }
 
 template <typename Tv, typename Tx>
@@ -789,6 +825,8 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
     template void launch_down<T>(const DevLevel<T> &, T *, hipStream_t, const int *);                      \
     template void launch_up<T>(const DevLevel<T> &, const T *, T *, hipStream_t, const int *);             \
     template void launch_coarse<T>(int, int, const T *, const T *, T *, hipStream_t, const int *);         \
+    template void launch_coarse_idx<T>(int, const int *, const T *, const T *, T *, T *, hipStream_t,      \
+                                       const int *);                                                       \
     template void launch_zspmv<T>(int, const int64_t *, const int *, const T *, const T *, T *, const int *,\
                                   hipStream_t, const int *);                                               \
     template void launch_sell_spmv<T, T>(const Sell<T> &, const T *, T *, const int *, hipStream_t,       \

@@ -311,6 +311,7 @@ struct LevelLocal {
     std::vector<int> g_col;
     std::vector<double> g_val;
     int n2x2 = 0, rejected = 0;
+    double g_min = 0.0, g_colsum = 1.0;
 };
 
 // scaled value
@@ -323,7 +324,8 @@ struct Scaled {
 }  // namespace
 
 static std::string factor_level(const Csr &A, const SetupParams &prm, const std::vector<double> &d,
-                                const std::vector<std::pair<int, int>> &blocks, LevelLocal &lv, Csr &S_next)
+                                const std::vector<std::pair<int, int>> &blocks, const std::vector<uint64_t> &key,
+                                LevelLocal &lv, Csr &S_next)
 {
     const int n = A.n;
     const bool exact = prm.drop_tol < 0;
@@ -416,9 +418,13 @@ static std::string factor_level(const Csr &A, const SetupParams &prm, const std:
     lv.C.clear();
     std::vector<int> loc(n, -1);
     for (int i = 0; i < n; ++i) {
-        if (state[i] == INB) { loc[i] = int(lv.B.size()); lv.B.push_back(i); }
+        if (state[i] == INB) lv.B.push_back(i);
         else { loc[i] = int(lv.C.size()); lv.C.push_back(i); }
     }
+    // pivots of the level in Morton order of their lattice sites: the order only sets
+    // memory positions, and keeps lattice neighbours close in the device vectors
+    std::stable_sort(lv.B.begin(), lv.B.end(), [&](int a, int b) { return key[a] < key[b]; });
+    for (size_t t = 0; t < lv.B.size(); ++t) loc[lv.B[t]] = int(t);
     const int nB = int(lv.B.size()), nC = int(lv.C.size());
     lv.rejected = rejected;
     lv.partner.assign(nB, 0);
@@ -470,6 +476,17 @@ static std::string factor_level(const Csr &A, const SetupParams &prm, const std:
                 if (std::fabs(e.second) > prm.agg_tau / std::max(cnt[e.first], 1)) row[w++] = e;
             row.resize(w);
         }
+    }
+    {
+        // invariants of the stored factor columns (reported for checks)
+        double mn = kInf;
+        std::vector<double> cs(nB, 0.0);
+        for (auto &row : grow)
+            for (auto &e : row) { mn = std::min(mn, std::fabs(e.second)); cs[e.first] += std::fabs(e.second); }
+        double mx = 1.0;
+        for (double v : cs) mx = std::max(mx, 1.0 + v);
+        lv.g_min = mn;
+        lv.g_colsum = mx;
     }
     lv.g_ptr.assign(nC + 1, 0);
     for (int r = 0; r < nC; ++r) lv.g_ptr[r + 1] = lv.g_ptr[r] + int64_t(grow[r].size());
@@ -597,8 +614,22 @@ static std::string factor_level(const Csr &A, const SetupParams &prm, const std:
     return "";
 }
 
+// Morton (bit-interleaved) code of the site s = i + L (j + L k)
+static uint64_t morton(int s, int L)
+{
+    if (L <= 0) return uint64_t(s);
+    const uint64_t i = uint64_t(s % L), j = uint64_t((s / L) % L), k = uint64_t(s / L / L);
+    uint64_t m = 0;
+    for (int b = 0; b < 21; ++b)
+        m |= (((i >> b) & 1ull) << (3 * b)) | (((j >> b) & 1ull) << (3 * b + 1)) | (((k >> b) & 1ull) << (3 * b + 2));
+    return m;
+}
+
 std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &out)
 {
+    // lattice edge for the locality order (0 if n is not a cube)
+    int L = int(std::lround(std::cbrt(double(A0.n))));
+    if (int64_t(L) * L * L != A0.n) L = 0;
     const double t0 = now_s();
     const int n = A0.n;
     out = Multilevel();
@@ -635,7 +666,9 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
         for (int i = 0; i < S.n; ++i) d[i] = std::exp(mr.logd[i]);
         Pending pl;
         Csr Snext;
-        std::string err = factor_level(S, prm, d, blocks, pl.lv, Snext);
+        std::vector<uint64_t> key(S.n);
+        for (int i = 0; i < S.n; ++i) key[i] = morton(orig[i], L);
+        std::string err = factor_level(S, prm, d, blocks, key, pl.lv, Snext);
         double td = now_s();
         t_match += tb - ta; t_split += tc - tb; t_fact += td - tc;
         if (verbose)
@@ -705,6 +738,8 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
         G.n_after = nC;
         G.n2x2 = lv.n2x2;
         G.cand_rejected = lv.rejected;
+        G.g_min_scaled = lv.g_min;
+        G.g_max_colsum = lv.g_colsum;
         // gpos (next level) -> this level
         std::vector<int> gl(lv.B.size() + lv.C.size());
         for (int t = 0; t < nB; ++t) gl[lv.B[t]] = pl.off + t;
@@ -766,7 +801,7 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
     if (verbose)
         fprintf(stderr, "levels %zu coarse %d: match %.2fs split %.2fs factor %.2fs total %.2fs\n", out.levels.size(),
                 out.coarse_n, t_match, t_split, t_fact, now_s() - t0);
-    if (prm.inverse_factor) build_inverse_factor(out, prm.z_drop);
+    if (prm.inverse_factor) build_inverse_factor(out, prm.z_drop, L);
     out.seconds = now_s() - t0;
     return "";
 }
@@ -778,7 +813,7 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
 // scaled domain) so that the device applies the whole preconditioner as
 // P^T Z^T D^{-1} Z P: two sparse products and a block-diagonal solve.
 // ---------------------------------------------------------------------------------
-void build_inverse_factor(Multilevel &ml, double z_drop)
+void build_inverse_factor(Multilevel &ml, double z_drop, int L)
 {
     const double t0 = now_s();
     const int n = ml.n;
@@ -819,15 +854,32 @@ void build_inverse_factor(Multilevel &ml, double z_drop)
             // implicit barrier of the worksharing loop: level m is complete
         }
     }
+    // renumbering: position p -> Morton rank of its site
+    std::vector<int> newidx(n);
+    {
+        std::vector<std::pair<uint64_t, int>> keyed(n);
+        for (int p = 0; p < n; ++p) keyed[p] = {morton(ml.perm[p], L), p};
+        std::sort(keyed.begin(), keyed.end());
+        Z.site_of.resize(n);
+        for (int q = 0; q < n; ++q) {
+            newidx[keyed[q].second] = q;
+            Z.site_of[q] = ml.perm[keyed[q].second];
+        }
+    }
+    std::vector<int> pos_of(n);
+    for (int p = 0; p < n; ++p) pos_of[newidx[p]] = p;
     Z.ptr.assign(n + 1, 0);
-    for (int r = 0; r < n; ++r) Z.ptr[r + 1] = Z.ptr[r] + int64_t(rows[r].size());
+    for (int q = 0; q < n; ++q) Z.ptr[q + 1] = Z.ptr[q] + int64_t(rows[pos_of[q]].size());
     Z.col.resize(Z.ptr[n]);
     Z.val.resize(Z.ptr[n]);
     Z.tptr.assign(n + 1, 0);
-    for (int r = 0; r < n; ++r) {
-        int64_t p = Z.ptr[r];
-        for (auto &e : rows[r]) { Z.col[p] = e.first; Z.val[p] = e.second; ++p; ++Z.tptr[e.first + 1]; }
-        std::vector<std::pair<int, double>>().swap(rows[r]);
+    for (int q = 0; q < n; ++q) {
+        auto &row = rows[pos_of[q]];
+        for (auto &e : row) e.first = newidx[e.first];
+        std::sort(row.begin(), row.end());
+        int64_t p = Z.ptr[q];
+        for (auto &e : row) { Z.col[p] = e.first; Z.val[p] = e.second; ++p; ++Z.tptr[e.first + 1]; }
+        std::vector<std::pair<int, double>>().swap(row);
     }
     for (int r = 0; r < n; ++r) Z.tptr[r + 1] += Z.tptr[r];
     Z.tcol.resize(Z.tptr[n]);
@@ -841,15 +893,19 @@ void build_inverse_factor(Multilevel &ml, double z_drop)
                 Z.tval[fp[c]++] = Z.val[p];
             }
     }
-    Z.dd.assign(ml.coarse_off, 0.0);
-    Z.dof.assign(ml.coarse_off, 0.0);
-    Z.dp.assign(ml.coarse_off, 0);
+    Z.dd.assign(n, 0.0);
+    Z.dof.assign(n, 0.0);
+    Z.dp.resize(n);
+    for (int q = 0; q < n; ++q) Z.dp[q] = q;
     for (const auto &Lv : ml.levels)
         for (int t = 0; t < Lv.nB; ++t) {
-            Z.dd[Lv.off + t] = Lv.bd[t];
-            Z.dof[Lv.off + t] = Lv.bo[t];
-            Z.dp[Lv.off + t] = Lv.bp[t];
+            const int q = newidx[Lv.off + t];
+            Z.dd[q] = Lv.bd[t];
+            Z.dof[q] = Lv.bo[t];
+            Z.dp[q] = newidx[Lv.bp[t]];
         }
+    Z.coarse_idx.resize(ml.coarse_n);
+    for (int i = 0; i < ml.coarse_n; ++i) Z.coarse_idx[i] = newidx[ml.coarse_off + i];
     Z.seconds = now_s() - t0;
 }
 

@@ -49,12 +49,17 @@ struct SetupParams {
 
 // Explicit inverse of the unit lower triangular factor of all levels, Z ~ L^{-1}
 // (global positions), and the block diagonal D^{-1}: K^{-1} = P^T Z^T D^{-1} Z P.
+// Rows and columns are renumbered in Morton order of the lattice sites (the apply does
+// not need the elimination order), so that the gathers of neighbouring rows share cache
+// lines: K^{-1} b = S^T Z^T D^{-1} Z S b with (S b)[q] = b[site_of[q]].
 struct InverseFactor {
-    std::vector<int64_t> ptr, tptr;   // CSR of Z and of Z^T (n + 1 each)
+    std::vector<int> site_of;         // n: new index -> lattice site
+    std::vector<int64_t> ptr, tptr;   // CSR of Z and of Z^T (n + 1 each), new numbering
     std::vector<int> col, tcol;
     std::vector<double> val, tval;
-    std::vector<double> dd, dof;      // D^{-1} for positions < coarse_off: dd w[j] + dof w[dp[j]]
+    std::vector<double> dd, dof;      // D^{-1}: z[q] = dd[q] y[q] + dof[q] y[dp[q]] (0 on the last level)
     std::vector<int> dp;
+    std::vector<int> coarse_idx;      // coarse_n: new index of each unknown of the last level
     double seconds = 0.0;
 };
 
@@ -75,6 +80,8 @@ struct Level {
     std::vector<double> bd, bo;                 // nB
     std::vector<int> bp;                        // nB, global partner position
     int cand_rejected = 0;                      // candidates refused by the kappa test
+    double g_min_scaled = 0.0;                  // smallest stored |L21 entry|, scaled domain
+    double g_max_colsum = 1.0;                  // largest 1 + sum_r |L21[r, j]| over pivots j
 };
 
 struct Multilevel {
@@ -92,7 +99,7 @@ struct Multilevel {
 
 // Z = L^{-1} row by row (row r = e_r - sum over earlier levels of G[r, c] z_c), dropping
 // entries with |z_rc| s_r / s_c < z_drop (s = pos_scale), and its transpose.
-void build_inverse_factor(Multilevel &ml, double z_drop);
+void build_inverse_factor(Multilevel &ml, double z_drop, int L);
 
 // Build the multilevel factorisation of the symmetric matrix A.
 // Returns an empty string on success, else a message.

@@ -1,0 +1,248 @@
+"""CPU checks of the C ABI and of the host-side setup (no GPU involved).
+
+* every function declared in include/jd.h is exported by libjdmi.so;
+* argument validation returns JD_EINVAL before any device call;
+* maximum-product matching against brute force and its scaling invariants
+  (section 6.1, eq. (1)-(2); section 5.2: scaled entries at most 1 in modulus);
+* the cycle split of the worked example of figures 3-4 (section 6.2);
+* invariants of the multilevel factorisation (section 7.2: dropped entries below
+  epsilon / kappa, ||L^{-1}||_1 <= kappa for accepted pivots).
+"""
+import ctypes
+import itertools
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="session")
+def jd():
+    import paper_math_0508111_amd as jd
+    if not os.path.exists(jd.LIB_PATH):
+        from paper_math_0508111_amd import build
+        build.build()
+    jd.lib()
+    return jd
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "jd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(jd_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_all_declared_symbols_exported(jd):
+    lib = jd.lib()
+    names = _declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(jd.EXPORTS) <= set(names)
+
+
+def test_invalid_arguments_rejected(jd):
+    lib = jd.lib()
+    ev = np.zeros(4)
+    p = ev.ctypes.data_as(ctypes.c_void_p)
+    for args in [(1, 16.5, 0, 0.0, 4, 1e-10),          # L < 2
+                 (8, -1.0, 0, 0.0, 4, 1e-10),          # W < 0
+                 (8, float("nan"), 0, 0.0, 4, 1e-10),  # W not finite
+                 (8, 16.5, 0, float("inf"), 4, 1e-10),  # sigma not finite
+                 (8, 16.5, 0, 0.0, 0, 1e-10),          # k < 1
+                 (8, 16.5, 0, 0.0, 4, 0.0),            # tol <= 0
+                 (2000, 16.5, 0, 0.0, 4, 1e-10)]:      # L^3 >= 2^31
+        rc = lib.jd_solve(*args, p, None, None, None, None)
+        assert rc == jd.JD_EINVAL, args
+        assert lib.jd_last_error().decode()
+    rc = lib.jd_solve(8, 16.5, 0, 0.0, 4, 1e-10, None, None, None, None, None)  # evals NULL
+    assert rc == jd.JD_EINVAL
+    o = jd.make_options(precision="fp64")
+    o.precision = 7
+    rc = lib.jd_solve(8, 16.5, 0, 0.0, 4, 1e-10, p, None, None, ctypes.byref(o), None)
+    assert rc == jd.JD_EINVAL
+
+
+# --- host setup helpers --------------------------------------------------------------
+
+def _csr(A):
+    # CSR with every nonzero and an explicit (possibly zero) diagonal entry per row
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    ptr, col, val = [0], [], []
+    for i in range(n):
+        js = [j for j in range(n) if A[i, j] != 0 or j == i]
+        col += js
+        val += [A[i, j] for j in js]
+        ptr.append(len(col))
+    M = sp.csr_matrix(A)
+    return (np.array(ptr, dtype=np.int64), np.array(col, dtype=np.int32), np.array(val, dtype=np.float64), M)
+
+
+def _vp(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _matching(jd, A):
+    ptr, col, val, M = _csr(A)
+    n = M.shape[0]
+    match = np.zeros(n, np.int32)
+    logd = np.zeros(n)
+    L = jd.lib()
+    f = L.jd_host_matching
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 5
+    un = f(n, _vp(ptr), _vp(col), _vp(val), _vp(match), _vp(logd))
+    assert un >= 0, L.jd_last_error()
+    return match, logd, un, (ptr, col, val, M)
+
+
+def _random_symmetric(n, density, rng):
+    A = np.zeros((n, n))
+    for i in range(n):
+        for j in range(i, n):
+            if i == j or rng.random() < density:
+                v = rng.standard_normal() * 10 ** rng.uniform(-2, 2)
+                A[i, j] = A[j, i] = v
+    return A
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_matching_maximises_the_diagonal_product(jd, seed):
+    # section 6.1, eq. (1): the matching maximises prod_i |a_{i, match(i)}|; brute force
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(3, 8))
+    A = _random_symmetric(n, 0.5, rng)
+    if seed % 3 == 0:
+        A[np.diag_indices(n)] *= 1e-3  # small diagonal: off-diagonal matches win
+    match, logd, un, _ = _matching(jd, A)
+    assert un == 0 and sorted(match) == list(range(n))
+    best = max(sum(math.log(abs(A[i, p[i]])) for i in range(n))
+               for p in itertools.permutations(range(n)) if all(A[i, p[i]] != 0 for i in range(n)))
+    got = sum(math.log(abs(A[i, match[i]])) for i in range(n))
+    assert got >= best - 1e-9
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_symmetric_scaling_invariants(jd, seed):
+    # section 5.2: after the symmetric scaling every entry has modulus <= 1; matched
+    # 1x1 diagonal entries and 2-cycle couplings have modulus 1
+    rng = np.random.default_rng(100 + seed)
+    n = 40
+    A = _random_symmetric(n, 0.15, rng)
+    match, logd, un, _ = _matching(jd, A)
+    assert un == 0
+    d = np.exp(logd)
+    S = d[:, None] * A * d[None, :]
+    assert np.abs(S).max() <= 1 + 1e-12
+    for i in range(n):
+        j = match[i]
+        if j == i or match[j] == i:
+            assert abs(abs(S[i, j]) - 1) <= 1e-12
+
+
+def test_anderson_matrix_matching(jd):
+    from oracle import generator, lattice  # the test builds its input with the oracle's generator
+    L = 6
+    A = lattice.hamiltonian(L, generator.disorder(L, 16.5, 3)).toarray()
+    match, logd, un, _ = _matching(jd, A)
+    assert un == 0
+    d = np.exp(logd)
+    assert np.abs(d[:, None] * A * d[None, :]).max() <= 1 + 1e-12
+
+
+def test_cycle_split_worked_example(jd):
+    # figures 3-4: P_M = (e4; e1; e5; e2; e3; e6) has the cycles (1 2 4)(3 5)(6); the
+    # split keeps (3 5) and (6), and breaks (1 2 4) into (1)(2 4).  Here the matched
+    # couplings are large and a_22 = a_44 = 0, so only 1 can be the 1x1 pivot of the
+    # odd cycle (the split must not leave a zero 1x1 pivot when it can avoid it).
+    n = 6
+    A = np.full((n, n), 0.0)
+    big = [(0, 1), (1, 3), (3, 0), (2, 4), (5, 5)]  # 0-based (row, matched column)
+    for i, j in big:
+        A[i, j] = A[j, i] = 10.0
+    A[0, 0] = 1.0
+    A[2, 2] = A[4, 4] = 0.5
+    A[0, 5] = A[5, 0] = 0.1
+    A[2, 5] = A[5, 2] = 0.1
+    match, logd, un, (ptr, col, val, M) = _matching(jd, A)
+    assert un == 0
+    # cycles of the matching permutation
+    seen, cycles = set(), []
+    for s in range(n):
+        if s in seen:
+            continue
+        c, t = [], s
+        while t not in seen:
+            seen.add(t)
+            c.append(t)
+            t = match[t]
+        cycles.append(sorted(c))
+    assert sorted(cycles) == [[0, 1, 3], [2, 4], [5]]
+    pairs = np.zeros(2 * n, np.int32)
+    nb = ctypes.c_int()
+    f = jd.lib().jd_host_split_cycles
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 7
+    assert f(n, _vp(ptr), _vp(col), _vp(val), _vp(match), _vp(logd), _vp(pairs), ctypes.byref(nb)) == 0
+    blocks = sorted(tuple(sorted(b for b in pairs[2 * i:2 * i + 2] if b >= 0)) for i in range(nb.value))
+    assert blocks == [(0,), (1, 3), (2, 4), (5,)]
+
+
+def _host_factor(jd, A, **opts):
+    ptr, col, val, M = _csr(A)
+    n = M.shape[0]
+    cap = 512
+    perm = np.zeros(n, np.int32)
+    scale = np.zeros(n)
+    off = np.zeros(cap, np.int32)
+    nb = np.zeros(cap, np.int32)
+    n2 = np.zeros(cap, np.int32)
+    gnnz = np.zeros(cap, np.int64)
+    gmin = np.zeros(cap)
+    gcs = np.zeros(cap)
+    cn = ctypes.c_int()
+    o = jd.make_options(**opts)
+    f = jd.lib().jd_host_factor
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 6 + [ctypes.c_int] + [ctypes.c_void_p] * 7
+    nl = f(n, _vp(ptr), _vp(col), _vp(val), ctypes.byref(o), _vp(perm), _vp(scale), cap, _vp(off), _vp(nb),
+           _vp(n2), _vp(gnnz), _vp(gmin), _vp(gcs), ctypes.byref(cn))
+    assert nl >= 0, jd.lib().jd_last_error()
+    return dict(levels=nl, perm=perm, scale=scale, off=off[:nl], nB=nb[:nl], n2x2=n2[:nl], gnnz=gnnz[:nl],
+                gmin=gmin[:nl], gcolsum=gcs[:nl], coarse=cn.value)
+
+
+@pytest.mark.parametrize("L,W,drop,kappa", [(10, 16.5, 1e-2, 5.0), (12, 12.0, 3e-3, 5.0), (12, 21.0, 1e-2, 10.0)])
+def test_multilevel_invariants(jd, L, W, drop, kappa):
+    from oracle import generator, lattice
+    A = lattice.hamiltonian(L, generator.disorder(L, W, 1)).toarray()
+    n = L ** 3
+    r = _host_factor(jd, A, drop_tol=drop, kappa=kappa, coarse_max=200)
+    assert r["levels"] >= 2
+    assert sorted(r["perm"]) == list(range(n))
+    # levels cover consecutive position ranges, the last level takes the rest
+    ends = r["off"] + r["nB"]
+    assert r["off"][0] == 0 and np.all(r["off"][1:] == ends[:-1]) and ends[-1] + r["coarse"] == n
+    assert np.all(r["nB"] > 0) and r["coarse"] <= 8192
+    # dropping: nothing below epsilon / kappa survives (scaled domain)
+    assert np.all(r["gmin"][r["gnnz"] > 0] >= drop / kappa * (1 - 1e-12))
+    # inverse-based pivoting: 1 + column sum of |L21| <= kappa for every accepted pivot
+    assert np.all(r["gcolsum"] <= kappa * (1 + 1e-12))
+    assert np.all(r["scale"] > 0)
+
+
+def test_multilevel_no_dropping_keeps_small_entries(jd):
+    from oracle import generator, lattice
+    L = 8
+    A = lattice.hamiltonian(L, generator.disorder(L, 16.5, 2)).toarray()
+    exact = _host_factor(jd, A, drop_tol=-1.0, coarse_max=40)
+    dropped = _host_factor(jd, A, drop_tol=5e-2, coarse_max=40)
+    assert exact["levels"] >= 2
+    assert exact["gnnz"].sum() >= dropped["gnnz"][: exact["levels"]].sum()
+    assert exact["gmin"][exact["gnnz"] > 0].min() < 5e-2 / 5.0  # small entries kept
