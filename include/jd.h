@@ -62,7 +62,7 @@ enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
  *  kappa      bound on ||L^{-1}|| of inverse-based pivoting, section 7.2 (0 -> 5).
  *  agg_tau    tau of the aggressive dropping rule of section 7.3 (0 -> 0.1).
  *  schur_tol  off-diagonal entries of a scaled Schur complement below this are
- *             dropped (0 -> drop_tol).
+ *             dropped (0 -> drop_tol / 2).
  *  coarse_max the multilevel recursion (section 7.3) stops at this size and the
  *             last Schur complement is inverted exactly (0 -> 1536); it also stops
  *             once a level accepts fewer than 1% of its unknowns and at most 8192 remain.

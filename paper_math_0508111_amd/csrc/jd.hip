@@ -310,7 +310,7 @@ void fill_defaults(jd_options &o, int n)
     if (o.drop_tol == 0) o.drop_tol = 1.0 / std::sqrt(double(n));
     if (o.kappa == 0) o.kappa = 5.0;
     if (o.agg_tau == 0) o.agg_tau = 0.1;
-    if (o.schur_tol == 0) o.schur_tol = o.drop_tol > 0 ? o.drop_tol : -1.0;
+    if (o.schur_tol == 0) o.schur_tol = o.drop_tol > 0 ? 0.5 * o.drop_tol : -1.0;
     if (o.coarse_max == 0) o.coarse_max = 1536;
     if (o.max_levels == 0) o.max_levels = 400;
     if (o.z_drop == 0) o.z_drop = o.drop_tol < 0 ? -1.0 : 1e-2;
@@ -335,6 +335,33 @@ void check_problem_args(int L, double W, double sigma, const jd_options *opt)
             !std::isfinite(opt->agg_tau) || !std::isfinite(opt->schur_tol) || !std::isfinite(opt->switch_tol))
             throw JdError(JD_EINVAL, "non-finite option");
     }
+}
+
+// The last Schur complement is inverted on the device (Gauss-Jordan with partial
+// pivoting, binary64) and the cumulative scaling folded in: diag(s) S^{-1} diag(s).
+void invert_coarse_on_device(Setup &S)
+{
+    jdmi::Multilevel &ml = S.ml;
+    const int nc = ml.coarse_n;
+    if (nc == 0 || !ml.coarse_inv.empty()) return;
+    DevMem tmp;
+    double *a = tmp.upload(ml.coarse_mat, S.stream);
+    double *inv = tmp.alloc<double>(size_t(nc) * nc);
+    double *colc = tmp.alloc<double>(nc);
+    double *sc = tmp.upload(ml.coarse_scale, S.stream);
+    int *status = tmp.alloc<int>(1);
+    HIPCHK(hipMemsetAsync(status, 0, sizeof(int), S.stream));
+    jdmi::launch_gauss_jordan(nc, a, inv, colc, status, S.stream);
+    jdmi::launch_scale_sym(nc, inv, sc, S.stream);
+    HIPCHK(hipGetLastError());
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, S.stream));
+    ml.coarse_inv.resize(size_t(nc) * nc);
+    HIPCHK(hipMemcpyAsync(ml.coarse_inv.data(), inv, ml.coarse_inv.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          S.stream));
+    HIPCHK(hipStreamSynchronize(S.stream));
+    if (st) throw JdError(JD_ESETUP, "singular last level");
+    std::vector<double>().swap(ml.coarse_mat);
 }
 
 void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const jd_options *opt)
@@ -377,8 +404,10 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
     prm.max_levels = S.opt.max_levels;
     prm.z_drop = S.opt.z_drop;
     prm.inverse_factor = (S.opt.flags & JD_FLAG_LEVELS) == 0;
+    prm.host_coarse_inverse = false;
     std::string err = jdmi::build_multilevel(A, prm, S.ml);
     if (!err.empty()) throw JdError(JD_ESETUP, err);
+    invert_coarse_on_device(S);
     S.n2x2 = 0;
     for (auto &lv : S.ml.levels) S.n2x2 += lv.n2x2;
     int *dperm = S.mem.upload(S.ml.perm, S.stream);

@@ -108,6 +108,13 @@ void launch_gemv_vs(int n, int m, const double *V, int64_t ldv, const double *s,
 void launch_gemm_vs(int n, int m, int mout, const double *V, int64_t ldv, const double *S, int lds,
                     double *Vout, int64_t ldo, hipStream_t st);
 
+// Dense inverse by Gauss-Jordan elimination with partial pivoting (the exactly inverted
+// last level): a (n x n row-major) is destroyed, inv receives A^{-1}; colc is an n
+// workspace; status[0] becomes 1 if a pivot column is zero.
+void launch_gauss_jordan(int n, double *a, double *inv, double *colc, int *status, hipStream_t s);
+// a[i, j] *= sc[i] sc[j]
+void launch_scale_sym(int n, double *a, const double *sc, hipStream_t s);
+
 // elementwise helpers
 template <typename Tin, typename Tout>
 void launch_convert(int n, const Tin *x, Tout *y, double scale, hipStream_t s);

@@ -584,6 +584,100 @@ void launch_gemm_vs(int n, int m, int mout, const double *V, int64_t ldv, const 
 }
 
 // ---------------------------------------------------------------------------------
+// Gauss-Jordan inverse of the dense last level.  One step per pivot column: a single
+// workgroup picks the pivot row (largest modulus, lowest index on ties), swaps it in,
+// scales it and saves the column of factors; then every other row is updated.
+// ---------------------------------------------------------------------------------
+constexpr int kGJ = 1024;
+
+__global__ void __launch_bounds__(kGJ) k_gj_pivot(int n, int c, double *__restrict__ a, double *__restrict__ inv,
+                                                  double *__restrict__ colc, int *status)
+{
+    __shared__ double sv[kGJ];
+    __shared__ int si[kGJ];
+    const int t = threadIdx.x;
+    double best = -1.0;
+    int bi = n;
+    for (int r = c + t; r < n; r += kGJ) {
+        const double v = fabs(a[int64_t(r) * n + c]);
+        if (v > best) { best = v; bi = r; }
+    }
+    sv[t] = best;
+    si[t] = bi;
+    __syncthreads();
+    for (int o = kGJ / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            if (sv[t + o] > sv[t] || (sv[t + o] == sv[t] && si[t + o] < si[t])) { sv[t] = sv[t + o]; si[t] = si[t + o]; }
+        }
+        __syncthreads();
+    }
+    const int p = si[0];
+    if (!(sv[0] > 0.0) || p >= n) {
+        if (t == 0) status[0] = 1;
+        return;
+    }
+    if (p != c) {
+        for (int k = t; k < n; k += kGJ) {
+            const double x = a[int64_t(c) * n + k];
+            a[int64_t(c) * n + k] = a[int64_t(p) * n + k];
+            a[int64_t(p) * n + k] = x;
+            const double y = inv[int64_t(c) * n + k];
+            inv[int64_t(c) * n + k] = inv[int64_t(p) * n + k];
+            inv[int64_t(p) * n + k] = y;
+        }
+    }
+    __syncthreads();
+    const double pinv = 1.0 / a[int64_t(c) * n + c];
+    __syncthreads();
+    for (int k = t; k < n; k += kGJ) {
+        a[int64_t(c) * n + k] *= pinv;
+        inv[int64_t(c) * n + k] *= pinv;
+    }
+    for (int r = t; r < n; r += kGJ) colc[r] = (r == c) ? 0.0 : a[int64_t(r) * n + c];
+}
+
+__global__ void __launch_bounds__(kBlock) k_gj_elim(int n, int c, double *__restrict__ a, double *__restrict__ inv,
+                                                    const double *__restrict__ colc, const int *status)
+{
+    if (status[0]) return;
+    const int r = blockIdx.y;
+    const double f = colc[r];
+    if (f == 0.0) return;
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    if (k >= c) a[int64_t(r) * n + k] -= f * a[int64_t(c) * n + k];
+    inv[int64_t(r) * n + k] -= f * inv[int64_t(c) * n + k];
+}
+
+__global__ void __launch_bounds__(kBlock) k_eye(int n, double *__restrict__ a)
+{
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < int64_t(n) * n) a[i] = (i / n == i % n) ? 1.0 : 0.0;
+}
+
+void launch_gauss_jordan(int n, double *a, double *inv, double *colc, int *status, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_eye, dim3(nblocks(int64_t(n) * n)), dim3(kBlock), 0, s, n, inv);
+    for (int c = 0; c < n; ++c) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kGJ), 0, s, n, c, a, inv, colc, status);
+        hipLaunchKernelGGL(k_gj_elim, dim3(nblocks(n), n), dim3(kBlock), 0, s, n, c, a, inv, colc, status);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_scale_sym(int n, double *__restrict__ a, const double *__restrict__ sc)
+{
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < int64_t(n) * n) a[i] *= sc[i / n] * sc[i % n];
+}
+
+void launch_scale_sym(int n, double *a, const double *sc, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_scale_sym, dim3(nblocks(int64_t(n) * n)), dim3(kBlock), 0, s, n, a, sc);
+}
+
+// ---------------------------------------------------------------------------------
 // Elementwise helpers.
 // ---------------------------------------------------------------------------------
 template <typename Tin, typename Tout>

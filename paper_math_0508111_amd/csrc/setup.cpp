@@ -13,6 +13,7 @@
 #include "setup.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -84,6 +85,7 @@ MatchResult max_product_matching(const Csr &A)
     const int n = A.n;
     std::vector<double> lmax(n, -kInf);
     std::vector<double> cost(A.val.size());
+#pragma omp parallel for schedule(dynamic, 4096)
     for (int i = 0; i < n; ++i) {
         for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p)
             if (A.val[p] != 0.0) lmax[i] = std::max(lmax[i], std::log(std::fabs(A.val[p])));
@@ -343,14 +345,20 @@ static std::string factor_level(const Csr &A, const SetupParams &prm, const std:
             if (A.col[p] != i) s += std::fabs(sv(p, i));
         return s;
     };
-    auto push1 = [&](int i) {
-        const double dii = sget(i, i);
-        if (!(std::fabs(dii) > 0.0)) return;
-        const double q = colsum1(i) / std::fabs(dii);
-        cands.push_back({i, -1, q, int(A.ptr[i + 1] - A.ptr[i]), 1.0 / dii, 0.0, 0.0});
-    };
-    for (auto [a, b] : blocks) {
-        if (b < 0) { push1(a); continue; }
+    // every block is evaluated on its own (in parallel), then the candidates are
+    // collected in block order
+    std::vector<std::array<Cand, 2>> per(blocks.size());
+    std::vector<int> nper(blocks.size(), 0);
+#pragma omp parallel for schedule(dynamic, 2048)
+    for (int64_t bi = 0; bi < int64_t(blocks.size()); ++bi) {
+        const int a = blocks[bi].first, b = blocks[bi].second;
+        auto put = [&](const Cand &c) { per[bi][nper[bi]++] = c; };
+        auto push1l = [&](int i) {
+            const double dii = sget(i, i);
+            if (!(std::fabs(dii) > 0.0)) return;
+            put({i, -1, colsum1(i) / std::fabs(dii), int(A.ptr[i + 1] - A.ptr[i]), 1.0 / dii, 0.0, 0.0});
+        };
+        if (b < 0) { push1l(a); continue; }
         const double saa = sget(a, a), sab = sget(a, b), sbb = sget(b, b);
         const double det = saa * sbb - sab * sab;
         const double scale = std::max({std::fabs(saa), std::fabs(sbb), std::fabs(sab)});
@@ -383,12 +391,14 @@ static std::string factor_level(const Csr &A, const SetupParams &prm, const std:
         const double d1b = (sbb != 0.0) ? colsum1(b) / std::fabs(sbb) : kInf;
         if (d2 < std::min(d1a, d1b)) {
             int deg = int(A.ptr[a + 1] - A.ptr[a] + A.ptr[b + 1] - A.ptr[b]);
-            cands.push_back({a, b, std::max(cs_a, cs_b), deg, i00, i01, i11});
+            put({a, b, std::max(cs_a, cs_b), deg, i00, i01, i11});
         } else {
-            push1(a);
-            push1(b);
+            push1l(a);
+            push1l(b);
         }
     }
+    for (size_t bi = 0; bi < blocks.size(); ++bi)
+        for (int t = 0; t < nper[bi]; ++t) cands.push_back(per[bi][t]);
     // greedy independent set of the compressed graph: fewest couplings first
     std::vector<int> order(cands.size());
     std::iota(order.begin(), order.end(), 0);
@@ -721,10 +731,15 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
         std::vector<double> dense(size_t(nc) * nc, 0.0);
         for (int i = 0; i < nc; ++i)
             for (int64_t p = S.ptr[i]; p < S.ptr[i + 1]; ++p) dense[size_t(i) * nc + S.col[p]] = S.val[p];
-        if (nc > 0 && !dense_inverse(nc, dense)) return "singular last level";
-        for (int i = 0; i < nc; ++i)
-            for (int j = 0; j < nc; ++j) dense[size_t(i) * nc + j] *= cum_prev[i] * cum_prev[j];
-        out.coarse_inv.swap(dense);
+        if (prm.host_coarse_inverse) {
+            if (nc > 0 && !dense_inverse(nc, dense)) return "singular last level";
+            for (int i = 0; i < nc; ++i)
+                for (int j = 0; j < nc; ++j) dense[size_t(i) * nc + j] *= cum_prev[i] * cum_prev[j];
+            out.coarse_inv.swap(dense);
+        } else {
+            out.coarse_mat.swap(dense);
+            out.coarse_scale = cum_prev;
+        }
     }
     out.levels.resize(pend.size());
     long long nnz_fact = 0;

@@ -45,6 +45,7 @@ struct SetupParams {
     int max_levels = 64;
     double z_drop = 1e-2;     // relative drop tolerance of the explicit inverse factor (< 0: none)
     bool inverse_factor = true;
+    bool host_coarse_inverse = true;  // false: leave the dense last level for the device to invert
 };
 
 // Explicit inverse of the unit lower triangular factor of all levels, Z ~ L^{-1}
@@ -91,6 +92,8 @@ struct Multilevel {
     std::vector<Level> levels;
     int coarse_off = 0, coarse_n = 0;
     std::vector<double> coarse_inv;  // coarse_n x coarse_n row-major, scalings folded in
+    std::vector<double> coarse_mat;  // the last Schur complement itself (when inverted on the device)
+    std::vector<double> coarse_scale;  // its cumulative scaling: inverse = diag(s) S^{-1} diag(s)
     long long nnz_lower_A = 0;
     double fill = 0.0;
     double seconds = 0.0;
