@@ -32,7 +32,36 @@ def parse():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48, help="0 disables the serving leg")
+    ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="setup, then only launches of the dominant kernel and a 256 MB copy "
+                         "(for hardware counter runs)")
     return ap.parse_args()
+
+
+def kernels_only(jd, torch, L, reps=20):
+    """Launches for counter collection: the binary32 inverse-factor product (Z and Z^T
+    alternately) and, as the calibration reference, a plain 256 MB device copy."""
+    print("# kernels-only: setup", file=sys.stderr, flush=True)
+    prob = jd.Problem(L, 16.5, 0, 0.0, precision="mixed")
+    print("# kernels-only: setup done", file=sys.stderr, flush=True)
+    pc = prob.precond()
+    n = L ** 3
+    s = torch.cuda.current_stream()
+    x = torch.randn(n, dtype=torch.float32, device="cuda")
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    for r in range(reps):
+        pc.factor_product(x, y, transpose=r % 2, stream=s)
+    a = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernels_only": True, "nnz": pc.factor_nnz(), "n": n, "reps": reps,
+                      "copy_bytes_each_way": a.numel() * 4}), flush=True)
+    pc.close()
+    prob.close()
 
 
 def stencil_bandwidth(jd, torch, L, W, seed, reps=50):
@@ -90,6 +119,47 @@ def factor_roofline(torch, prob, n, reps=40):
             "bytes_per_launch": int(b), "nnz": int(nnz), "avg_us": round(us, 2), "reps": reps}
 
 
+def serving(jd, nreq, workers, warm=16):
+    """Continuous batching of the mixed request stream: a closed-loop warm-up measures
+    the saturated request rate, then nreq requests arrive as a Poisson process at 0.8
+    of that rate; latency = submission -> completion."""
+    import numpy as np
+    from tests import seeded_inputs
+    reqs = seeded_inputs.serving_requests(warm + nreq)
+    mk = lambda r: jd.Server.request(r["L"], r["W"], r["seed"], r["sigma"], r["k"], 1e-10, "mixed")
+    srv = jd.Server(workers=workers)
+    t0 = time.time()
+    tk = [srv.submit(mk(r)) for r in reqs[:warm]]
+    for t in tk:
+        srv.wait(t)
+    rate = warm / (time.time() - t0)
+    lam = 0.8 * rate
+    arrivals = seeded_inputs.poisson_arrivals(nreq, lam)
+    print(f"# serving: saturated {rate:.2f} req/s, Poisson arrivals at {lam:.2f} req/s", file=sys.stderr, flush=True)
+    t0 = time.time()
+    tickets = []
+    for a, r in zip(arrivals, reqs[warm:]):
+        dt = t0 + a - time.time()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(mk(r)))
+    res = [srv.wait(t) for t in tickets]
+    span = time.time() - t0
+    srv.close()
+    lat = np.array([r["latency_s"] for r in res])
+    ok = sum(r["status"] == 0 for r in res)
+    pairs = sum(r["n_converged"] for r in res)
+    return {"requests": nreq, "workers": workers, "saturated_rps": round(rate, 3), "arrival_rps": round(lam, 3),
+            "completed_ok": int(ok), "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+            "p50_setup_s": round(float(np.percentile([r["setup_s"] for r in res], 50)), 3),
+            "p50_solve_s": round(float(np.percentile([r["solve_s"] for r in res], 50)), 3),
+            "p50_queued_s": round(float(np.percentile([r["queued_s"] for r in res], 50)), 3),
+            "eigenpairs_per_s": round(pairs / span, 3),
+            "workload": "L in {20..60}, W in {12, 16.5, 21}, sigma ~ U[-1,1], k in 1..10, seeds 1e6+i, "
+                        "FP32 inner / FP64 outer, tol 1e-10"}
+
+
 def cpu_baseline(k):
     """The oracle (exact multifrontal LDL^T + shift-and-invert Lanczos, binary64) on a
     bounded sample: the same method parameters on the 30^3 lattice."""
@@ -122,6 +192,9 @@ def main():
     import paper_math_0508111_amd as jd
 
     torch.cuda.set_device(0)
+    if a.kernels_only:
+        kernels_only(jd, torch, a.L)
+        return
     L, W, seed, sigma, k, tol = a.L, 16.5, 0, 0.0, a.k, 1e-10
     t0 = time.time()
     prob = jd.Problem(L, W, seed, sigma, precision="mixed")
@@ -175,6 +248,8 @@ def main():
     out["roofline"] = factor_roofline(torch, prob, L ** 3)
     out["stencil"] = stencil_bandwidth(jd, torch, L, W, seed)
     prob.close()
+    if a.serve_requests > 0:
+        out["serving"] = serving(jd, a.serve_requests, a.serve_workers)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(k)
     print(json.dumps(out), flush=True)

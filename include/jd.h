@@ -75,8 +75,9 @@ enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
  *  max_inner  SQMR steps per correction equation (0 -> 40).
  *  switch_tol the correction operator uses sigma until ||r|| < switch_tol ||A||_inf,
  *             then the Ritz value theta (0 -> 1e-3).
- *  flags      bit 0 (JD_FLAG_EAGER): launch the inner iteration kernel by kernel instead
- *             of replaying it as a captured HIP graph (same arithmetic, same results).
+ *  flags      bit 0 (JD_FLAG_GRAPHS): replay the inner iteration as a captured HIP graph
+ *             instead of launching it kernel by kernel (same kernels in the same order,
+ *             same results; the serving workers always launch kernel by kernel).
  *             bit 1 (JD_FLAG_LEVELS): apply the factorisation level by level (two
  *             dependent sparse passes per level) instead of through Z.
  *  stream     stream for the solve's device work (NULL: a library-created blocking stream).
@@ -97,7 +98,7 @@ typedef struct jd_options {
     void *stream;
 } jd_options;
 
-enum { JD_FLAG_EAGER = 1, JD_FLAG_LEVELS = 2 };
+enum { JD_FLAG_GRAPHS = 1, JD_FLAG_LEVELS = 2 };
 
 /* Statistics of a solve (the paper's Tables 3-5 quantities plus timings). */
 typedef struct jd_info {
@@ -205,6 +206,58 @@ int jd_precond_factor_product(jd_precond *p, int precision, int transpose, const
  */
 int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int pcols,
                             const double *d_b, double *d_x, double rtol, int maxit, int *its);
+
+/*
+ * Serving: continuous batching of independent solve requests (the disorder averaging
+ * of section 3 needs many realisations).  A request is admitted when a worker is free
+ * and its estimated device footprint fits the HBM budget; admitted requests run their
+ * host setup and their device solve concurrently, each on its own stream, so work of
+ * requests that arrived at different times overlaps on the GPU (each worker launches
+ * on its own non-blocking stream).  Every request's
+ * arithmetic is independent of the others (deterministic kernels and setup), so its
+ * result is identical alone and in the mix.  All jd_server_* calls are thread-safe.
+ */
+typedef struct jd_request {
+    int L;
+    double W;
+    uint64_t seed;
+    double sigma;
+    int k;            /* 1 .. 64 */
+    double tol;
+    int precision;    /* JD_FP64, JD_MIXED or JD_MIXED_FACTORS */
+    int flags;        /* jd_options flags (JD_FLAG_LEVELS; JD_FLAG_GRAPHS is ignored) */
+} jd_request;
+
+typedef struct jd_result {
+    int status;           /* JD_OK, JD_ENOCONV or a negative code */
+    int k, n_converged, outer_its, inner_its;
+    double evals[64];     /* sorted by (|lambda - sigma|, lambda); NaN past n_converged */
+    double resid[64];     /* ||A x - lambda x|| / ||A||_inf */
+    double queued_s;      /* submission -> admission */
+    double setup_s;       /* host setup and upload */
+    double solve_s;       /* device solve */
+    double latency_s;     /* submission -> completion */
+    size_t device_bytes;  /* footprint reserved for the request */
+    char error[160];      /* message of a failed request ("" on success) */
+} jd_result;
+
+typedef struct jd_server jd_server;
+
+/* hbm_budget_bytes: device memory the server may reserve (0 -> 80% of free memory);
+ * workers: concurrently active requests (0 -> 8); setup_threads: host threads per
+ * setup (0 -> hardware threads / workers). */
+int jd_server_create(size_t hbm_budget_bytes, int workers, int setup_threads, jd_server **out);
+/* Queue a request (never blocks); *ticket identifies it.  JD_EINVAL for bad fields, or
+ * a footprint larger than the whole budget. */
+int jd_server_submit(jd_server *s, const jd_request *req, uint64_t *ticket);
+/* 0: done (result filled, ticket released); 1: still queued or running; < 0: error. */
+int jd_server_poll(jd_server *s, uint64_t ticket, jd_result *res);
+/* Block until the request is done; returns 0 with the result, or a negative code. */
+int jd_server_wait(jd_server *s, uint64_t ticket, jd_result *res);
+/* Estimated device footprint of a request (the admission test). */
+size_t jd_server_footprint(const jd_request *req);
+/* Finish queued and running requests, then release everything. */
+void jd_server_destroy(jd_server *s);
 
 /*
  * Host setup steps on their own (no GPU involved), for checks of the setup logic.

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libjdmi.so")
 
 JD_OK, JD_ENOCONV, JD_EINVAL, JD_ENOMEM, JD_EDEVICE, JD_ESETUP, JD_ENOTIMPL = 0, 1, -1, -2, -3, -4, -5
 JD_FP64, JD_MIXED, JD_MIXED_FACTORS = 0, 1, 2
-JD_FLAG_EAGER = 1
+JD_FLAG_GRAPHS = 1
 JD_FLAG_LEVELS = 2
 _PREC = {"fp64": JD_FP64, "mixed": JD_MIXED, "mixed_factors": JD_MIXED_FACTORS, JD_FP64: JD_FP64,
          JD_MIXED: JD_MIXED, JD_MIXED_FACTORS: JD_MIXED_FACTORS}
@@ -37,6 +37,26 @@ class Options(ctypes.Structure):
                 ("flags", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int), ("W", ctypes.c_double), ("seed", ctypes.c_uint64), ("sigma", ctypes.c_double),
+                ("k", ctypes.c_int), ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("k", ctypes.c_int), ("n_converged", ctypes.c_int),
+                ("outer_its", ctypes.c_int), ("inner_its", ctypes.c_int), ("evals", ctypes.c_double * 64),
+                ("resid", ctypes.c_double * 64), ("queued_s", ctypes.c_double), ("setup_s", ctypes.c_double),
+                ("solve_s", ctypes.c_double), ("latency_s", ctypes.c_double), ("device_bytes", ctypes.c_size_t),
+                ("error", ctypes.c_char * 160)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("evals", "resid", "error")}
+        d["error"] = self.error.decode(errors="replace")
+        d["evals"] = np.array(self.evals[: self.k])
+        d["resid"] = np.array(self.resid[: self.k])
+        return d
+
+
 class Info(ctypes.Structure):
     _fields_ = [("n_converged", ctypes.c_int), ("outer_its", ctypes.c_int), ("inner_its", ctypes.c_int),
                 ("levels", ctypes.c_int), ("n_2x2", ctypes.c_int), ("coarse_n", ctypes.c_int),
@@ -50,7 +70,9 @@ class Info(ctypes.Structure):
 EXPORTS = ["jd_solve", "jd_setup", "jd_problem_solve", "jd_problem_info", "jd_problem_set_precision", "jd_problem_free", "jd_gen_diag",
            "jd_stencil_spmv", "jd_precond_create", "jd_precond_apply", "jd_precond_levels", "jd_precond_free", "jd_problem_precond", "jd_precond_factor_nnz",
            "jd_precond_factor_product",
-           "jd_problem_linear_solve", "jd_last_error", "jd_version"]
+           "jd_problem_linear_solve", "jd_last_error", "jd_version", "jd_server_create", "jd_server_submit",
+           "jd_server_poll", "jd_server_wait", "jd_server_footprint", "jd_server_destroy",
+           "jd_host_matching", "jd_host_split_cycles", "jd_host_factor"]
 
 _lib = None
 
@@ -82,6 +104,12 @@ def lib():
         "jd_precond_factor_nnz": (I, [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I)]),
         "jd_precond_factor_product": (I, [P, I, I, P, P, P]),
         "jd_problem_linear_solve": (I, [P, D, P, I, P, P, D, I, ctypes.POINTER(I)]),
+        "jd_server_create": (I, [ctypes.c_size_t, I, I, ctypes.POINTER(P)]),
+        "jd_server_submit": (I, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+        "jd_server_poll": (I, [P, ctypes.c_uint64, ctypes.POINTER(Result)]),
+        "jd_server_wait": (I, [P, ctypes.c_uint64, ctypes.POINTER(Result)]),
+        "jd_server_footprint": (ctypes.c_size_t, [ctypes.POINTER(Request)]),
+        "jd_server_destroy": (None, [P]),
         "jd_last_error": (ctypes.c_char_p, []),
         "jd_version": (ctypes.c_char_p, []),
     }
@@ -253,3 +281,48 @@ def stencil_spmv(L, eps, shift, x, y, precision="fp64", stream=None):
 
 def version():
     return lib().jd_version().decode()
+
+
+class Server:
+    """jd_server_*: continuous batching of independent solve requests."""
+
+    def __init__(self, hbm_budget_bytes=0, workers=0, setup_threads=0):
+        h = ctypes.c_void_p()
+        _check(lib().jd_server_create(int(hbm_budget_bytes), int(workers), int(setup_threads), ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def request(L, W, seed, sigma, k, tol=1e-10, precision="mixed", flags=0):
+        return Request(int(L), float(W), int(seed), float(sigma), int(k), float(tol), _PREC[precision], int(flags))
+
+    def submit(self, req):
+        t = ctypes.c_uint64()
+        _check(lib().jd_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket):
+        r = Result()
+        rc = lib().jd_server_poll(self._h, ticket, ctypes.byref(r))
+        if rc < 0:
+            _check(rc)
+        return r.as_dict() if rc == 0 else None
+
+    def wait(self, ticket):
+        r = Result()
+        _check(lib().jd_server_wait(self._h, ticket, ctypes.byref(r)))
+        return r.as_dict()
+
+    @staticmethod
+    def footprint(req):
+        return lib().jd_server_footprint(ctypes.byref(req))
+
+    def close(self):
+        if self._h:
+            lib().jd_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,7 +16,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <stdexcept>
 #include <type_traits>
@@ -50,6 +52,15 @@ double now_s()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Allocation, freeing, synchronous copies and graph capture are serialised process-wide:
+// with several solves running on their own threads (serving), an implicitly
+// synchronising call must never meet another thread's stream capture.
+std::mutex &dev_mutex()
+{
+    static std::mutex m;
+    return m;
+}
+
 // Device allocation list owned by a handle.
 struct DevMem {
     std::vector<void *> ptrs;
@@ -59,21 +70,29 @@ struct DevMem {
     {
         if (count == 0) count = 1;
         void *p = nullptr;
+        std::lock_guard<std::mutex> g(dev_mutex());
         HIPCHK(hipMalloc(&p, count * sizeof(T)));
         ptrs.push_back(p);
         bytes += count * sizeof(T);
         return static_cast<T *>(p);
     }
+    // The copy is ordered on s, the stream whose kernels read the buffer: a copy on
+    // the legacy stream is not ordered before work on a non-blocking stream (serving
+    // workers), so a kernel there could read the buffer before the data arrived.
+    // Complete on return, so v may be a temporary.
     template <typename T>
     T *upload(const std::vector<T> &v, hipStream_t s)
     {
         T *p = alloc<T>(v.size());
-        (void)s;
-        if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        if (!v.empty()) {
+            HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
         return p;
     }
     void release()
     {
+        std::lock_guard<std::mutex> g(dev_mutex());
         for (void *p : ptrs) (void)hipFree(p);
         ptrs.clear();
         bytes = 0;
@@ -212,7 +231,10 @@ struct DevPrecond {
         n = ml.n;
         perm = const_cast<int *>(dperm);
         levels.clear();
+        inv = !ml.z.ptr.empty();
+        // the level-by-level factors are needed on the device only without Z
         for (const auto &L : ml.levels) {
+            if (inv) break;
             jdmi::DevLevel<T> d{};
             d.off = L.off;
             d.nB = L.nB;
@@ -233,7 +255,6 @@ struct DevPrecond {
         cinv = mem.upload(cast_vec<T>(ml.coarse_inv), s);
         w = mem.alloc<T>(n);
         x = mem.alloc<T>(n);
-        inv = !ml.z.ptr.empty();
         if (inv) {
             site_of = mem.upload(ml.z.site_of, s);
             cidx = mem.upload(ml.z.coarse_idx, s);
@@ -329,7 +350,7 @@ void check_problem_args(int L, double W, double sigma, const jd_options *opt)
         if (opt->coarse_max < 0 || opt->coarse_max > 8192) throw JdError(JD_EINVAL, "coarse_max must be in [0, 8192]");
         if (opt->jmin < 0 || opt->jmax < 0 || opt->jmax > 120) throw JdError(JD_EINVAL, "jmin/jmax out of range");
         if (opt->max_inner < 0 || opt->max_outer < 0 || opt->max_levels < 0) throw JdError(JD_EINVAL, "negative iteration cap");
-        if (opt->flags & ~(JD_FLAG_EAGER | JD_FLAG_LEVELS)) throw JdError(JD_EINVAL, "unknown flag bits");
+        if (opt->flags & ~(JD_FLAG_GRAPHS | JD_FLAG_LEVELS)) throw JdError(JD_EINVAL, "unknown flag bits");
         if (!std::isfinite(opt->z_drop)) throw JdError(JD_EINVAL, "non-finite option");
         if (!std::isfinite(opt->drop_tol) || !std::isfinite(opt->kappa) || opt->kappa < 0 ||
             !std::isfinite(opt->agg_tau) || !std::isfinite(opt->schur_tol) || !std::isfinite(opt->switch_tol))
@@ -503,10 +524,10 @@ struct SqmrBufs {
     int *flags_host;  // pinned, two slots
 };
 
-// Simplified QMR on the device.  The start and one step are each captured once per
-// projection width p into a HIP graph and replayed; every scalar (alpha, theta, c,
-// tau, beta, the shift and the stop flag) lives in device memory, and the host reads
-// only the stop flag, one step behind the device.
+// Simplified QMR on the device.  Every scalar (alpha, theta, c, tau, beta, the shift
+// and the stop flag) lives in device memory and the host reads only the stop flag, one
+// step behind the device.  Optionally the start and one step are captured once per
+// projection width p into a HIP graph and replayed.
 template <typename T, typename P>
 struct Solver {
     Setup &S;
@@ -536,13 +557,17 @@ struct Solver {
         B.red = mem.alloc<double>(256);
         B.coef = mem.alloc<double>(256);
         B.g = mem.alloc<double>(256);
-        HIPCHK(hipHostMalloc((void **)&B.flags_host, 2 * sizeof(int), hipHostMallocDefault));
+        {
+            std::lock_guard<std::mutex> g(dev_mutex());
+            HIPCHK(hipHostMalloc((void **)&B.flags_host, 2 * sizeof(int), hipHostMallocDefault));
+        }
         HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
         cache.resize(130);
     }
     ~Solver()
     {
+        std::lock_guard<std::mutex> g(dev_mutex());
         for (auto &c : cache) {
             if (c.init) (void)hipGraphExecDestroy(c.init);
             if (c.step) (void)hipGraphExecDestroy(c.step);
@@ -588,6 +613,7 @@ struct Solver {
     {
         hipGraph_t g = nullptr;
         hipGraphExec_t e = nullptr;
+        std::lock_guard<std::mutex> lk(dev_mutex());
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
         f();
         HIPCHK(hipStreamEndCapture(s, &g));
@@ -607,6 +633,7 @@ struct Solver {
             if (p >= int(cache.size())) throw JdError(JD_EINVAL, "projection too wide");
             pr = &cache[p];
             if (pr->init && (pr->Qt != Qt || pr->Y != Y || pr->M != dM)) {
+                std::lock_guard<std::mutex> g(dev_mutex());
                 (void)hipGraphExecDestroy(pr->init);
                 (void)hipGraphExecDestroy(pr->step);
                 pr->init = pr->step = nullptr;
@@ -618,15 +645,22 @@ struct Solver {
                 pr->Y = Y;
                 pr->M = dM;
             }
-            HIPCHK(hipGraphLaunch(pr->init, s));
+            {
+                std::lock_guard<std::mutex> g(dev_mutex());
+                HIPCHK(hipGraphLaunch(pr->init, s));
+            }
         } else {
             enqueue_init(Qt, Y, p, dM);
         }
         // one step of look-ahead: the host reads the stop flag of step j-1 while step j runs
         int launched = 0;
         while (launched < maxit) {
-            if (graphs) HIPCHK(hipGraphLaunch(pr->step, s));
-            else enqueue_step(Qt, Y, p, dM);
+            if (graphs) {
+                std::lock_guard<std::mutex> g(dev_mutex());
+                HIPCHK(hipGraphLaunch(pr->step, s));
+            } else {
+                enqueue_step(Qt, Y, p, dM);
+            }
             const int slot = launched & 1;
             ++launched;
             HIPCHK(hipMemcpyAsync(&B.flags_host[slot], &B.st->done, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -673,7 +707,7 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
     const double anorm = S.anorm;
     const double sigma = S.sigma;
 
-    Solver<T, P> sv(S, pc, eps, (o.flags & JD_FLAG_EAGER) == 0);
+    Solver<T, P> sv(S, pc, eps, (o.flags & JD_FLAG_GRAPHS) != 0);
     DevMem mem;
     double *V = mem.alloc<double>(size_t(n) * jmax);
     double *AV = mem.alloc<double>(size_t(n) * jmax);
@@ -784,7 +818,7 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
                 d2h(&rr, red, 1);
                 const double rfresh = std::sqrt(std::max(rr, 0.0) / q2[1]);
                 if (rfresh <= tol * anorm) {
-                    jdmi::launch_axpby_d(n, 1.0 / std::sqrt(q2[1]), u64, 0.0, Q + size_t(nq) * n, s);
+                    jdmi::launch_convert<double, double>(n, u64, Q + size_t(nq) * n, 1.0 / std::sqrt(q2[1]), s);
                     lam[nq] = rq;
                     // preconditioner image of the new locked vector, and its row of Qt^T Y
                     jdmi::launch_convert<double, T>(n, Q + size_t(nq) * n, Qt + size_t(nq) * n, 1.0, s);
@@ -1285,7 +1319,7 @@ int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int 
         auto run = [&](auto tag, const auto &pc, const auto *eps) {
             using T = decltype(tag);
             using PC = std::decay_t<decltype(pc)>;
-            Solver<T, PC> sv(S, pc, eps, (S.opt.flags & JD_FLAG_EAGER) == 0);
+            Solver<T, PC> sv(S, pc, eps, (S.opt.flags & JD_FLAG_GRAPHS) != 0);
             DevMem mem;
             const int pc_ = pcols;
             T *Qt = mem.alloc<T>(size_t(n) * std::max(pc_, 1));
@@ -1322,6 +1356,219 @@ int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int 
         else run(double(0), S.pc64, S.eps64);
         return JD_OK;
     });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Serving: continuous batching of independent requests.
+// ---------------------------------------------------------------------------------
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <set>
+#include <thread>
+
+namespace {
+
+double wall_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct ServerReq {
+    uint64_t id;
+    jd_request r;
+    double t_submit;
+    size_t est;
+};
+
+size_t footprint_estimate(const jd_request &r)
+{
+    const double n = double(r.L) * r.L * r.L;
+    const int jmin = std::max(r.k + 5, 10), jmax = 2 * jmin;
+    const double nc = std::min(n, 8192.0);
+    // factors in both precisions (inverse factor ~ 100 entries per unknown, twice,
+    // with padding), search space V, AV and restart buffer, projection blocks, SQMR
+    // and preconditioner work vectors, the dense last level, and a fixed reserve
+    const double per_unknown = 4800.0 + 24.0 * jmax + 32.0 * (r.k + 1) + 200.0;
+    return size_t(n * per_unknown + nc * nc * 12.0 + 64.0 * (1 << 20));
+}
+
+void check_request(const jd_request &r)
+{
+    check_problem_args(r.L, r.W, r.sigma, nullptr);
+    const long long n = (long long)r.L * r.L * r.L;
+    if (r.k < 1 || r.k > 64 || r.k > n) throw JdError(JD_EINVAL, "k must satisfy 1 <= k <= min(n, 64)");
+    if (!(r.tol >= 1e-14 && r.tol < 1.0)) throw JdError(JD_EINVAL, "tol must be in [1e-14, 1)");
+    if (r.precision != JD_FP64 && r.precision != JD_MIXED && r.precision != JD_MIXED_FACTORS)
+        throw JdError(JD_EINVAL, "unknown precision");
+    if (r.flags & ~(JD_FLAG_GRAPHS | JD_FLAG_LEVELS)) throw JdError(JD_EINVAL, "unknown flag bits");
+}
+
+}  // namespace
+
+struct jd_server {
+    std::mutex m;
+    std::condition_variable cv_work, cv_done;
+    std::deque<ServerReq> queue;
+    std::set<uint64_t> pending;
+    std::map<uint64_t, jd_result> done;
+    size_t budget = 0, reserved = 0;
+    int setup_threads = 1;
+    bool stop = false;
+    uint64_t next_id = 1;
+    std::vector<std::thread> workers;
+
+    void run_one(const ServerReq &q, hipStream_t stream)
+    {
+        jd_result res;
+        std::memset(&res, 0, sizeof(res));
+        for (int i = 0; i < 64; ++i) res.evals[i] = res.resid[i] = std::nan("");
+        res.k = q.r.k;
+        res.device_bytes = q.est;
+        const double t_admit = wall_s();
+        res.queued_s = t_admit - q.t_submit;
+        jdmi::set_setup_threads(setup_threads);
+        jd_options o{};
+        o.precision = q.r.precision;
+        o.flags = q.r.flags & ~JD_FLAG_GRAPHS;  // workers launch eagerly
+        o.stream = stream;
+        jd_problem *p = nullptr;
+        int rc = jd_setup(q.r.L, q.r.W, q.r.seed, q.r.sigma, &o, &p);
+        const double t_setup = wall_s();
+        res.setup_s = t_setup - t_admit;
+        if (rc == JD_OK) {
+            jd_info info{};
+            rc = jd_problem_solve(p, q.r.k, q.r.tol, res.evals, nullptr, nullptr, res.resid, &info);
+            res.n_converged = info.n_converged;
+            res.outer_its = info.outer_its;
+            res.inner_its = info.inner_its;
+            res.solve_s = info.solve_s;
+        }
+        if (rc != JD_OK && rc != JD_ENOCONV) std::snprintf(res.error, sizeof(res.error), "%s", jd_last_error());
+        if (p) jd_problem_free(p);
+        res.status = rc;
+        res.latency_s = wall_s() - q.t_submit;
+        std::lock_guard<std::mutex> g(m);
+        reserved -= q.est;
+        pending.erase(q.id);
+        done[q.id] = res;
+        cv_done.notify_all();
+        cv_work.notify_all();
+    }
+
+    void worker()
+    {
+        hipStream_t stream = nullptr;
+        if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+        while (true) {
+            ServerReq q;
+            {
+                std::unique_lock<std::mutex> lk(m);
+                // first come, first admitted: the head of the queue waits for memory
+                cv_work.wait(lk, [&] {
+                    return (stop && queue.empty()) || (!queue.empty() && reserved + queue.front().est <= budget);
+                });
+                if (queue.empty()) break;
+                q = queue.front();
+                queue.pop_front();
+                reserved += q.est;
+            }
+            run_one(q, stream);
+        }
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+extern "C" {
+
+size_t jd_server_footprint(const jd_request *req)
+{
+    return req ? footprint_estimate(*req) : 0;
+}
+
+int jd_server_create(size_t hbm_budget_bytes, int workers, int setup_threads, jd_server **out)
+{
+    return guarded([&] {
+        if (!out) throw JdError(JD_EINVAL, "out must not be NULL");
+        if (workers < 0 || workers > 256 || setup_threads < 0) throw JdError(JD_EINVAL, "bad worker counts");
+        *out = nullptr;
+        auto s = std::make_unique<jd_server>();
+        if (hbm_budget_bytes == 0) {
+            size_t fr = 0, tot = 0;
+            HIPCHK(hipMemGetInfo(&fr, &tot));
+            hbm_budget_bytes = size_t(0.8 * double(fr));
+        }
+        s->budget = hbm_budget_bytes;
+        const int w = workers ? workers : 8;
+        const int hw = std::max(1u, std::thread::hardware_concurrency());
+        s->setup_threads = setup_threads ? setup_threads : std::max(1, hw / w);
+        for (int i = 0; i < w; ++i) s->workers.emplace_back([p = s.get()] { p->worker(); });
+        *out = s.release();
+        return JD_OK;
+    });
+}
+
+int jd_server_submit(jd_server *s, const jd_request *req, uint64_t *ticket)
+{
+    return guarded([&] {
+        if (!s || !req || !ticket) throw JdError(JD_EINVAL, "NULL argument");
+        check_request(*req);
+        const size_t est = footprint_estimate(*req);
+        std::lock_guard<std::mutex> g(s->m);
+        if (est > s->budget) throw JdError(JD_EINVAL, "request footprint exceeds the server's HBM budget");
+        if (s->stop) throw JdError(JD_EINVAL, "server is shutting down");
+        const uint64_t id = s->next_id++;
+        s->queue.push_back({id, *req, wall_s(), est});
+        s->pending.insert(id);
+        *ticket = id;
+        s->cv_work.notify_all();
+        return JD_OK;
+    });
+}
+
+int jd_server_poll(jd_server *s, uint64_t ticket, jd_result *res)
+{
+    return guarded([&] {
+        if (!s || !res) throw JdError(JD_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> g(s->m);
+        auto it = s->done.find(ticket);
+        if (it != s->done.end()) {
+            *res = it->second;
+            s->done.erase(it);
+            return 0;
+        }
+        if (s->pending.count(ticket)) return 1;
+        throw JdError(JD_EINVAL, "unknown ticket");
+    });
+}
+
+int jd_server_wait(jd_server *s, uint64_t ticket, jd_result *res)
+{
+    return guarded([&] {
+        if (!s || !res) throw JdError(JD_EINVAL, "NULL argument");
+        std::unique_lock<std::mutex> lk(s->m);
+        if (!s->pending.count(ticket) && !s->done.count(ticket)) throw JdError(JD_EINVAL, "unknown ticket");
+        s->cv_done.wait(lk, [&] { return s->done.count(ticket) > 0; });
+        auto it = s->done.find(ticket);
+        *res = it->second;
+        s->done.erase(it);
+        return 0;
+    });
+}
+
+void jd_server_destroy(jd_server *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(s->m);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    for (auto &t : s->workers) t.join();
+    delete s;
 }
 
 }  // extern "C"

@@ -23,6 +23,13 @@ inline int red_blocks(int64_t n)
     return b < 1 ? 1 : (b > kRedBlocks ? kRedBlocks : b);
 }
 
+// streamed-once matrix data: non-temporal loads keep the gathered vector in cache
+template <typename T>
+__device__ inline T nt_load(const T *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
 __device__ inline double wave_sum(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -353,14 +360,16 @@ __global__ void __launch_bounds__(kBlock) k_hyb_spmv(int nlong, const int *__res
         Tx a0 = Tx(0), a1 = Tx(0), a2 = Tx(0), a3 = Tx(0);
         int64_t p = b + lane;
         for (; p + 192 < e; p += 256) {
-            const int c0 = long_col[p], c1 = long_col[p + 64], c2 = long_col[p + 128], c3 = long_col[p + 192];
-            const Tv v0 = long_val[p], v1 = long_val[p + 64], v2 = long_val[p + 128], v3 = long_val[p + 192];
+            const int c0 = nt_load(long_col + p), c1 = nt_load(long_col + p + 64);
+            const int c2 = nt_load(long_col + p + 128), c3 = nt_load(long_col + p + 192);
+            const Tv v0 = nt_load(long_val + p), v1 = nt_load(long_val + p + 64);
+            const Tv v2 = nt_load(long_val + p + 128), v3 = nt_load(long_val + p + 192);
             a0 += Tx(v0) * x[c0];
             a1 += Tx(v1) * x[c1];
             a2 += Tx(v2) * x[c2];
             a3 += Tx(v3) * x[c3];
         }
-        for (; p < e; p += 64) a0 += Tx(long_val[p]) * x[long_col[p]];
+        for (; p < e; p += 64) a0 += Tx(nt_load(long_val + p)) * x[nt_load(long_col + p)];
         Tx a = (a0 + a1) + (a2 + a3);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
@@ -380,14 +389,14 @@ __global__ void __launch_bounds__(kBlock) k_hyb_spmv(int nlong, const int *__res
     int j = 0;
     for (; j + 3 < w; j += 4) {
         const int64_t o = int64_t(j) * 64;
-        const int c0 = c[o], c1 = c[o + 64], c2 = c[o + 128], c3 = c[o + 192];
-        const Tv v0 = v[o], v1 = v[o + 64], v2 = v[o + 128], v3 = v[o + 192];
+        const int c0 = nt_load(c + o), c1 = nt_load(c + o + 64), c2 = nt_load(c + o + 128), c3 = nt_load(c + o + 192);
+        const Tv v0 = nt_load(v + o), v1 = nt_load(v + o + 64), v2 = nt_load(v + o + 128), v3 = nt_load(v + o + 192);
         a0 += Tx(v0) * x[c0];
         a1 += Tx(v1) * x[c1];
         a2 += Tx(v2) * x[c2];
         a3 += Tx(v3) * x[c3];
     }
-    for (; j < w; ++j) a0 += Tx(v[int64_t(j) * 64]) * x[c[int64_t(j) * 64]];
+    for (; j < w; ++j) a0 += Tx(nt_load(v + int64_t(j) * 64)) * x[nt_load(c + int64_t(j) * 64)];
     const int r = rowidx[int64_t(slice) * 64 + lane];
     if (r >= 0) y[out_perm ? out_perm[r] : r] = (a0 + a1) + (a2 + a3);
 }
@@ -697,7 +706,8 @@ __global__ void __launch_bounds__(kBlock) k_axpby_d(int n, double a, const doubl
                                                     double *__restrict__ y)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) y[i] = a * x[i] + b * y[i];
+    // b = 0 never reads y (it may be uninitialised memory, where 0 * NaN = NaN)
+    if (i < n) y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
 }
 void launch_axpby_d(int n, double a, const double *x, double b, double *y, hipStream_t s)
 {

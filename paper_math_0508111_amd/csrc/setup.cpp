@@ -46,6 +46,15 @@ inline double get(const Csr &A, int i, int j)
 }
 }  // namespace
 
+void set_setup_threads(int threads)
+{
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+}
+
 Csr anderson_shifted(int L, const double *eps, double sigma)
 {
     const int n = L * L * L;

@@ -108,6 +108,9 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L);
 // Returns an empty string on success, else a message.
 std::string build_multilevel(const Csr &A, const SetupParams &prm, Multilevel &out);
 
+// Host threads used by the setup of the calling thread (OpenMP); <= 0 leaves the default.
+void set_setup_threads(int threads);
+
 // A - sigma I for the periodic Anderson lattice (hopping -1), CSR.
 Csr anderson_shifted(int L, const double *eps, double sigma);
 

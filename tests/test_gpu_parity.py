@@ -206,3 +206,34 @@ def test_solve_against_stored_oracle(name, precision):
     evals, evecs, resid, info = jd.solve(g["L"], g["W"], g["seed"], g["sigma"], g["k"], 1e-10, vectors=True,
                                          precision=precision)
     _check_pairs(g["L"], g["W"], g["seed"], g["sigma"], g["k"], np.array(g["lams"]), evals, evecs, resid, info)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_matches_eager(precision):
+    # The inner iteration replayed as a captured HIP graph runs the same kernels in the
+    # same order as the eager launches: identical iteration counts and eigenvalues.
+    L, W, seed, sigma, k = 16, 16.5, 2, 0.0, 4
+    ref, _, _, _ = eig.anderson_nearest(L, W, seed, sigma, k)
+    e0, _, _, i0 = jd.solve(L, W, seed, sigma, k, 1e-10, precision=precision)
+    e1, _, _, i1 = jd.solve(L, W, seed, sigma, k, 1e-10, precision=precision, flags=jd.JD_FLAG_GRAPHS)
+    assert i0["status"] == 0 and i1["status"] == 0
+    assert (i0["outer_its"], i0["inner_its"]) == (i1["outer_its"], i1["inner_its"])
+    assert np.array_equal(e0, e1)
+    assert np.max(np.abs(np.sort(e0) - np.sort(ref))) <= 1e-9
+
+
+@pytest.mark.parametrize("L,W,seed,sigma,k", [(10, 21.0, 1000002, 0.9, 3), (8, 12.0, 1000005, 0.1, 7),
+                                              (20, 21.0, 1000004, -0.2, 2)])
+def test_solve_on_recycled_memory(L, W, seed, sigma, k):
+    # Device memory handed out again after a free keeps its old contents.  Fill a large
+    # block with NaN and release it to the runtime first: a solve must read nothing it
+    # did not write (locking a vector once formed 0 * Q with Q not yet written).
+    junk = torch.full((1 << 27,), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+    ref, _, _, _ = eig.anderson_nearest(L, W, seed, sigma, k)
+    for precision in ("mixed", "fp64"):
+        evals, _, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, precision=precision)
+        assert info["status"] == 0 and info["n_converged"] == k
+        assert np.max(np.abs(np.sort(evals) - np.sort(ref))) <= 1e-9
