@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=48, help="0 disables the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=32, help="0 disables the serving leg")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--kernels-only", action="store_true",
                     help="setup, then only launches of the dominant kernel and a 256 MB copy "
@@ -93,7 +93,7 @@ def stencil_bandwidth(jd, torch, L, W, seed, reps=50):
 
 def factor_roofline(torch, prob, n, reps=40):
     """Roofline of the dominant kernel, the binary32 product with the explicit inverse
-    factor Z (k_zspmv<float>; two launches per preconditioner apply, Z and Z^T).
+    factor Z (k_hyb_spmv<float, float>; two launches per preconditioner apply, Z and Z^T).
     Algorithmic bytes per launch: nnz (4 value + 4 index) + (n + 1) 8 row pointers +
     n 4 input + n 4 output (+ n 4 output permutation for Z^T), averaged over the two."""
     pc = prob.precond()
@@ -114,12 +114,12 @@ def factor_roofline(torch, prob, n, reps=40):
     b = nnz * 8 + (n + 1) * 8 + n * 8 + n * 2  # the n*4 permutation read of every other launch
     achieved = b / (us * 1e-6) / 1e9
     pc.close()
-    return {"kernel": "k_zspmv<float>", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+    return {"kernel": "k_hyb_spmv<float, float>", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "bytes_per_launch": int(b), "nnz": int(nnz), "avg_us": round(us, 2), "reps": reps}
 
 
-def serving(jd, nreq, workers, warm=16):
+def serving(jd, nreq, workers, warm=8):
     """Continuous batching of the mixed request stream: a closed-loop warm-up measures
     the saturated request rate, then nreq requests arrive as a Poisson process at 0.8
     of that rate; latency = submission -> completion."""
@@ -146,6 +146,10 @@ def serving(jd, nreq, workers, warm=16):
     res = [srv.wait(t) for t in tickets]
     span = time.time() - t0
     srv.close()
+    for r, q in zip(res, reqs[warm:]):
+        if r["status"] != 0:
+            print(f"# serving: request {q} -> status {r['status']}, {r['n_converged']}/{r['k']} converged, "
+                  f"outer {r['outer_its']}, {r['error']}", file=sys.stderr, flush=True)
     lat = np.array([r["latency_s"] for r in res])
     ok = sum(r["status"] == 0 for r in res)
     pairs = sum(r["n_converged"] for r in res)

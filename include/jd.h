@@ -60,6 +60,9 @@ enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
  *             its modulus is below drop_tol / kappa (0 -> 1/sqrt(n), the paper's
  *             choice in section 8.2; < 0 -> nothing dropped, exact factorisation).
  *  kappa      bound on ||L^{-1}|| of inverse-based pivoting, section 7.2 (0 -> 5).
+ *             After a level that accepts fewer than 1% of its unknowns while more
+ *             than 8192 remain, the bound (and with it drop_tol / kappa) doubles for
+ *             the following levels, up to max(1000, kappa).
  *  agg_tau    tau of the aggressive dropping rule of section 7.3 (0 -> 0.1).
  *  schur_tol  off-diagonal entries of a scaled Schur complement below this are
  *             dropped (0 -> drop_tol / 2).

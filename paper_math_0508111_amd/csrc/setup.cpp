@@ -675,6 +675,11 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
     int off = 0;
     const bool verbose = std::getenv("JDMI_VERBOSE") != nullptr;
     double t_match = 0, t_split = 0, t_fact = 0;
+    // kappa of the current level: doubled (up to kKappaMax) after a level that accepted
+    // fewer than 1% of its unknowns while the rest is still too large for the exact last
+    // level, so that a stalled recursion keeps shrinking
+    SetupParams lp = prm;
+    constexpr double kKappaMax = 1e3;
     while (S.n > prm.coarse_max && int(pend.size()) < prm.max_levels) {
         double ta = now_s();
         MatchResult mr = max_product_matching(S);
@@ -687,17 +692,18 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
         Csr Snext;
         std::vector<uint64_t> key(S.n);
         for (int i = 0; i < S.n; ++i) key[i] = morton(orig[i], L);
-        std::string err = factor_level(S, prm, d, blocks, key, pl.lv, Snext);
+        std::string err = factor_level(S, lp, d, blocks, key, pl.lv, Snext);
         double td = now_s();
         t_match += tb - ta; t_split += tc - tb; t_fact += td - tc;
         if (verbose)
-            fprintf(stderr, "level %zu: n %d nnz %lld nB %zu 2x2 %d rej %d | match %.3fs split %.3fs factor %.3fs\n",
-                    pend.size(), S.n, (long long)S.col.size(), pl.lv.B.size(), pl.lv.n2x2, pl.lv.rejected,
+            fprintf(stderr, "level %zu: n %d nnz %lld nB %zu 2x2 %d rej %d kappa %g | match %.3fs split %.3fs factor %.3fs\n",
+                    pend.size(), S.n, (long long)S.col.size(), pl.lv.B.size(), pl.lv.n2x2, pl.lv.rejected, lp.kappa,
                     tb - ta, tc - tb, td - tc);
         if (!err.empty()) return err;
         // no acceptable pivot, or the level barely shrinks and the rest fits the
         // exactly inverted last level: stop the recursion here
         if (pl.lv.B.empty() || (int64_t(pl.lv.B.size()) * 100 < S.n && S.n <= 8192)) break;
+        if (int64_t(pl.lv.B.size()) * 100 < S.n && lp.drop_tol >= 0) lp.kappa = std::min(2.0 * lp.kappa, std::max(kKappaMax, prm.kappa));
         pl.cum.resize(S.n);
         for (int i = 0; i < S.n; ++i) pl.cum[i] = cum_prev[i] * d[i];
         pl.off = off;

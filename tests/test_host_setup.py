@@ -194,8 +194,16 @@ def test_cycle_split_worked_example(jd):
     assert blocks == [(0,), (1, 3), (2, 4), (5,)]
 
 
+def _csr_sparse(A):
+    # a scipy matrix whose diagonal entries are all nonzero (so none is dropped)
+    M = sp.csr_matrix(A)
+    M.sort_indices()
+    assert np.all(M.diagonal() != 0)
+    return (M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data.astype(np.float64), M)
+
+
 def _host_factor(jd, A, **opts):
-    ptr, col, val, M = _csr(A)
+    ptr, col, val, M = _csr_sparse(A) if sp.issparse(A) else _csr(A)
     n = M.shape[0]
     cap = 512
     perm = np.zeros(n, np.int32)
@@ -246,3 +254,28 @@ def test_multilevel_no_dropping_keeps_small_entries(jd):
     assert exact["levels"] >= 2
     assert exact["gnnz"].sum() >= dropped["gnnz"][: exact["levels"]].sum()
     assert exact["gmin"][exact["gnnz"] > 0].min() < 5e-2 / 5.0  # small entries kept
+
+
+def test_multilevel_stalled_recursion_terminates(jd):
+    # W = 12 near the band centre: the inverse-based test refuses most candidates and a
+    # level can accept fewer than 1% of its unknowns while the rest is still too large
+    # for the exact last level.  kappa then doubles for the following levels (section
+    # 7.2's bound applied level by level), so the recursion keeps shrinking and ends
+    # with a last level the device can invert.
+    from oracle import generator, lattice
+    L, W, seed, sigma = 40, 12.0, 1000009, 0.9233143873275735
+    n = L ** 3
+    A = (lattice.hamiltonian(L, generator.disorder(L, W, seed)) - sigma * sp.identity(n)).tocsr()
+    drop, kappa = 1.0 / math.sqrt(n), 5.0
+    r = _host_factor(jd, A, drop_tol=drop, kappa=kappa)
+    assert r["coarse"] <= 8192 and sorted(r["perm"]) == list(range(n))
+    k_l, stalls = kappa, 0
+    for l in range(r["levels"]):
+        rest = n - r["off"][l]
+        assert r["gcolsum"][l] <= k_l * (1 + 1e-12)
+        if r["gnnz"][l] > 0:
+            assert r["gmin"][l] >= drop / k_l * (1 - 1e-12)
+        if r["nB"][l] * 100 < rest:
+            assert rest > 8192  # below that the recursion stops instead
+            k_l, stalls = min(2 * k_l, 1e3), stalls + 1
+    assert stalls >= 1  # the case does exercise the rule
