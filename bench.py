@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=32, help="0 disables the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=16, help="0 disables the serving leg")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--kernels-only", action="store_true",
                     help="setup, then only launches of the dominant kernel and a 256 MB copy "
@@ -122,29 +122,39 @@ def factor_roofline(torch, prob, n, reps=40):
 def serving(jd, nreq, workers, warm=8):
     """Continuous batching of the mixed request stream: a closed-loop warm-up measures
     the saturated request rate, then nreq requests arrive as a Poisson process at 0.8
-    of that rate; latency = submission -> completion."""
+    of that rate; latency = submission -> completion (measured by the server)."""
     import numpy as np
     from tests import seeded_inputs
     reqs = seeded_inputs.serving_requests(warm + nreq)
     mk = lambda r: jd.Server.request(r["L"], r["W"], r["seed"], r["sigma"], r["k"], 1e-10, "mixed")
     srv = jd.Server(workers=workers)
-    t0 = time.time()
-    tk = [srv.submit(mk(r)) for r in reqs[:warm]]
-    for t in tk:
-        srv.wait(t)
-    rate = warm / (time.time() - t0)
+
+    def run(batch, arrivals, label):
+        # submit each request at its arrival time and report every completion
+        t0, i, pending, res = time.time(), 0, {}, [None] * len(batch)
+        while i < len(batch) or pending:
+            now = time.time() - t0
+            while i < len(batch) and (arrivals is None or arrivals[i] <= now):
+                pending[srv.submit(mk(batch[i]))] = i
+                i += 1
+            for t, j in list(pending.items()):
+                r = srv.poll(t)
+                if r is None:
+                    continue
+                res[j] = r
+                del pending[t]
+                q = batch[j]
+                print(f"# serving {label} {j}: L={q['L']} W={q['W']} k={q['k']} status {r['status']} "
+                      f"setup {r['setup_s']:.2f} s solve {r['solve_s']:.2f} s latency {r['latency_s']:.2f} s",
+                      file=sys.stderr, flush=True)
+            time.sleep(0.01)
+        return res, time.time() - t0
+
+    _, span = run(reqs[:warm], None, "warm-up")
+    rate = warm / span
     lam = 0.8 * rate
-    arrivals = seeded_inputs.poisson_arrivals(nreq, lam)
     print(f"# serving: saturated {rate:.2f} req/s, Poisson arrivals at {lam:.2f} req/s", file=sys.stderr, flush=True)
-    t0 = time.time()
-    tickets = []
-    for a, r in zip(arrivals, reqs[warm:]):
-        dt = t0 + a - time.time()
-        if dt > 0:
-            time.sleep(dt)
-        tickets.append(srv.submit(mk(r)))
-    res = [srv.wait(t) for t in tickets]
-    span = time.time() - t0
+    res, span = run(reqs[warm:], seeded_inputs.poisson_arrivals(nreq, lam), "poisson")
     srv.close()
     for r, q in zip(res, reqs[warm:]):
         if r["status"] != 0:
@@ -158,6 +168,7 @@ def serving(jd, nreq, workers, warm=8):
             "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
             "p50_setup_s": round(float(np.percentile([r["setup_s"] for r in res], 50)), 3),
             "p50_solve_s": round(float(np.percentile([r["solve_s"] for r in res], 50)), 3),
+            "p99_solve_s": round(float(np.percentile([r["solve_s"] for r in res], 99)), 3),
             "p50_queued_s": round(float(np.percentile([r["queued_s"] for r in res], 50)), 3),
             "eigenpairs_per_s": round(pairs / span, 3),
             "workload": "L in {20..60}, W in {12, 16.5, 21}, sigma ~ U[-1,1], k in 1..10, seeds 1e6+i, "

@@ -247,8 +247,10 @@ typedef struct jd_result {
 typedef struct jd_server jd_server;
 
 /* hbm_budget_bytes: device memory the server may reserve (0 -> 80% of free memory);
- * workers: concurrently active requests (0 -> 8); setup_threads: host threads per
- * setup (0 -> hardware threads / workers). */
+ * workers: concurrently active requests (0 -> 8); setup_threads: host threads of one
+ * setup (0 -> half the OpenMP thread budget, OMP_NUM_THREADS).  Host setups are a
+ * resource of their own: at most max(1, budget / setup_threads) run at once (the
+ * others wait, their time counts in setup_s), while admitted solves all run. */
 int jd_server_create(size_t hbm_budget_bytes, int workers, int setup_threads, jd_server **out);
 /* Queue a request (never blocks); *ticket identifies it.  JD_EINVAL for bad fields, or
  * a footprint larger than the whole budget. */

@@ -106,85 +106,6 @@ std::vector<To> cast_vec(const std::vector<double> &v)
     return std::vector<To>(v.begin(), v.end());
 }
 
-// CSR -> sliced ELL: rows ordered by decreasing length (stable), 64 rows per slice,
-// slice j-th entries of its 64 rows stored contiguously; padding has value 0, index 0.
-struct SellHost {
-    std::vector<int64_t> slice_ptr;
-    std::vector<int> rowidx, col;
-    std::vector<double> val;
-};
-struct HybHost {
-    std::vector<int> long_row;
-    std::vector<int64_t> long_ptr;
-    std::vector<int> long_col;
-    std::vector<double> long_val;
-    SellHost sell;
-};
-constexpr int64_t kLongRow = 96;  // rows with more entries than this are reduced by a whole wave
-
-SellHost to_sell(int n, const std::vector<int64_t> &ptr, const std::vector<int> &col, const std::vector<double> &val,
-                 std::vector<int> *only_rows = nullptr)
-{
-    SellHost h;
-    std::vector<int> order;
-    if (only_rows) order = *only_rows;
-    else { order.resize(n); std::iota(order.begin(), order.end(), 0); }
-    // sort by decreasing length only inside windows of consecutive rows, so that a
-    // slice holds rows of similar length that are also neighbours in position order
-    // (their gathers then share cache lines)
-    constexpr size_t kWindow = 2048;
-    for (size_t w0 = 0; w0 < order.size(); w0 += kWindow) {
-        auto b = order.begin() + w0, e = order.begin() + std::min(order.size(), w0 + kWindow);
-        std::stable_sort(b, e, [&](int a, int c) { return ptr[a + 1] - ptr[a] > ptr[c + 1] - ptr[c]; });
-    }
-    n = int(order.size());
-    const int ns = (n + 63) / 64;
-    h.slice_ptr.assign(ns + 1, 0);
-    h.rowidx.assign(size_t(ns) * 64, -1);
-    for (int sl = 0; sl < ns; ++sl) {
-        int64_t w = 0;
-        for (int l = 0; l < 64 && sl * 64 + l < n; ++l) {
-            const int r = order[sl * 64 + l];
-            h.rowidx[size_t(sl) * 64 + l] = r;
-            w = std::max(w, ptr[r + 1] - ptr[r]);
-        }
-        h.slice_ptr[sl + 1] = h.slice_ptr[sl] + w * 64;
-    }
-    h.col.assign(h.slice_ptr[ns], 0);
-    h.val.assign(h.slice_ptr[ns], 0.0);
-    for (int sl = 0; sl < ns; ++sl)
-        for (int l = 0; l < 64 && sl * 64 + l < n; ++l) {
-            const int r = order[sl * 64 + l];
-            int64_t j = 0;
-            for (int64_t p = ptr[r]; p < ptr[r + 1]; ++p, ++j) {
-                h.col[h.slice_ptr[sl] + j * 64 + l] = col[p];
-                h.val[h.slice_ptr[sl] + j * 64 + l] = val[p];
-            }
-        }
-    return h;
-}
-
-HybHost to_hyb(int n, const std::vector<int64_t> &ptr, const std::vector<int> &col, const std::vector<double> &val)
-{
-    HybHost h;
-    std::vector<int> shortr;
-    for (int r = 0; r < n; ++r) {
-        if (ptr[r + 1] - ptr[r] > kLongRow) h.long_row.push_back(r);
-        else shortr.push_back(r);
-    }
-    std::stable_sort(h.long_row.begin(), h.long_row.end(),
-                     [&](int a, int b) { return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b]; });
-    h.long_ptr.assign(h.long_row.size() + 1, 0);
-    for (size_t i = 0; i < h.long_row.size(); ++i) {
-        const int r = h.long_row[i];
-        h.long_ptr[i + 1] = h.long_ptr[i] + (ptr[r + 1] - ptr[r]);
-        h.long_col.insert(h.long_col.end(), col.begin() + ptr[r], col.begin() + ptr[r + 1]);
-        h.long_val.insert(h.long_val.end(), val.begin() + ptr[r], val.begin() + ptr[r + 1]);
-    }
-    h.sell = to_sell(n, ptr, col, val, &shortr);
-    return h;
-}
-
 // The multilevel factors on the device in one precision.
 template <typename T>
 struct DevPrecond {
@@ -199,25 +120,22 @@ struct DevPrecond {
     const int *site_of = nullptr, *cidx = nullptr, *dp = nullptr;
     const T *dd = nullptr, *dof = nullptr;
     T *yc = nullptr;
-    jdmi::Sell<T> zs, zts;  // the same two factors in sliced-ELL layout
     jdmi::Hyb<T> zh, zth;   // hybrid layout (long rows per wave + sliced ELL)
 
-    static jdmi::Hyb<T> upload_hyb(const HybHost &h, DevMem &mem, hipStream_t s)
+    static jdmi::Hyb<T> upload_hyb(const jdmi::HybHost &h, DevMem &mem, hipStream_t s)
     {
         jdmi::Hyb<T> d;
         d.nlong = int(h.long_row.size());
+        d.nslices = int(h.slice_ptr.size()) - 1;
+        for (int k = 0; k < jdmi::kHybParts; ++k) {
+            d.tbeg[k] = h.tbeg[k];
+            d.tend[k] = h.tend[k];
+        }
+        d.task = mem.upload(h.task, s);
         d.long_row = mem.upload(h.long_row, s);
         d.long_ptr = mem.upload(h.long_ptr, s);
         d.long_col = mem.upload(h.long_col, s);
         d.long_val = mem.upload(cast_vec<T>(h.long_val), s);
-        d.sell = upload_sell(h.sell, mem, s);
-        return d;
-    }
-
-    static jdmi::Sell<T> upload_sell(const SellHost &h, DevMem &mem, hipStream_t s)
-    {
-        jdmi::Sell<T> d;
-        d.nslices = int(h.slice_ptr.size()) - 1;
         d.slice_ptr = mem.upload(h.slice_ptr, s);
         d.rowidx = mem.upload(h.rowidx, s);
         d.col = mem.upload(h.col, s);
@@ -226,7 +144,7 @@ struct DevPrecond {
     }
 
     void upload(const jdmi::Multilevel &ml, const int *dperm, DevMem &mem, hipStream_t s,
-                const HybHost *zsh = nullptr, const HybHost *ztsh = nullptr)
+                const jdmi::HybHost *zsh = nullptr, const jdmi::HybHost *ztsh = nullptr)
     {
         n = ml.n;
         perm = const_cast<int *>(dperm);
@@ -432,10 +350,10 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
     S.n2x2 = 0;
     for (auto &lv : S.ml.levels) S.n2x2 += lv.n2x2;
     int *dperm = S.mem.upload(S.ml.perm, S.stream);
-    HybHost zsh, ztsh;
+    jdmi::HybHost zsh, ztsh;
     if (!S.ml.z.ptr.empty()) {
-        zsh = to_hyb(S.n, S.ml.z.ptr, S.ml.z.col, S.ml.z.val);
-        ztsh = to_hyb(S.n, S.ml.z.tptr, S.ml.z.tcol, S.ml.z.tval);
+        zsh = jdmi::to_hyb(S.n, S.ml.z.ptr, S.ml.z.col, S.ml.z.val);
+        ztsh = jdmi::to_hyb(S.n, S.ml.z.tptr, S.ml.z.tcol, S.ml.z.tval);
     }
     S.pc64.upload(S.ml, dperm, S.mem, S.stream, &zsh, &ztsh);
     S.pc32.upload(S.ml, dperm, S.mem, S.stream, &zsh, &ztsh);
@@ -1416,7 +1334,8 @@ struct jd_server {
     std::set<uint64_t> pending;
     std::map<uint64_t, jd_result> done;
     size_t budget = 0, reserved = 0;
-    int setup_threads = 1;
+    int setup_threads = 1, setup_slots = 1, setups_running = 0;
+    std::condition_variable cv_setup;
     bool stop = false;
     uint64_t next_id = 1;
     std::vector<std::thread> workers;
@@ -1436,7 +1355,17 @@ struct jd_server {
         o.flags = q.r.flags & ~JD_FLAG_GRAPHS;  // workers launch eagerly
         o.stream = stream;
         jd_problem *p = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(m);
+            cv_setup.wait(lk, [&] { return setups_running < setup_slots; });
+            ++setups_running;
+        }
         int rc = jd_setup(q.r.L, q.r.W, q.r.seed, q.r.sigma, &o, &p);
+        {
+            std::lock_guard<std::mutex> g(m);
+            --setups_running;
+        }
+        cv_setup.notify_one();
         const double t_setup = wall_s();
         res.setup_s = t_setup - t_admit;
         if (rc == JD_OK) {
@@ -1503,8 +1432,9 @@ int jd_server_create(size_t hbm_budget_bytes, int workers, int setup_threads, jd
         }
         s->budget = hbm_budget_bytes;
         const int w = workers ? workers : 8;
-        const int hw = std::max(1u, std::thread::hardware_concurrency());
-        s->setup_threads = setup_threads ? setup_threads : std::max(1, hw / w);
+        const int hw = jdmi::setup_thread_budget();
+        s->setup_threads = setup_threads ? setup_threads : std::max(1, hw / 2);
+        s->setup_slots = std::max(1, std::min(w, hw / s->setup_threads));
         for (int i = 0; i < w; ++i) s->workers.emplace_back([p = s.get()] { p->worker(); });
         *out = s.release();
         return JD_OK;

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "setup.h"
+
 namespace jdmi {
 
 constexpr int kBlock = 256;        // threads per workgroup for streaming kernels
@@ -48,37 +50,26 @@ template <typename T>
 void launch_coarse_idx(int nc, const int *idx, const T *cinv, const T *y, T *yc, T *z, hipStream_t s,
                        const int *skip);
 
-// explicit inverse factor apply: y = Z w (16 lanes per row); optional output permutation
-// out[perm[r]] = (Z w)[r]
-template <typename T>
-void launch_zspmv(int n, const int64_t *ptr, const int *col, const T *val, const T *w, T *y, const int *out_perm,
-                  hipStream_t s, const int *skip);
-// The same product in a sliced-ELL layout (rows sorted by length, 64 rows per slice,
-// each slice stored column-major): one wave per slice, one row per lane, every value
-// and index load a contiguous 256-byte segment.
-template <typename T>
-struct Sell {
-    int nslices = 0;
-    const int64_t *slice_ptr = nullptr;  // nslices + 1, in entries (multiples of 64)
-    const int *rowidx = nullptr;         // nslices * 64, -1 for padding lanes
-    const int *col = nullptr;
-    const T *val = nullptr;
-};
-template <typename T, typename To = T>
-void launch_sell_spmv(const Sell<T> &A, const T *x, To *y, const int *out_perm, hipStream_t s, const int *skip);
-
-// Hybrid layout for skewed row lengths: rows longer than a threshold are kept in CSR
-// and reduced by a whole wave each (longest first); the rest form sliced-ELL slices.
-// Values are stored in Tv, vectors and accumulation are in Tx.
+// Product with the explicit inverse factor (y = Z w, or Z^T w) in the hybrid layout of
+// jdmi::HybHost; workgroup b works on part b % kHybParts, so that on an 8-XCD device a
+// part's gathers stay in one XCD's L2.  Values are stored in Tv; the vectors and the
+// accumulation are in Tx.  Summation order is fixed (per lane, then a fixed shuffle
+// tree): results are reproducible.
 template <typename Tv>
 struct Hyb {
-    int nlong = 0;
-    const int *long_row = nullptr;     // original row of each long row
+    int nlong = 0, nslices = 0;
+    int tbeg[kHybParts] = {}, tend[kHybParts] = {};  // task range of each part
+    const int *task = nullptr;         // >= 0: long row index; < 0: slice -1 - task
+    const int *long_row = nullptr;     // row of each long row
     const int64_t *long_ptr = nullptr; // nlong + 1
     const int *long_col = nullptr;
     const Tv *long_val = nullptr;
-    Sell<Tv> sell;
+    const int64_t *slice_ptr = nullptr;  // nslices + 1, in entries (multiples of 64)
+    const int *rowidx = nullptr;         // nslices * kSliceRows, -1 for padding rows
+    const int *col = nullptr;
+    const Tv *val = nullptr;
 };
+// out_perm (optional): y[out_perm[r]] = (Z w)[r]
 template <typename Tv, typename Tx>
 void launch_hyb_spmv(const Hyb<Tv> &A, const Tx *x, Tx *y, const int *out_perm, hipStream_t s, const int *skip);
 // w[p] = Tout(b[perm[p]])

@@ -6,6 +6,7 @@
 // final pass), so a result never depends on what else runs on the device.
 #include "kernels.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace jdmi {
@@ -275,119 +276,53 @@ void launch_coarse(int nc, int off, const T *cinv, const T *w, T *x, hipStream_t
 }
 
 // ---------------------------------------------------------------------------------
-// Explicit inverse factor: 16 lanes per row stride over the row's entries (coalesced
-// column/value reads), then a fixed-order shuffle tree inside the 16-lane segment.
+// Explicit inverse factor, hybrid layout (see kernels.h for the layout).
 // ---------------------------------------------------------------------------------
-constexpr int kZLanes = 16;
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_zspmv(int n, const int64_t *__restrict__ ptr, const int *__restrict__ col,
-                                                  const T *__restrict__ val, const T *__restrict__ w,
-                                                  T *__restrict__ y, const int *__restrict__ out_perm,
-                                                  const int *skip)
-{
-    if (skip && *skip) return;
-    const int lane = threadIdx.x & (kZLanes - 1);
-    const int r = blockIdx.x * (kBlock / kZLanes) + (threadIdx.x / kZLanes);
-    if (r >= n) return;  // the whole 16-lane segment leaves together
-    T acc = T(0);
-    for (int64_t p = ptr[r] + lane, e = ptr[r + 1]; p < e; p += kZLanes) acc += val[p] * w[col[p]];
-#pragma unroll
-    for (int o = kZLanes / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kZLanes);
-    if (lane == 0) y[out_perm ? out_perm[r] : r] = acc;
-}
-
-template <typename T>
-void launch_zspmv(int n, const int64_t *ptr, const int *col, const T *val, const T *w, T *y, const int *out_perm,
-                  hipStream_t s, const int *skip)
-{
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_zspmv<T>, dim3(nblocks(n, kBlock / kZLanes)), dim3(kBlock), 0, s, n, ptr, col, val, w, y,
-                       out_perm, skip);
-}
-
-template <typename T, typename To>
-__global__ void __launch_bounds__(kBlock) k_sell_spmv(int nslices, const int64_t *__restrict__ slice_ptr,
-                                                      const int *__restrict__ rowidx, const int *__restrict__ col,
-                                                      const T *__restrict__ val, const T *__restrict__ x,
-                                                      To *__restrict__ y, const int *__restrict__ out_perm,
-                                                      const int *skip)
-{
-    if (skip && *skip) return;
-    const int slice = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (slice >= nslices) return;
-    const int64_t b = slice_ptr[slice];
-    const int w = int((slice_ptr[slice + 1] - b) >> 6);
-    const int *c = col + b + lane;
-    const T *v = val + b + lane;
-    T a0 = T(0), a1 = T(0);
-    int j = 0;
-    for (; j + 1 < w; j += 2) {
-        a0 += v[int64_t(j) * 64] * x[c[int64_t(j) * 64]];
-        a1 += v[int64_t(j + 1) * 64] * x[c[int64_t(j + 1) * 64]];
-    }
-    if (j < w) a0 += v[int64_t(j) * 64] * x[c[int64_t(j) * 64]];
-    const int r = rowidx[int64_t(slice) * 64 + lane];
-    if (r >= 0) y[out_perm ? out_perm[r] : r] = To(a0 + a1);
-}
-
-template <typename T, typename To>
-void launch_sell_spmv(const Sell<T> &A, const T *x, To *y, const int *out_perm, hipStream_t s, const int *skip)
-{
-    if (A.nslices <= 0) return;
-    hipLaunchKernelGGL((k_sell_spmv<T, To>), dim3(nblocks(A.nslices, kBlock / 64)), dim3(kBlock), 0, s, A.nslices,
-                       A.slice_ptr, A.rowidx, A.col, A.val, x, y, out_perm, skip);
-}
-
 template <typename Tv, typename Tx>
-__global__ void __launch_bounds__(kBlock) k_hyb_spmv(int nlong, const int *__restrict__ long_row,
-                                                     const int64_t *__restrict__ long_ptr,
-                                                     const int *__restrict__ long_col, const Tv *__restrict__ long_val,
-                                                     int nslices, const int64_t *__restrict__ slice_ptr,
-                                                     const int *__restrict__ rowidx, const int *__restrict__ col,
-                                                     const Tv *__restrict__ val, const Tx *__restrict__ x,
-                                                     Tx *__restrict__ y, const int *__restrict__ out_perm,
-                                                     const int *skip)
+__global__ void __launch_bounds__(kBlock) k_hyb_spmv(Hyb<Tv> A, const Tx *__restrict__ x, Tx *__restrict__ y,
+                                                     const int *__restrict__ out_perm, const int *skip)
 {
     if (skip && *skip) return;
-    const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int part = blockIdx.x % kHybParts;
+    const int t = A.tbeg[part] + int(blockIdx.x / kHybParts) * (kBlock / 64) + int(threadIdx.x >> 6);
+    if (t >= A.tend[part]) return;
     const int lane = threadIdx.x & 63;
-    if (wave < nlong) {
+    const int code = A.task[t];
+    if (code >= 0) {
         // one long row per wave: lanes stride over the row (four entries in flight per
         // lane: all index and value loads are issued before the dependent gathers)
-        const int64_t b = long_ptr[wave], e = long_ptr[wave + 1];
+        const int64_t b = A.long_ptr[code], e = A.long_ptr[code + 1];
         Tx a0 = Tx(0), a1 = Tx(0), a2 = Tx(0), a3 = Tx(0);
         int64_t p = b + lane;
         for (; p + 192 < e; p += 256) {
-            const int c0 = nt_load(long_col + p), c1 = nt_load(long_col + p + 64);
-            const int c2 = nt_load(long_col + p + 128), c3 = nt_load(long_col + p + 192);
-            const Tv v0 = nt_load(long_val + p), v1 = nt_load(long_val + p + 64);
-            const Tv v2 = nt_load(long_val + p + 128), v3 = nt_load(long_val + p + 192);
+            const int c0 = nt_load(A.long_col + p), c1 = nt_load(A.long_col + p + 64);
+            const int c2 = nt_load(A.long_col + p + 128), c3 = nt_load(A.long_col + p + 192);
+            const Tv v0 = nt_load(A.long_val + p), v1 = nt_load(A.long_val + p + 64);
+            const Tv v2 = nt_load(A.long_val + p + 128), v3 = nt_load(A.long_val + p + 192);
             a0 += Tx(v0) * x[c0];
             a1 += Tx(v1) * x[c1];
             a2 += Tx(v2) * x[c2];
             a3 += Tx(v3) * x[c3];
         }
-        for (; p < e; p += 64) a0 += Tx(nt_load(long_val + p)) * x[nt_load(long_col + p)];
+        for (; p < e; p += 64) a0 += Tx(nt_load(A.long_val + p)) * x[nt_load(A.long_col + p)];
         Tx a = (a0 + a1) + (a2 + a3);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
         if (lane == 0) {
-            const int r = long_row[wave];
+            const int r = A.long_row[code];
             y[out_perm ? out_perm[r] : r] = a;
         }
         return;
     }
-    const int slice = wave - nlong;
-    if (slice >= nslices) return;
-    const int64_t b = slice_ptr[slice];
-    const int w = int((slice_ptr[slice + 1] - b) >> 6);
-    const int *c = col + b + lane;
-    const Tv *v = val + b + lane;
+    // a slice of kSliceRows short rows, kSliceLanes lanes per row
+    const int slice = -1 - code;
+    const int64_t b = A.slice_ptr[slice];
+    const int groups = int((A.slice_ptr[slice + 1] - b) >> 6);
+    const int *c = A.col + b + lane;
+    const Tv *v = A.val + b + lane;
     Tx a0 = Tx(0), a1 = Tx(0), a2 = Tx(0), a3 = Tx(0);
     int j = 0;
-    for (; j + 3 < w; j += 4) {
+    for (; j + 3 < groups; j += 4) {
         const int64_t o = int64_t(j) * 64;
         const int c0 = nt_load(c + o), c1 = nt_load(c + o + 64), c2 = nt_load(c + o + 128), c3 = nt_load(c + o + 192);
         const Tv v0 = nt_load(v + o), v1 = nt_load(v + o + 64), v2 = nt_load(v + o + 128), v3 = nt_load(v + o + 192);
@@ -396,19 +331,25 @@ __global__ void __launch_bounds__(kBlock) k_hyb_spmv(int nlong, const int *__res
         a2 += Tx(v2) * x[c2];
         a3 += Tx(v3) * x[c3];
     }
-    for (; j < w; ++j) a0 += Tx(nt_load(v + int64_t(j) * 64)) * x[nt_load(c + int64_t(j) * 64)];
-    const int r = rowidx[int64_t(slice) * 64 + lane];
-    if (r >= 0) y[out_perm ? out_perm[r] : r] = (a0 + a1) + (a2 + a3);
+    for (; j < groups; ++j) a0 += Tx(nt_load(v + int64_t(j) * 64)) * x[nt_load(c + int64_t(j) * 64)];
+    Tx a = (a0 + a1) + (a2 + a3);
+    // lanes l, l + kSliceRows, l + 2 kSliceRows, ... hold the pieces of row l
+#pragma unroll
+    for (int o = kSliceRows; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
+    if (lane < kSliceRows) {
+        const int r = A.rowidx[int64_t(slice) * kSliceRows + lane];
+        if (r >= 0) y[out_perm ? out_perm[r] : r] = a;
+    }
 }
 
 template <typename Tv, typename Tx>
 void launch_hyb_spmv(const Hyb<Tv> &A, const Tx *x, Tx *y, const int *out_perm, hipStream_t s, const int *skip)
 {
-    const int waves = A.nlong + A.sell.nslices;
-    if (waves <= 0) return;
-    hipLaunchKernelGGL((k_hyb_spmv<Tv, Tx>), dim3(nblocks(waves, kBlock / 64)), dim3(kBlock), 0, s, A.nlong,
-                       A.long_row, A.long_ptr, A.long_col, A.long_val, A.sell.nslices, A.sell.slice_ptr,
-                       A.sell.rowidx, A.sell.col, A.sell.val, x, y, out_perm, skip);
+    int most = 0;
+    for (int k = 0; k < kHybParts; ++k) most = std::max(most, A.tend[k] - A.tbeg[k]);
+    if (most <= 0) return;
+    const int blocks = kHybParts * ((most + kBlock / 64 - 1) / (kBlock / 64));
+    hipLaunchKernelGGL((k_hyb_spmv<Tv, Tx>), dim3(blocks), dim3(kBlock), 0, s, A, x, y, out_perm, skip);
 }
 template void launch_hyb_spmv<float, float>(const Hyb<float> &, const float *, float *, const int *, hipStream_t,
                                             const int *);
@@ -432,8 +373,6 @@ void launch_gather_cvt(int n, const int *perm, const Tin *b, Tout *w, hipStream_
 }
 template void launch_gather_cvt<double, float>(int, const int *, const double *, float *, hipStream_t, const int *);
 template void launch_gather_cvt<double, double>(int, const int *, const double *, double *, hipStream_t, const int *);
-template void launch_sell_spmv<float, double>(const Sell<float> &, const float *, double *, const int *, hipStream_t,
-                                              const int *);
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dinv(int m, const T *__restrict__ dd, const T *__restrict__ dof,
@@ -931,10 +870,6 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
     template void launch_coarse<T>(int, int, const T *, const T *, T *, hipStream_t, const int *);         \
     template void launch_coarse_idx<T>(int, const int *, const T *, const T *, T *, T *, hipStream_t,      \
                                        const int *);                                                       \
-    template void launch_zspmv<T>(int, const int64_t *, const int *, const T *, const T *, T *, const int *,\
-                                  hipStream_t, const int *);                                               \
-    template void launch_sell_spmv<T, T>(const Sell<T> &, const T *, T *, const int *, hipStream_t,       \
-                                      const int *);                                                        \
     template void launch_dinv<T>(int, const T *, const T *, const int *, const T *, T *, hipStream_t,      \
                                  const int *);                                                             \
     template void launch_multidot<T>(int, int, const T *, int64_t, const T *, double *, double *,          \

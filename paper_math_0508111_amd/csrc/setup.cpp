@@ -46,6 +46,15 @@ inline double get(const Csr &A, int i, int j)
 }
 }  // namespace
 
+int setup_thread_budget()
+{
+#ifdef _OPENMP
+    return std::max(1, omp_get_max_threads());
+#else
+    return 1;
+#endif
+}
+
 void set_setup_threads(int threads)
 {
 #ifdef _OPENMP
@@ -937,6 +946,63 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L)
     Z.coarse_idx.resize(ml.coarse_n);
     for (int i = 0; i < ml.coarse_n; ++i) Z.coarse_idx[i] = newidx[ml.coarse_off + i];
     Z.seconds = now_s() - t0;
+}
+
+// CSR -> the hybrid device layout (see HybHost).
+HybHost to_hyb(int n, const std::vector<int64_t> &ptr, const std::vector<int> &col, const std::vector<double> &val)
+{
+    constexpr int P = kHybParts, C = kSliceRows, G = kSliceLanes;
+    constexpr size_t kWindow = 2048;
+    HybHost h;
+    auto len = [&](int r) { return ptr[r + 1] - ptr[r]; };
+    const int64_t nnz = ptr[n];
+    int r0 = 0;
+    for (int part = 0; part < P; ++part) {
+        // rows [r0, r1): the part's share of the nonzeros
+        int r1 = r0;
+        const int64_t target = nnz * (part + 1) / P;
+        while (r1 < n && (part == P - 1 || ptr[r1] < target)) ++r1;
+        h.tbeg[part] = int(h.task.size());
+        std::vector<int> longr, shortr;
+        for (int r = r0; r < r1; ++r) (len(r) > kLongRow ? longr : shortr).push_back(r);
+        std::stable_sort(longr.begin(), longr.end(), [&](int a, int b) { return len(a) > len(b); });
+        for (int r : longr) {
+            h.task.push_back(int(h.long_row.size()));
+            h.long_row.push_back(r);
+            h.long_col.insert(h.long_col.end(), col.begin() + ptr[r], col.begin() + ptr[r + 1]);
+            h.long_val.insert(h.long_val.end(), val.begin() + ptr[r], val.begin() + ptr[r + 1]);
+            h.long_ptr.push_back(int64_t(h.long_col.size()));
+        }
+        for (size_t w0 = 0; w0 < shortr.size(); w0 += kWindow) {
+            auto b = shortr.begin() + w0, e = shortr.begin() + std::min(shortr.size(), w0 + kWindow);
+            std::stable_sort(b, e, [&](int a, int c) { return len(a) > len(c); });
+        }
+        for (size_t s0 = 0; s0 < shortr.size(); s0 += C) {
+            int64_t w = 0;
+            for (size_t l = 0; l < size_t(C) && s0 + l < shortr.size(); ++l) w = std::max(w, len(shortr[s0 + l]));
+            const int64_t base = h.slice_ptr.back(), groups = (w + G - 1) / G;
+            h.slice_ptr.push_back(base + groups * 64);
+            h.col.resize(size_t(base + groups * 64), 0);
+            h.val.resize(size_t(base + groups * 64), 0.0);
+            for (int l = 0; l < C; ++l) {
+                if (s0 + l >= shortr.size()) {
+                    h.rowidx.push_back(-1);
+                    continue;
+                }
+                const int r = shortr[s0 + l];
+                h.rowidx.push_back(r);
+                for (int64_t j = 0; j < len(r); ++j) {
+                    const int64_t at = base + (j / G) * 64 + (j % G) * C + l;
+                    h.col[at] = col[ptr[r] + j];
+                    h.val[at] = val[ptr[r] + j];
+                }
+            }
+            h.task.push_back(-int(h.slice_ptr.size() - 1));  // -1 - slice index
+        }
+        h.tend[part] = int(h.task.size());
+        r0 = r1;
+    }
+    return h;
 }
 
 }  // namespace jdmi

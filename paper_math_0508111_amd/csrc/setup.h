@@ -110,8 +110,36 @@ std::string build_multilevel(const Csr &A, const SetupParams &prm, Multilevel &o
 
 // Host threads used by the setup of the calling thread (OpenMP); <= 0 leaves the default.
 void set_setup_threads(int threads);
+// OpenMP threads available to the calling thread (OMP_NUM_THREADS when set).
+int setup_thread_budget();
 
 // A - sigma I for the periodic Anderson lattice (hopping -1), CSR.
 Csr anderson_shifted(int L, const double *eps, double sigma);
+
+// Device layout of the explicit inverse factor's products (built on the host; the
+// kernel reads it as jdmi::Hyb).  The rows (lattice sites in Morton order) are cut into
+// kHybParts contiguous parts of equal nonzero count; inside a part, rows with more than
+// kLongRow entries are kept in CSR (longest first, one wave each) and the other rows
+// form slices of kSliceRows rows with kSliceLanes lanes per row: entry j of the slice's
+// row l sits at slice_ptr[s] + (j / kSliceLanes) * 64 + (j % kSliceLanes) * kSliceRows + l
+// (padding: index 0, value 0).  Short rows are sorted by decreasing length inside
+// windows of 2048 consecutive rows, so a slice holds rows of similar length that are
+// also neighbours in position order.
+constexpr int kHybParts = 8;
+constexpr int kLongRow = 96;
+constexpr int kSliceRows = 8;
+constexpr int kSliceLanes = 64 / kSliceRows;
+struct HybHost {
+    int tbeg[kHybParts] = {}, tend[kHybParts] = {};  // task range of each part
+    std::vector<int> task;                 // >= 0: long row index; < 0: slice -1 - task
+    std::vector<int> long_row;
+    std::vector<int64_t> long_ptr{0};
+    std::vector<int> long_col;
+    std::vector<double> long_val;
+    std::vector<int64_t> slice_ptr{0};     // in entries (multiples of 64)
+    std::vector<int> rowidx, col;          // rowidx: kSliceRows per slice, -1 for padding rows
+    std::vector<double> val;
+};
+HybHost to_hyb(int n, const std::vector<int64_t> &ptr, const std::vector<int> &col, const std::vector<double> &val);
 
 }  // namespace jdmi
