@@ -114,6 +114,7 @@ struct DevPrecond {
     std::vector<jdmi::DevLevel<T>> levels;
     int coarse_off = 0, coarse_n = 0;
     T *cinv = nullptr;
+    int cld = 0;  // row stride of cinv: coarse_n rounded up to a multiple of kCoarseAlign
     T *w = nullptr, *x = nullptr;  // workspaces
     // explicit inverse factor form
     bool inv = false;
@@ -170,13 +171,21 @@ struct DevPrecond {
         }
         coarse_off = ml.coarse_off;
         coarse_n = ml.coarse_n;
-        cinv = mem.upload(cast_vec<T>(ml.coarse_inv), s);
+        cld = (ml.coarse_n + jdmi::kCoarseAlign - 1) / jdmi::kCoarseAlign * jdmi::kCoarseAlign;
+        {
+            std::vector<T> padded(size_t(ml.coarse_n) * cld, T(0));
+            for (int i = 0; i < ml.coarse_n; ++i)
+                for (int j = 0; j < ml.coarse_n; ++j)
+                    padded[size_t(i) * cld + j] = T(ml.coarse_inv[size_t(i) * ml.coarse_n + j]);
+            cinv = mem.upload(padded, s);
+        }
         w = mem.alloc<T>(n);
         x = mem.alloc<T>(n);
         if (inv) {
             site_of = mem.upload(ml.z.site_of, s);
             cidx = mem.upload(ml.z.coarse_idx, s);
-            yc = mem.alloc<T>(std::max(ml.coarse_n, 1));
+            yc = mem.alloc<T>(std::max(cld, 1));
+            HIPCHK(hipMemsetAsync(yc, 0, std::max(cld, 1) * sizeof(T), s));  // padding stays zero
             dd = mem.upload(cast_vec<T>(ml.z.dd), s);
             dof = mem.upload(cast_vec<T>(ml.z.dof), s);
             dp = mem.upload(ml.z.dp, s);
@@ -196,13 +205,13 @@ struct DevPrecond {
             jdmi::launch_gather<T>(n, site_of, in, w, s, skip);
             jdmi::launch_hyb_spmv<T, T>(zh, w, x, nullptr, s, skip);
             jdmi::launch_dinv<T>(n, dd, dof, dp, x, w, s, skip);
-            jdmi::launch_coarse_idx<T>(coarse_n, cidx, cinv, x, yc, w, s, skip);
+            jdmi::launch_coarse_idx<T>(coarse_n, cld, cidx, cinv, x, yc, w, s, skip);
             jdmi::launch_hyb_spmv<T, T>(zth, w, out, site_of, s, skip);
             return;
         }
         jdmi::launch_gather<T>(n, perm, in, w, s, skip);
         for (const auto &lv : levels) jdmi::launch_down<T>(lv, w, s, skip);
-        jdmi::launch_coarse<T>(coarse_n, coarse_off, cinv, w, x, s, skip);
+        jdmi::launch_coarse<T>(coarse_n, cld, coarse_off, cinv, w, x, s, skip);
         for (int l = int(levels.size()) - 1; l >= 0; --l) jdmi::launch_up<T>(levels[l], w, x, s, skip);
         jdmi::launch_scatter<T>(n, perm, x, out, s, skip);
     }
@@ -221,7 +230,7 @@ struct MixedPrecond {
         jdmi::launch_gather<double>(pd.n, pd.site_of, in, pd.w, s, skip);
         jdmi::launch_hyb_spmv<float, double>(pc.zh, pd.w, pd.x, nullptr, s, skip);
         jdmi::launch_dinv<double>(pd.n, pd.dd, pd.dof, pd.dp, pd.x, pd.w, s, skip);
-        jdmi::launch_coarse_idx<double>(pd.coarse_n, pd.cidx, pd.cinv, pd.x, pd.yc, pd.w, s, skip);
+        jdmi::launch_coarse_idx<double>(pd.coarse_n, pd.cld, pd.cidx, pd.cinv, pd.x, pd.yc, pd.w, s, skip);
         jdmi::launch_hyb_spmv<float, double>(pc.zth, pd.w, out, pd.site_of, s, skip);
     }
 };
@@ -515,14 +524,11 @@ struct Solver {
             jdmi::launch_multidot<T>(n, p, Qt, n, B.t, B.partial, B.coef, s, skip_a);
             jdmi::launch_sub_qc<T>(n, p, Qt, n, B.coef, B.t, s, skip_a);
         }
-        jdmi::launch_dot<T>(n, B.q, B.t, B.partial, B.red + 2, s, skip_a);
-        jdmi::launch_sqmr_scalar_alpha(B.st, B.red + 2, s);
+        jdmi::launch_sqmr_dot_alpha<T>(n, B.q, B.t, B.partial, B.red + 2, B.st, s);
         jdmi::launch_sqmr_update_r<T>(n, B.st, B.t, B.r, B.partial, B.red + 3, s);
-        jdmi::launch_sqmr_scalar_theta(B.st, B.red + 3, s);
         jdmi::launch_sqmr_update_xd<T>(n, B.st, B.q, B.d, B.x, s);
         precond_projected(B.r, B.u, Qt, Y, p, dM, skip_b);
-        jdmi::launch_dot<T>(n, B.r, B.u, B.partial, B.red + 4, s, skip_b);
-        jdmi::launch_sqmr_scalar_beta(B.st, B.red + 4, s);
+        jdmi::launch_sqmr_dot_beta<T>(n, B.r, B.u, B.partial, B.red + 4, B.st, s);
         jdmi::launch_sqmr_update_q<T>(n, B.st, B.u, B.q, s);
     }
 

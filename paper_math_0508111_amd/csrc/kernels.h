@@ -43,11 +43,14 @@ template <typename T>
 void launch_down(const DevLevel<T> &lv, T *w, hipStream_t s, const int *skip);
 template <typename T>
 void launch_up(const DevLevel<T> &lv, const T *w, T *x, hipStream_t s, const int *skip);
+// last level (dense inverse Cinv, row i at cinv + i * ld): x[off + i] = sum_j Cinv[i, j] w[off + j]
 template <typename T>
-void launch_coarse(int nc, int off, const T *cinv, const T *w, T *x, hipStream_t s, const int *skip);
-// last level with scattered unknowns: yc[i] = y[idx[i]], then z[idx[i]] = sum_j Cinv[i, j] yc[j]
+void launch_coarse(int nc, int ld, int off, const T *cinv, const T *w, T *x, hipStream_t s, const int *skip);
+// last level with scattered unknowns: yc[i] = y[idx[i]], then z[idx[i]] = sum_j Cinv[i, j] yc[j];
+// ld is a multiple of 64, and Cinv's row padding and yc[nc .. ld) hold zeros
+constexpr int kCoarseAlign = 64;
 template <typename T>
-void launch_coarse_idx(int nc, const int *idx, const T *cinv, const T *y, T *yc, T *z, hipStream_t s,
+void launch_coarse_idx(int nc, int ld, const int *idx, const T *cinv, const T *y, T *yc, T *z, hipStream_t s,
                        const int *skip);
 
 // Product with the explicit inverse factor (y = Z w, or Z^T w) in the hybrid layout of
@@ -123,11 +126,20 @@ template <typename T>
 void launch_stencil_state(int L, const T *eps, const SqmrState *st, const T *x, T *y, hipStream_t s);
 template <typename T>
 void launch_copy(int n, const T *x, T *y, hipStream_t s);
-void launch_sqmr_scalar_alpha(SqmrState *st, const double *sigma, hipStream_t s);
-void launch_sqmr_scalar_theta(SqmrState *st, const double *rr, hipStream_t s);
-void launch_sqmr_scalar_beta(SqmrState *st, const double *rho, hipStream_t s);
+// sigma = q.t (stored in *sigma) and, in the same final reduction, alpha = rho / sigma
+// (skipped when st->done; a zero or non-finite sigma is a breakdown that stops the solve)
+template <typename T>
+void launch_sqmr_dot_alpha(int n, const T *q, const T *t, double *partial, double *sigma, SqmrState *st,
+                           hipStream_t s);
+// r -= alpha t; |r|^2 (stored in *rr) and, in the same final reduction, the theta / c / tau
+// update and the stopping test (skipped when st->done)
 template <typename T>
 void launch_sqmr_update_r(int n, SqmrState *st, const T *t, T *r, double *partial, double *rr, hipStream_t s);
+// rho' = r.u (stored in *rho, skipped when st->done_next) and, in the same final reduction,
+// beta = rho' / rho; then st->done takes the value of st->done_next
+template <typename T>
+void launch_sqmr_dot_beta(int n, const T *r, const T *u, double *partial, double *rho, SqmrState *st,
+                          hipStream_t s);
 template <typename T>
 void launch_sqmr_update_xd(int n, SqmrState *st, const T *q, T *d, T *x, hipStream_t s);
 template <typename T>

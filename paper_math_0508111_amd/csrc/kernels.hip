@@ -202,46 +202,79 @@ __global__ void __launch_bounds__(kBlock) k_up(int off, int nB, const int64_t *_
     x[j] = acc;
 }
 
-// x[off + i] = sum_j Cinv[i, j] w[off + j]: one wave per row
+// 16-byte vector of T and its dot product, accumulated in binary64
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_coarse(int nc, int off, const T *__restrict__ cinv,
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = f32x4;
+    static constexpr int n = 4;
+    __device__ static double dot(const f32x4 &a, const f32x4 &b)
+    {
+        return (double(a.x) * double(b.x) + double(a.y) * double(b.y)) +
+               (double(a.z) * double(b.z) + double(a.w) * double(b.w));
+    }
+};
+template <>
+struct Vec16<double> {
+    using type = f64x2;
+    static constexpr int n = 2;
+    __device__ static double dot(const f64x2 &a, const f64x2 &b) { return a.x * b.x + a.y * b.y; }
+};
+
+// x[off + i] = sum_j Cinv[i, j] w[off + j] (rows of Cinv ld apart): one wave per row
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_coarse(int nc, int ld, int off, const T *__restrict__ cinv,
                                                    const T *__restrict__ w, T *__restrict__ x, const int *skip)
 {
     if (skip && *skip) return;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= nc) return;
-    const T *a = cinv + int64_t(row) * nc;
+    const T *a = cinv + int64_t(row) * ld;
     double acc = 0.0;
     for (int c = lane; c < nc; c += 64) acc += double(a[c]) * double(w[off + c]);
     acc = wave_sum(acc);
     if (lane == 0) x[off + row] = T(acc);
 }
 
+// z[idx[i]] = sum_j Cinv[i, j] yc[j]: one wave per row, 16-byte loads (ld is a multiple
+// of 64 and the padding of Cinv's rows and of yc holds zeros)
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_coarse_rows(int nc, const int *__restrict__ idx,
+__global__ void __launch_bounds__(kBlock) k_coarse_rows(int nc, int ld, const int *__restrict__ idx,
                                                         const T *__restrict__ cinv, const T *__restrict__ yc,
                                                         T *__restrict__ z, const int *skip)
 {
     if (skip && *skip) return;
+    using V = typename Vec16<T>::type;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= nc) return;
-    const T *a = cinv + int64_t(row) * nc;
-    double acc = 0.0;
-    for (int c = lane; c < nc; c += 64) acc += double(a[c]) * double(yc[c]);
-    acc = wave_sum(acc);
+    const V *a = reinterpret_cast<const V *>(cinv + int64_t(row) * ld);
+    const V *y = reinterpret_cast<const V *>(yc);
+    const int nv = ld / Vec16<T>::n;
+    double acc0 = 0.0, acc1 = 0.0;
+    int c = lane;
+    for (; c + 64 < nv; c += 128) {
+        const V a0 = nt_load(a + c), a1 = nt_load(a + c + 64);
+        acc0 += Vec16<T>::dot(a0, y[c]);
+        acc1 += Vec16<T>::dot(a1, y[c + 64]);
+    }
+    for (; c < nv; c += 64) acc0 += Vec16<T>::dot(nt_load(a + c), y[c]);
+    const double acc = wave_sum(acc0 + acc1);
     if (lane == 0) z[idx[row]] = T(acc);
 }
 
 template <typename T>
-void launch_coarse_idx(int nc, const int *idx, const T *cinv, const T *y, T *yc, T *z, hipStream_t s,
+void launch_coarse_idx(int nc, int ld, const int *idx, const T *cinv, const T *y, T *yc, T *z, hipStream_t s,
                        const int *skip)
 {
     if (nc <= 0) return;
     hipLaunchKernelGGL(k_gather<T>, dim3(nblocks(nc)), dim3(kBlock), 0, s, nc, idx, y, yc, skip);
-    hipLaunchKernelGGL(k_coarse_rows<T>, dim3(nblocks(nc, kBlock / 64)), dim3(kBlock), 0, s, nc, idx, cinv, yc, z,
-                       skip);
+    hipLaunchKernelGGL(k_coarse_rows<T>, dim3(nblocks(nc, kBlock / 64)), dim3(kBlock), 0, s, nc, ld, idx, cinv, yc,
+                       z, skip);
 }
 
 template <typename T>
@@ -269,10 +302,11 @@ void launch_up(const DevLevel<T> &lv, const T *w, T *x, hipStream_t s, const int
                        lv.gt_val, lv.bd, lv.bo, lv.bp, w, x, skip);
 }
 template <typename T>
-void launch_coarse(int nc, int off, const T *cinv, const T *w, T *x, hipStream_t s, const int *skip)
+void launch_coarse(int nc, int ld, int off, const T *cinv, const T *w, T *x, hipStream_t s, const int *skip)
 {
     if (nc <= 0) return;
-    hipLaunchKernelGGL(k_coarse<T>, dim3(nblocks(nc, kBlock / 64)), dim3(kBlock), 0, s, nc, off, cinv, w, x, skip);
+    hipLaunchKernelGGL(k_coarse<T>, dim3(nblocks(nc, kBlock / 64)), dim3(kBlock), 0, s, nc, ld, off, cinv, w, x,
+                       skip);
 }
 
 // ---------------------------------------------------------------------------------
@@ -727,28 +761,25 @@ void launch_sqmr_scalar_start(SqmrState *st, const double *rr, const double *rho
     hipLaunchKernelGGL(k_sqmr_start, dim3(1), dim3(64), 0, s, st, rr, rho);
 }
 
-__global__ void k_sqmr_alpha(SqmrState *st, const double *sigma)
+// scalar steps of simplified QMR, run by one thread after the reduction they need
+__device__ inline void sqmr_alpha(SqmrState *st, double sigma)
 {
-    if (threadIdx.x != 0 || st->done) return;
-    st->sigma = *sigma;
-    if (st->sigma == 0.0 || !isfinite(st->sigma)) {
+    if (st->done) return;
+    st->sigma = sigma;
+    if (sigma == 0.0 || !isfinite(sigma)) {
         st->breakdown = 1;
         st->done = 1;
         st->done_next = 1;
         return;
     }
-    st->alpha = st->rho / st->sigma;
-}
-void launch_sqmr_scalar_alpha(SqmrState *st, const double *sigma, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_sqmr_alpha, dim3(1), dim3(64), 0, s, st, sigma);
+    st->alpha = st->rho / sigma;
 }
 
-__global__ void k_sqmr_theta(SqmrState *st, const double *rr)
+__device__ inline void sqmr_theta(SqmrState *st, double rr)
 {
-    if (threadIdx.x != 0 || st->done) return;
-    st->rr = *rr;
-    const double th = sqrt(st->rr) / st->tau;
+    if (st->done) return;
+    st->rr = rr;
+    const double th = sqrt(rr) / st->tau;
     const double c2 = 1.0 / (1.0 + th * th);
     st->tau = st->tau * th * sqrt(c2);
     st->c1 = c2 * st->theta_old * st->theta_old;
@@ -758,16 +789,12 @@ __global__ void k_sqmr_theta(SqmrState *st, const double *rr)
     st->j += 1;
     if (st->tau * sqrt(double(st->j + 1)) <= st->tol * st->tau0 || !isfinite(st->tau)) st->done_next = 1;
 }
-void launch_sqmr_scalar_theta(SqmrState *st, const double *rr, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_sqmr_theta, dim3(1), dim3(64), 0, s, st, rr);
-}
 
-__global__ void k_sqmr_beta(SqmrState *st, const double *rho)
+// rn is read only when neither flag is set (then the reduction ran)
+__device__ inline void sqmr_beta(SqmrState *st, const double *rn_p)
 {
-    if (threadIdx.x != 0) return;
     if (!st->done && !st->done_next) {
-        const double rn = *rho;
+        const double rn = *rn_p;
         if (rn == 0.0 || !isfinite(rn)) {
             st->breakdown = 1;
             st->done_next = 1;
@@ -778,9 +805,47 @@ __global__ void k_sqmr_beta(SqmrState *st, const double *rho)
     }
     st->done = st->done_next;
 }
-void launch_sqmr_scalar_beta(SqmrState *st, const double *rho, hipStream_t s)
+
+enum SqmrOp { kOpAlpha = 0, kOpTheta = 1, kOpBeta = 2 };
+
+// out = sum of nparts partial sums (skipped, out untouched, when *skip), then one
+// scalar step of simplified QMR by thread 0 (always run: it tests the flags itself)
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_final_sum_sqmr(int nparts, const double *__restrict__ partial,
+                                                           double *__restrict__ out, const int *skip, SqmrState *st)
 {
-    hipLaunchKernelGGL(k_sqmr_beta, dim3(1), dim3(64), 0, s, st, rho);
+    __shared__ double sh[kBlock / 64];
+    if (!*skip) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < nparts; b += kBlock) a += partial[b];
+        const double r = block_sum(a, sh);
+        if (threadIdx.x == 0) *out = r;
+    }
+    if (threadIdx.x != 0) return;
+    __threadfence_block();
+    if (OP == kOpAlpha) sqmr_alpha(st, *out);
+    else if (OP == kOpTheta) sqmr_theta(st, *out);
+    else sqmr_beta(st, out);
+}
+
+template <typename T>
+void launch_sqmr_dot_alpha(int n, const T *q, const T *t, double *partial, double *sigma, SqmrState *st,
+                           hipStream_t s)
+{
+    const int nb = red_blocks(n);
+    hipLaunchKernelGGL(k_multidot_partial<T>, dim3(nb, 1), dim3(kBlock), 0, s, n, 1, q, int64_t(n), t, partial,
+                       kRedBlocks, &st->done);
+    hipLaunchKernelGGL(k_final_sum_sqmr<kOpAlpha>, dim3(1), dim3(kBlock), 0, s, nb, partial, sigma, &st->done, st);
+}
+
+template <typename T>
+void launch_sqmr_dot_beta(int n, const T *r, const T *u, double *partial, double *rho, SqmrState *st,
+                          hipStream_t s)
+{
+    const int nb = red_blocks(n);
+    hipLaunchKernelGGL(k_multidot_partial<T>, dim3(nb, 1), dim3(kBlock), 0, s, n, 1, r, int64_t(n), u, partial,
+                       kRedBlocks, &st->done_next);
+    hipLaunchKernelGGL(k_final_sum_sqmr<kOpBeta>, dim3(1), dim3(kBlock), 0, s, nb, partial, rho, &st->done_next, st);
 }
 
 // r -= alpha t, with the partial sums of |r|^2
@@ -805,7 +870,7 @@ void launch_sqmr_update_r(int n, SqmrState *st, const T *t, T *r, double *partia
 {
     const int nb = red_blocks(n);
     hipLaunchKernelGGL(k_sqmr_update_r<T>, dim3(nb), dim3(kBlock), 0, s, n, st, t, r, partial);
-    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, s, nb, kRedBlocks, partial, rr, &st->done);
+    hipLaunchKernelGGL(k_final_sum_sqmr<kOpTheta>, dim3(1), dim3(kBlock), 0, s, nb, partial, rr, &st->done, st);
 }
 
 // d = c1 d + c2 q ; x += d
@@ -867,8 +932,8 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
     template void launch_scatter<T>(int, const int *, const T *, T *, hipStream_t, const int *);           \
     template void launch_down<T>(const DevLevel<T> &, T *, hipStream_t, const int *);                      \
     template void launch_up<T>(const DevLevel<T> &, const T *, T *, hipStream_t, const int *);             \
-    template void launch_coarse<T>(int, int, const T *, const T *, T *, hipStream_t, const int *);         \
-    template void launch_coarse_idx<T>(int, const int *, const T *, const T *, T *, T *, hipStream_t,      \
+    template void launch_coarse<T>(int, int, int, const T *, const T *, T *, hipStream_t, const int *);    \
+    template void launch_coarse_idx<T>(int, int, const int *, const T *, const T *, T *, T *, hipStream_t, \
                                        const int *);                                                       \
     template void launch_dinv<T>(int, const T *, const T *, const int *, const T *, T *, hipStream_t,      \
                                  const int *);                                                             \
@@ -879,6 +944,10 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
                                    const int *, double);                                                   \
     template void launch_sqmr_init<T>(int, const T *, T *, T *, T *, hipStream_t);                        \
     template void launch_sqmr_update_r<T>(int, SqmrState *, const T *, T *, double *, double *,           \
+                                          hipStream_t);                                                    \
+    template void launch_sqmr_dot_alpha<T>(int, const T *, const T *, double *, double *, SqmrState *,     \
+                                           hipStream_t);                                                   \
+    template void launch_sqmr_dot_beta<T>(int, const T *, const T *, double *, double *, SqmrState *,      \
                                           hipStream_t);                                                    \
     template void launch_sqmr_update_xd<T>(int, SqmrState *, const T *, T *, T *, hipStream_t);           \
     template void launch_sqmr_update_q<T>(int, SqmrState *, const T *, T *, hipStream_t);
