@@ -241,7 +241,7 @@ def main():
         "config": {"workload": f"Anderson {L}^3 periodic, W=16.5, seed 0, 10 eigenpairs nearest 0, tol 1e-10, "
                                f"FP32 inner / FP64 outer", "L": L, "n": L ** 3, "k": k, "sigma": sigma,
                    "W": W, "tol": tol},
-        "setup_s": round(setup_wall, 3),
+        "setup_s": round(setup_wall, 3), "device_bytes": int(infos[-1]["device_bytes"]),
         "outer_its": infos[-1]["outer_its"], "inner_its": infos[-1]["inner_its"],
         "levels": pinfo["levels"], "coarse_n": pinfo["coarse_n"], "fill": round(pinfo["fill"], 3),
         "max_resid_over_anorm": float(np.nanmax(res)),

@@ -55,3 +55,12 @@ def test_poll_and_unknown_ticket():
     with pytest.raises(jd.JdError):
         srv.poll(t)  # released after it was returned
     srv.close()
+
+
+@pytest.mark.parametrize("L,W,k", [(20, 12.0, 10), (40, 16.5, 1), (40, 12.0, 10)])
+def test_footprint_estimate_covers_the_device_memory(L, W, k):
+    # admission reserves the estimate: the memory a request really holds must not exceed it
+    req = jd.Server.request(L, W, 1000000 + L, 0.1, k)
+    _, _, _, info = jd.solve(L, W, 1000000 + L, 0.1, k, 1e-10, precision="mixed")
+    assert info["status"] == 0
+    assert 0 < info["device_bytes"] <= jd.Server.footprint(req)
