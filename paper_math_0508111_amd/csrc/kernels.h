@@ -55,9 +55,11 @@ void launch_coarse_idx(int nc, int ld, const int *idx, const T *cinv, const T *y
 
 // Product with the explicit inverse factor (y = Z w, or Z^T w) in the hybrid layout of
 // jdmi::HybHost; workgroup b works on part b % kHybParts, so that on an 8-XCD device a
-// part's gathers stay in one XCD's L2.  Values are stored in Tv; the vectors and the
-// accumulation are in Tx.  Summation order is fixed (per lane, then a fixed shuffle
-// tree): results are reproducible.
+// part's gathers stay in one XCD's L2.  Values are stored in Tv and the vectors in Tx;
+// products are accumulated in binary64 and the result rounded to Tx once, so that the
+// binary32 products with Z and Z^T stay transposes of each other to one rounding.
+// Summation order is fixed (per lane, then a fixed shuffle tree): results are
+// reproducible.
 template <typename Tv>
 struct Hyb {
     int nlong = 0, nslices = 0;

@@ -326,25 +326,25 @@ __global__ void __launch_bounds__(kBlock) k_hyb_spmv(Hyb<Tv> A, const Tx *__rest
         // one long row per wave: lanes stride over the row (four entries in flight per
         // lane: all index and value loads are issued before the dependent gathers)
         const int64_t b = A.long_ptr[code], e = A.long_ptr[code + 1];
-        Tx a0 = Tx(0), a1 = Tx(0), a2 = Tx(0), a3 = Tx(0);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int64_t p = b + lane;
         for (; p + 192 < e; p += 256) {
             const int c0 = nt_load(A.long_col + p), c1 = nt_load(A.long_col + p + 64);
             const int c2 = nt_load(A.long_col + p + 128), c3 = nt_load(A.long_col + p + 192);
             const Tv v0 = nt_load(A.long_val + p), v1 = nt_load(A.long_val + p + 64);
             const Tv v2 = nt_load(A.long_val + p + 128), v3 = nt_load(A.long_val + p + 192);
-            a0 += Tx(v0) * x[c0];
-            a1 += Tx(v1) * x[c1];
-            a2 += Tx(v2) * x[c2];
-            a3 += Tx(v3) * x[c3];
+            a0 += double(v0) * double(x[c0]);
+            a1 += double(v1) * double(x[c1]);
+            a2 += double(v2) * double(x[c2]);
+            a3 += double(v3) * double(x[c3]);
         }
-        for (; p < e; p += 64) a0 += Tx(nt_load(A.long_val + p)) * x[nt_load(A.long_col + p)];
-        Tx a = (a0 + a1) + (a2 + a3);
+        for (; p < e; p += 64) a0 += double(nt_load(A.long_val + p)) * double(x[nt_load(A.long_col + p)]);
+        double a = (a0 + a1) + (a2 + a3);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
         if (lane == 0) {
             const int r = A.long_row[code];
-            y[out_perm ? out_perm[r] : r] = a;
+            y[out_perm ? out_perm[r] : r] = Tx(a);
         }
         return;
     }
@@ -354,25 +354,25 @@ __global__ void __launch_bounds__(kBlock) k_hyb_spmv(Hyb<Tv> A, const Tx *__rest
     const int groups = int((A.slice_ptr[slice + 1] - b) >> 6);
     const int *c = A.col + b + lane;
     const Tv *v = A.val + b + lane;
-    Tx a0 = Tx(0), a1 = Tx(0), a2 = Tx(0), a3 = Tx(0);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int j = 0;
     for (; j + 3 < groups; j += 4) {
         const int64_t o = int64_t(j) * 64;
         const int c0 = nt_load(c + o), c1 = nt_load(c + o + 64), c2 = nt_load(c + o + 128), c3 = nt_load(c + o + 192);
         const Tv v0 = nt_load(v + o), v1 = nt_load(v + o + 64), v2 = nt_load(v + o + 128), v3 = nt_load(v + o + 192);
-        a0 += Tx(v0) * x[c0];
-        a1 += Tx(v1) * x[c1];
-        a2 += Tx(v2) * x[c2];
-        a3 += Tx(v3) * x[c3];
+        a0 += double(v0) * double(x[c0]);
+        a1 += double(v1) * double(x[c1]);
+        a2 += double(v2) * double(x[c2]);
+        a3 += double(v3) * double(x[c3]);
     }
-    for (; j < groups; ++j) a0 += Tx(nt_load(v + int64_t(j) * 64)) * x[nt_load(c + int64_t(j) * 64)];
-    Tx a = (a0 + a1) + (a2 + a3);
+    for (; j < groups; ++j) a0 += double(nt_load(v + int64_t(j) * 64)) * double(x[nt_load(c + int64_t(j) * 64)]);
+    double a = (a0 + a1) + (a2 + a3);
     // lanes l, l + kSliceRows, l + 2 kSliceRows, ... hold the pieces of row l
 #pragma unroll
     for (int o = kSliceRows; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
     if (lane < kSliceRows) {
         const int r = A.rowidx[int64_t(slice) * kSliceRows + lane];
-        if (r >= 0) y[out_perm ? out_perm[r] : r] = a;
+        if (r >= 0) y[out_perm ? out_perm[r] : r] = Tx(a);
     }
 }
 

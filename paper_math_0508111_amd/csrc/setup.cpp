@@ -905,8 +905,25 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L)
             Z.site_of[q] = ml.perm[keyed[q].second];
         }
     }
-    std::vector<int> pos_of(n);
-    for (int p = 0; p < n; ++p) pos_of[newidx[p]] = p;
+    // numbering of the product's middle vector (Z's rows, Z^T's columns, D^{-1}): blocks
+    // of kMidBlock consecutive Morton ranks, by elimination level inside a block. The
+    // rows of Z^T (pivots) then find their later-level dependants packed together,
+    // which cuts the cache lines each of Z^T's gathers touches by about a third.
+    std::vector<int> midx(n), pos_of(n);
+    {
+        std::vector<int> level(n, int(ml.levels.size()));
+        for (size_t l = 0; l < ml.levels.size(); ++l)
+            for (int t = 0; t < ml.levels[l].nB; ++t) level[ml.levels[l].off + t] = int(l);
+        std::vector<std::tuple<int, int, int>> keyed(n);
+        for (int p = 0; p < n; ++p) keyed[p] = {newidx[p] / kMidBlock, level[p], newidx[p]};
+        std::vector<int> order(n);
+        std::iota(order.begin(), order.end(), 0);
+        std::sort(order.begin(), order.end(), [&](int a, int b) { return keyed[a] < keyed[b]; });
+        for (int m = 0; m < n; ++m) {
+            midx[order[m]] = m;
+            pos_of[m] = order[m];
+        }
+    }
     Z.ptr.assign(n + 1, 0);
     for (int q = 0; q < n; ++q) Z.ptr[q + 1] = Z.ptr[q] + int64_t(rows[pos_of[q]].size());
     Z.col.resize(Z.ptr[n]);
@@ -938,13 +955,13 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L)
     for (int q = 0; q < n; ++q) Z.dp[q] = q;
     for (const auto &Lv : ml.levels)
         for (int t = 0; t < Lv.nB; ++t) {
-            const int q = newidx[Lv.off + t];
+            const int q = midx[Lv.off + t];
             Z.dd[q] = Lv.bd[t];
             Z.dof[q] = Lv.bo[t];
-            Z.dp[q] = newidx[Lv.bp[t]];
+            Z.dp[q] = midx[Lv.bp[t]];
         }
     Z.coarse_idx.resize(ml.coarse_n);
-    for (int i = 0; i < ml.coarse_n; ++i) Z.coarse_idx[i] = newidx[ml.coarse_off + i];
+    for (int i = 0; i < ml.coarse_n; ++i) Z.coarse_idx[i] = midx[ml.coarse_off + i];
     Z.seconds = now_s() - t0;
 }
 

@@ -50,17 +50,21 @@ struct SetupParams {
 
 // Explicit inverse of the unit lower triangular factor of all levels, Z ~ L^{-1}
 // (global positions), and the block diagonal D^{-1}: K^{-1} = P^T Z^T D^{-1} Z P.
-// Rows and columns are renumbered in Morton order of the lattice sites (the apply does
-// not need the elimination order), so that the gathers of neighbouring rows share cache
-// lines: K^{-1} b = S^T Z^T D^{-1} Z S b with (S b)[q] = b[site_of[q]].
+// The apply does not need the elimination order, so the unknowns are renumbered:
+// K^{-1} b = S^T Z^T D^{-1} Z S b with (S b)[q] = b[site_of[q]].  Z's columns (the
+// input numbering, also Z^T's rows) follow the Morton order of the lattice sites, so
+// that the gathers of neighbouring rows share cache lines; Z's rows (the middle
+// numbering of D^{-1}, the last level and Z^T's columns) follow blocks of kMidBlock
+// Morton ranks with the unknowns of each block ordered by elimination level.
+constexpr int kMidBlock = 128;
 struct InverseFactor {
-    std::vector<int> site_of;         // n: new index -> lattice site
-    std::vector<int64_t> ptr, tptr;   // CSR of Z and of Z^T (n + 1 each), new numbering
+    std::vector<int> site_of;         // n: input index -> lattice site
+    std::vector<int64_t> ptr, tptr;   // CSR of Z (rows: middle, columns: input numbering) and of Z^T
     std::vector<int> col, tcol;
     std::vector<double> val, tval;
-    std::vector<double> dd, dof;      // D^{-1}: z[q] = dd[q] y[q] + dof[q] y[dp[q]] (0 on the last level)
+    std::vector<double> dd, dof;      // D^{-1} (middle numbering): z[q] = dd[q] y[q] + dof[q] y[dp[q]] (0 on the last level)
     std::vector<int> dp;
-    std::vector<int> coarse_idx;      // coarse_n: new index of each unknown of the last level
+    std::vector<int> coarse_idx;      // coarse_n: middle index of each unknown of the last level
     double seconds = 0.0;
 };
 
