@@ -73,11 +73,15 @@ enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
  *  z_drop     the preconditioner is applied as P^T Z^T D^{-1} Z P with Z the explicit
  *             inverse of the unit lower triangular factor of all levels; entries of Z
  *             below z_drop (scaled domain) are dropped (0 -> 1e-2; < 0 -> none).
- *  jmin, jmax search-space sizes after / before a restart (0 -> max(k+5,10), 2 jmin).
+ *  jmin, jmax search-space sizes after / before a restart (0 -> for n >= 2^19
+ *             max(k+20,30) and min(3 jmin, 120), else max(k+5,10) and min(2 jmin, 120));
+ *             jmax <= 120.
  *  max_outer  outer Jacobi-Davidson iterations (0 -> 60 k + 200).
  *  max_inner  SQMR steps per correction equation (0 -> 40).
  *  switch_tol the correction operator uses sigma until ||r|| < switch_tol ||A||_inf,
- *             then the Ritz value theta (0 -> 1e-3).
+ *             then the Ritz value theta; < 0: always sigma (0 -> 1e-3, and always
+ *             sigma for JD_MIXED, whose binary32 inner solves lose accuracy on the
+ *             nearly singular A - theta I).
  *  flags      bit 0 (JD_FLAG_GRAPHS): replay the inner iteration as a captured HIP graph
  *             instead of launching it kernel by kernel (same kernels in the same order,
  *             same results; the serving workers always launch kernel by kernel).
@@ -145,9 +149,15 @@ int jd_setup(int L, double W, uint64_t seed, double sigma, const jd_options *opt
  * array of n*k binary64 values that receives the eigenvectors. */
 int jd_problem_solve(jd_problem *p, int k, double tol, double *evals, double *evecs_host,
                      void *evecs_device, double *resid, jd_info *info);
-/* Switch the precision of later jd_problem_solve calls (JD_FP64 or JD_MIXED); the setup
- * keeps the factors in both precisions, so no new setup is needed. */
+/* Switch the precision of later jd_problem_solve calls (JD_FP64, JD_MIXED or
+ * JD_MIXED_FACTORS); the setup keeps the factors in both precisions, so no new setup
+ * is needed. */
 int jd_problem_set_precision(jd_problem *p, int precision);
+/* Replace the solve-time options of later jd_problem_solve calls: jmin, jmax,
+ * max_outer, max_inner, switch_tol and the JD_FLAG_GRAPHS bit of flags are taken from
+ * *opt (0 -> the default, as in jd_setup); every setup option of *opt is ignored.
+ * JD_EINVAL for out-of-range values, and the problem keeps its previous options. */
+int jd_problem_set_solve_options(jd_problem *p, const jd_options *opt);
 /* Setup statistics of a problem (levels, fill, timings so far). */
 int jd_problem_info(const jd_problem *p, jd_info *info);
 void jd_problem_free(jd_problem *p);

@@ -67,7 +67,7 @@ class Info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-EXPORTS = ["jd_solve", "jd_setup", "jd_problem_solve", "jd_problem_info", "jd_problem_set_precision", "jd_problem_free", "jd_gen_diag",
+EXPORTS = ["jd_solve", "jd_setup", "jd_problem_solve", "jd_problem_info", "jd_problem_set_precision", "jd_problem_set_solve_options", "jd_problem_free", "jd_gen_diag",
            "jd_stencil_spmv", "jd_precond_create", "jd_precond_apply", "jd_precond_levels", "jd_precond_free", "jd_problem_precond", "jd_precond_factor_nnz",
            "jd_precond_factor_product",
            "jd_problem_linear_solve", "jd_last_error", "jd_version", "jd_server_create", "jd_server_submit",
@@ -180,6 +180,11 @@ class Problem:
 
     def set_precision(self, precision):
         _check(lib().jd_problem_set_precision(self._h, _PREC[precision]))
+
+    def set_solve_options(self, **opts):
+        """jd_problem_set_solve_options: jmin, jmax, max_outer, max_inner, switch_tol, flags."""
+        o = make_options(**opts)
+        _check(lib().jd_problem_set_solve_options(self._h, ctypes.byref(o)))
 
     def precond(self):
         """A view of the problem's preconditioner (keep the problem alive while using it)."""

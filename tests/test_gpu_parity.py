@@ -237,3 +237,48 @@ def test_solve_on_recycled_memory(L, W, seed, sigma, k):
         evals, _, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, precision=precision)
         assert info["status"] == 0 and info["n_converged"] == k
         assert np.max(np.abs(np.sort(evals) - np.sort(ref))) <= 1e-9
+
+
+# --- edge cases -------------------------------------------------------------------------------
+
+def test_solve_every_eigenpair_of_the_smallest_lattice():
+    # L = 2: n = 8 and k = n (the whole spectrum; the last level is the whole matrix)
+    L, W, seed, sigma = 2, 16.5, 11, 0.0
+    ref, X, _, _ = eig.anderson_nearest(L, W, seed, sigma, 8, method="dense")
+    evals, evecs, resid, info = jd.solve(L, W, seed, sigma, 8, 1e-10, vectors=True, precision="fp64")
+    _check_pairs(L, W, seed, sigma, 8, ref, evals, evecs, resid, info, vec_ref=X)
+
+
+@pytest.mark.parametrize("L,k,precision", [(3, 1, "fp64"), (5, 1, "mixed"), (6, 64, "fp64"), (7, 64, "mixed_factors")])
+def test_solve_odd_lattices_and_the_largest_k(L, k, precision):
+    W, seed, sigma = 12.0, 21, 0.25
+    ref, X, _, _ = eig.anderson_nearest(L, W, seed, sigma, k, method="dense")
+    evals, evecs, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, vectors=True, precision=precision)
+    _check_pairs(L, W, seed, sigma, k, ref, evals, evecs, resid, info)
+
+
+def test_partial_convergence_reports_what_converged():
+    # an outer-iteration cap too small for k pairs: JD_ENOCONV, the converged pairs are
+    # exact, the others NaN
+    L, W, seed, sigma, k = 10, 16.5, 0, 0.0, 5
+    ref, _, _, _ = eig.anderson_nearest(L, W, seed, sigma, k)
+    evals, _, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, precision="fp64", max_outer=6)
+    assert info["status"] == 1 and info["outer_its"] == 6 and info["n_converged"] < k
+    got = evals[: info["n_converged"]]
+    assert np.all(np.isnan(evals[info["n_converged"]:]))
+    for v in got:  # each converged value is one of the wanted ones (or the next few)
+        assert np.min(np.abs(eig.anderson_nearest(L, W, seed, sigma, k + 5)[0] - v)) <= 1e-9
+    assert np.all(resid[: info["n_converged"]] <= 1e-10 * 1.0001)
+
+
+def test_solve_options_setter():
+    p = jd.Problem(12, 16.5, 3, 0.0, precision="fp64")
+    ref = eig.anderson_nearest(12, 16.5, 3, 0.0, 4)[0]
+    e0, _, _, i0 = p.solve(4, 1e-10)
+    p.set_solve_options(jmin=12, jmax=40, max_inner=60, switch_tol=1e-6)
+    e1, _, _, i1 = p.solve(4, 1e-10)
+    assert i0["status"] == 0 and i1["status"] == 0
+    assert np.max(np.abs(np.sort(e0) - np.sort(ref))) <= 1e-9 and np.max(np.abs(np.sort(e1) - np.sort(ref))) <= 1e-9
+    with pytest.raises(jd.JdError):
+        p.set_solve_options(jmax=121)
+    p.close()
