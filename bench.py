@@ -31,6 +31,8 @@ def parse():
     ap.add_argument("--L", type=int, default=100)
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seeds", type=str, default="",
+                    help="comma-separated extra disorder seeds: one setup and one solve each, reported as 'seeds'")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=16, help="0 disables the serving leg")
     ap.add_argument("--serve-workers", type=int, default=8)
@@ -238,7 +240,7 @@ def main():
         "value": round(value, 4), "unit": "eigenpairs/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(1e3 * T / a.steps, 2), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32-inner/f64-outer", "data": "synthetic",
-        "config": {"workload": f"Anderson {L}^3 periodic, W=16.5, seed 0, 10 eigenpairs nearest 0, tol 1e-10, "
+        "config": {"workload": f"Anderson {L}^3 periodic, W=16.5, seed 0, {k} eigenpairs nearest 0, tol 1e-10, "
                                f"FP32 inner / FP64 outer", "L": L, "n": L ** 3, "k": k, "sigma": sigma,
                    "W": W, "tol": tol},
         "setup_s": round(setup_wall, 3), "device_bytes": int(infos[-1]["device_bytes"]),
@@ -263,6 +265,19 @@ def main():
     out["roofline"] = factor_roofline(torch, prob, L ** 3)
     out["stencil"] = stencil_bandwidth(jd, torch, L, W, seed)
     prob.close()
+    if a.seeds:
+        # seed-to-seed spread of the same workload (other disorder realisations)
+        out["seeds"] = []
+        for sd in [int(v) for v in a.seeds.split(",") if v.strip()]:
+            p2 = jd.Problem(L, W, sd, sigma, precision="mixed")
+            e2, _, r2, i2 = p2.solve(k, tol)
+            p2.close()
+            out["seeds"].append({"seed": sd, "setup_s": round(i2["setup_s"], 2), "solve_s": round(i2["solve_s"], 3),
+                                 "outer_its": i2["outer_its"], "inner_its": i2["inner_its"],
+                                 "converged": i2["n_converged"], "value": round(i2["n_converged"] / i2["solve_s"], 4),
+                                 "max_resid_over_anorm": float(np.nanmax(r2))})
+            print(f"# seed {sd}: setup {i2['setup_s']:.1f} s, solve {i2['solve_s']:.3f} s, outer {i2['outer_its']}, "
+                  f"inner {i2['inner_its']}, converged {i2['n_converged']}", file=sys.stderr, flush=True)
     if a.serve_requests > 0:
         out["serving"] = serving(jd, a.serve_requests, a.serve_workers)
     if not a.no_cpu_baseline:

@@ -72,7 +72,8 @@ enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
  *  max_levels cap on the number of levels (0 -> 400).
  *  z_drop     the preconditioner is applied as P^T Z^T D^{-1} Z P with Z the explicit
  *             inverse of the unit lower triangular factor of all levels; entries of Z
- *             below z_drop (scaled domain) are dropped (0 -> 1e-2; < 0 -> none).
+ *             below z_drop (scaled domain) are dropped (0 -> min(1e-2, 10 drop_tol);
+ *             < 0 -> none).
  *  jmin, jmax search-space sizes after / before a restart (0 -> for n >= 2^19
  *             max(k+20,30) and min(3 jmin, 120), else max(k+5,10) and min(2 jmin, 120));
  *             jmax <= 120.

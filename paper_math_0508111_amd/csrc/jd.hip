@@ -277,7 +277,11 @@ void fill_defaults(jd_options &o, int n)
     if (o.schur_tol == 0) o.schur_tol = o.drop_tol > 0 ? 0.5 * o.drop_tol : -1.0;
     if (o.coarse_max == 0) o.coarse_max = 1536;
     if (o.max_levels == 0) o.max_levels = 400;
-    if (o.z_drop == 0) o.z_drop = o.drop_tol < 0 ? -1.0 : 1e-2;
+    // the explicit inverse factor drops relative to 10 epsilon (at most 1e-2): with the
+    // paper's epsilon = 1/sqrt(n) that is 1e-2 up to n = 10^6 and tighter beyond, where a
+    // fixed 1e-2 left the preconditioner too coarse (L = 150: 626 instead of 158 outer
+    // iterations)
+    if (o.z_drop == 0) o.z_drop = o.drop_tol < 0 ? -1.0 : std::min(1e-2, 10.0 * o.drop_tol);
     if (o.max_inner == 0) o.max_inner = 40;
 }
 
@@ -1357,7 +1361,9 @@ size_t footprint_estimate(const jd_request &r)
     // factors in both precisions (inverse factor ~ 100 entries per unknown, twice,
     // with padding), search space V, AV and restart buffer, projection blocks, SQMR
     // and preconditioner work vectors, the dense last level, and a fixed reserve
-    const double per_unknown = 4800.0 + 24.0 * jmax + 32.0 * (r.k + 1) + 200.0;
+    const double z_drop = std::min(1e-2, 10.0 / std::sqrt(n));  // the default of fill_defaults
+    const double factors = 4800.0 * std::sqrt(1e-2 / z_drop);      // more entries per row below 1e-2
+    const double per_unknown = factors + 24.0 * jmax + 32.0 * (r.k + 1) + 200.0;
     return size_t(n * per_unknown + nc * nc * 12.0 + 64.0 * (1 << 20));
 }
 
