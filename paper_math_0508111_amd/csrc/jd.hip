@@ -1362,7 +1362,7 @@ size_t footprint_estimate(const jd_request &r)
     // with padding), search space V, AV and restart buffer, projection blocks, SQMR
     // and preconditioner work vectors, the dense last level, and a fixed reserve
     const double z_drop = std::min(1e-2, 10.0 / std::sqrt(n));  // the default of fill_defaults
-    const double factors = 4800.0 * std::sqrt(1e-2 / z_drop);      // more entries per row below 1e-2
+    const double factors = 5400.0 * std::sqrt(1e-2 / z_drop);      // more entries per row below 1e-2
     const double per_unknown = factors + 24.0 * jmax + 32.0 * (r.k + 1) + 200.0;
     return size_t(n * per_unknown + nc * nc * 12.0 + 64.0 * (1 << 20));
 }
