@@ -77,9 +77,6 @@ struct Hyb {
 // out_perm (optional): y[out_perm[r]] = (Z w)[r]
 template <typename Tv, typename Tx>
 void launch_hyb_spmv(const Hyb<Tv> &A, const Tx *x, Tx *y, const int *out_perm, hipStream_t s, const int *skip);
-// w[p] = Tout(b[perm[p]])
-template <typename Tin, typename Tout>
-void launch_gather_cvt(int n, const int *perm, const Tin *b, Tout *w, hipStream_t s, const int *skip);
 
 // z[j] = dd[j] y[j] + dof[j] y[dp[j]] for j < m
 template <typename T>

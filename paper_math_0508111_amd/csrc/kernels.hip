@@ -392,21 +392,6 @@ template void launch_hyb_spmv<double, double>(const Hyb<double> &, const double 
 template void launch_hyb_spmv<float, double>(const Hyb<float> &, const double *, double *, const int *, hipStream_t,
                                              const int *);
 
-template <typename Tin, typename Tout>
-__global__ void __launch_bounds__(kBlock) k_gather_cvt(int n, const int *__restrict__ perm, const Tin *__restrict__ b,
-                                                       Tout *__restrict__ w, const int *skip)
-{
-    if (skip && *skip) return;
-    const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p < n) w[p] = Tout(b[perm[p]]);
-}
-template <typename Tin, typename Tout>
-void launch_gather_cvt(int n, const int *perm, const Tin *b, Tout *w, hipStream_t s, const int *skip)
-{
-    hipLaunchKernelGGL((k_gather_cvt<Tin, Tout>), dim3(nblocks(n)), dim3(kBlock), 0, s, n, perm, b, w, skip);
-}
-template void launch_gather_cvt<double, float>(int, const int *, const double *, float *, hipStream_t, const int *);
-template void launch_gather_cvt<double, double>(int, const int *, const double *, double *, hipStream_t, const int *);
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dinv(int m, const T *__restrict__ dd, const T *__restrict__ dof,
