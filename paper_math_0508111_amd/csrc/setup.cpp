@@ -343,6 +343,84 @@ struct Scaled {
 
 }  // namespace
 
+// (S + S^T) / 2 on the union pattern, rows sorted.  The transpose is built in parallel
+// from per-thread column counts over fixed row ranges, so its rows keep increasing row
+// order; the merge counts each output row, then writes it.
+static Csr symmetrize(const Csr &S)
+{
+    const int n = S.n;
+    Csr T;
+    T.n = n;
+    T.ptr.assign(n + 1, 0);
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+#endif
+    std::vector<std::vector<int64_t>> cnt(nt, std::vector<int64_t>(n + 1, 0));
+    auto range = [&](int t, int &a, int &b) {
+        a = int(int64_t(n) * t / nt);
+        b = int(int64_t(n) * (t + 1) / nt);
+    };
+    // one iteration per row range: every range is done whatever the team size
+#pragma omp parallel for schedule(static, 1)
+    for (int t = 0; t < nt; ++t) {
+        int a, b;
+        range(t, a, b);
+        auto &c = cnt[t];
+        for (int r = a; r < b; ++r)
+            for (int64_t p = S.ptr[r]; p < S.ptr[r + 1]; ++p) ++c[S.col[p]];
+    }
+    // offsets: column c of thread t starts after the entries of c from threads < t
+    for (int c = 0; c < n; ++c) {
+        int64_t o = T.ptr[c];
+        for (int t = 0; t < nt; ++t) {
+            const int64_t k = cnt[t][c];
+            cnt[t][c] = o;
+            o += k;
+        }
+        T.ptr[c + 1] = o;
+    }
+    T.col.resize(T.ptr[n]);
+    T.val.resize(T.ptr[n]);
+#pragma omp parallel for schedule(static, 1)
+    for (int t = 0; t < nt; ++t) {
+        int a, b;
+        range(t, a, b);
+        auto &fp = cnt[t];
+        for (int r = a; r < b; ++r)
+            for (int64_t p = S.ptr[r]; p < S.ptr[r + 1]; ++p) {
+                const int c = S.col[p];
+                T.col[fp[c]] = r;
+                T.val[fp[c]++] = S.val[p];
+            }
+    }
+    Csr U;
+    U.n = n;
+    U.ptr.assign(n + 1, 0);
+    // merged length of row r of S and row r of T (both sorted)
+    auto merge = [&](int r, int *col, double *val) {
+        int64_t a = S.ptr[r], ae = S.ptr[r + 1], b = T.ptr[r], be = T.ptr[r + 1], k = 0;
+        while (a < ae || b < be) {
+            int c;
+            double v;
+            if (b >= be || (a < ae && S.col[a] < T.col[b])) { c = S.col[a]; v = 0.5 * S.val[a]; ++a; }
+            else if (a >= ae || T.col[b] < S.col[a]) { c = T.col[b]; v = 0.5 * T.val[b]; ++b; }
+            else { c = S.col[a]; v = 0.5 * (S.val[a] + T.val[b]); ++a; ++b; }
+            if (col) { col[k] = c; val[k] = v; }
+            ++k;
+        }
+        return k;
+    };
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int r = 0; r < n; ++r) U.ptr[r + 1] = merge(r, nullptr, nullptr);
+    for (int r = 0; r < n; ++r) U.ptr[r + 1] += U.ptr[r];
+    U.col.resize(U.ptr[n]);
+    U.val.resize(U.ptr[n]);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int r = 0; r < n; ++r) merge(r, U.col.data() + U.ptr[r], U.val.data() + U.ptr[r]);
+    return U;
+}
+
 static std::string factor_level(const Csr &A, const SetupParams &prm, const std::vector<double> &d,
                                 const std::vector<std::pair<int, int>> &blocks, const std::vector<uint64_t> &key,
                                 LevelLocal &lv, Csr &S_next)
@@ -558,7 +636,7 @@ static std::string factor_level(const Csr &A, const SetupParams &prm, const std:
     {
         std::vector<double> acc(nC, 0.0);
         std::vector<int> mark(nC, -1), list;
-#pragma omp for schedule(dynamic, 512)
+#pragma omp for schedule(dynamic, 64)
         for (int r = 0; r < nC; ++r) {
             list.clear();
             const int i = lv.C[r];
@@ -582,63 +660,27 @@ static std::string factor_level(const Csr &A, const SetupParams &prm, const std:
                 if (tp != t)
                     for (int64_t q = gt_ptr[tp]; q < gt_ptr[tp + 1]; ++q) put(gt_col[q], -g * Bo[t] * gt_val[q]);
             }
-            std::sort(list.begin(), list.end());
             auto &out = srow[r];
             for (int c : list) {
                 const double v = acc[c];
                 if (c == r || std::fabs(v) >= stol) out.push_back({c, v});
             }
+            std::sort(out.begin(), out.end());  // columns are distinct: sorts by column
         }
     }
     S_next.ptr.assign(nC + 1, 0);
     for (int r = 0; r < nC; ++r) S_next.ptr[r + 1] = S_next.ptr[r] + int64_t(srow[r].size());
     S_next.col.resize(S_next.ptr[nC]);
     S_next.val.resize(S_next.ptr[nC]);
+#pragma omp parallel for schedule(dynamic, 256)
     for (int r = 0; r < nC; ++r) {
         int64_t p = S_next.ptr[r];
         for (auto &e : srow[r]) { S_next.col[p] = e.first; S_next.val[p] = e.second; ++p; }
+        std::vector<std::pair<int, double>>().swap(srow[r]);
     }
     // the computed Schur complement is symmetric up to rounding; enforce it by
     // averaging mirrored entries and keeping the union pattern
-    {
-        Csr T;
-        T.n = nC;
-        T.ptr.assign(nC + 1, 0);
-        for (int r = 0; r < nC; ++r)
-            for (int64_t p = S_next.ptr[r]; p < S_next.ptr[r + 1]; ++p) ++T.ptr[S_next.col[p] + 1];
-        for (int r = 0; r < nC; ++r) T.ptr[r + 1] += T.ptr[r];
-        T.col.resize(T.ptr[nC]);
-        T.val.resize(T.ptr[nC]);
-        std::vector<int64_t> fp(T.ptr.begin(), T.ptr.end() - 1);
-        for (int r = 0; r < nC; ++r)
-            for (int64_t p = S_next.ptr[r]; p < S_next.ptr[r + 1]; ++p) {
-                const int c = S_next.col[p];
-                T.col[fp[c]] = r;
-                T.val[fp[c]++] = S_next.val[p];
-            }
-        Csr U;
-        U.n = nC;
-        U.ptr.assign(nC + 1, 0);
-        std::vector<std::vector<std::pair<int, double>>> urow(nC);
-#pragma omp parallel for schedule(dynamic, 1024)
-        for (int r = 0; r < nC; ++r) {
-            int64_t a = S_next.ptr[r], ae = S_next.ptr[r + 1], b = T.ptr[r], be = T.ptr[r + 1];
-            auto &o = urow[r];
-            while (a < ae || b < be) {
-                if (b >= be || (a < ae && S_next.col[a] < T.col[b])) { o.push_back({S_next.col[a], 0.5 * S_next.val[a]}); ++a; }
-                else if (a >= ae || T.col[b] < S_next.col[a]) { o.push_back({T.col[b], 0.5 * T.val[b]}); ++b; }
-                else { o.push_back({S_next.col[a], 0.5 * (S_next.val[a] + T.val[b])}); ++a; ++b; }
-            }
-        }
-        for (int r = 0; r < nC; ++r) U.ptr[r + 1] = U.ptr[r] + int64_t(urow[r].size());
-        U.col.resize(U.ptr[nC]);
-        U.val.resize(U.ptr[nC]);
-        for (int r = 0; r < nC; ++r) {
-            int64_t p = U.ptr[r];
-            for (auto &e : urow[r]) { U.col[p] = e.first; U.val[p] = e.second; ++p; }
-        }
-        S_next = std::move(U);
-    }
+    S_next = symmetrize(S_next);
     return "";
 }
 
@@ -867,7 +909,7 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L)
         for (int m = 0; m <= nl; ++m) {
             const int r0 = (m < nl) ? ml.levels[m].off : ml.coarse_off;
             const int r1 = (m < nl) ? ml.levels[m].off + ml.levels[m].nB : n;
-#pragma omp for schedule(dynamic, 256)
+#pragma omp for schedule(dynamic, 16)
             for (int r = r0; r < r1; ++r) {
                 list.clear();
                 auto put = [&](int c, double v) {
@@ -883,8 +925,12 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L)
                         for (const auto &e : rows[Lv.g_col[p]]) put(e.first, -g * e.second);
                     }
                 }
-                std::sort(list.begin(), list.end());
+                // kept entries in any order: the assembly below renumbers and sorts each row
                 auto &out = rows[r];
+                size_t keep = 0;
+                for (int c : list)
+                    if (c == r || z_drop < 0 || std::fabs(acc[c]) * sc[r] / sc[c] >= z_drop) ++keep;
+                out.reserve(keep);
                 for (int c : list) {
                     const double v = acc[c];
                     if (c == r || z_drop < 0 || std::fabs(v) * sc[r] / sc[c] >= z_drop) out.push_back({c, v});
