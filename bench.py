@@ -259,9 +259,27 @@ def main():
                          "outer_its": i2["outer_its"], "inner_its": i2["inner_its"],
                          "converged": i2["n_converged"],
                          "max_abs_eval_diff_vs_mixed": float(np.nanmax(np.abs(e2 - ev)))}
+            gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                                f"L{L}_W16.5_s{seed}_k{k}.json")
+            if os.path.exists(gold):
+                with open(gold) as fh:
+                    out[name]["oracle_max_abs_err"] = float(np.nanmax(np.abs(e2 - np.array(json.load(fh)["lams"]))))
             print(f"# {name} solve {i2['solve_s']:.3f} s, outer {i2['outer_its']}, inner {i2['inner_its']}",
                   file=sys.stderr, flush=True)
     prob.set_precision("mixed")
+    # error of every returned eigenvalue against the stored FP64 oracle result of the same
+    # workload (tests/golden, written by a script that calls only the oracle), when there is one
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", f"L{L}_W16.5_s{seed}_k{k}.json")
+    if os.path.exists(gold):
+        with open(gold) as fh:
+            g = json.load(fh)
+        if g["sigma"] == sigma and g["k"] == k:
+            ref = np.array(g["lams"])
+            out["oracle_error"] = {"reference": os.path.relpath(gold, os.path.dirname(os.path.abspath(__file__))),
+                                   "method": g["method"], "mixed": [float(v) for v in np.abs(ev - ref)]}
+            for name in ("fp64", "mixed_factors"):
+                if name in out:
+                    out["oracle_error"][name + "_max"] = out[name].get("oracle_max_abs_err")
     out["roofline"] = factor_roofline(torch, prob, L ** 3)
     out["stencil"] = stencil_bandwidth(jd, torch, L, W, seed)
     prob.close()
