@@ -62,7 +62,7 @@ enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
  *  kappa      bound on ||L^{-1}|| of inverse-based pivoting, section 7.2 (0 -> 5).
  *             After a level that accepts fewer than 1% of its unknowns while more
  *             than 8192 remain, the bound (and with it drop_tol / kappa) doubles for
- *             the following levels, up to max(1000, kappa).
+ *             the following levels, up to max(20, kappa).
  *  agg_tau    tau of the aggressive dropping rule of section 7.3 (0 -> 0.1).
  *  schur_tol  off-diagonal entries of a scaled Schur complement below this are
  *             dropped (0 -> drop_tol / 2).

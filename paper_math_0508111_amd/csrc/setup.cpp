@@ -728,9 +728,11 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
     double t_match = 0, t_split = 0, t_fact = 0;
     // kappa of the current level: doubled (up to kKappaMax) after a level that accepted
     // fewer than 1% of its unknowns while the rest is still too large for the exact last
-    // level, so that a stalled recursion keeps shrinking
+    // level, so that a stalled recursion keeps shrinking.  A higher cap (1000) also ended
+    // every recursion tried, but its pivots left preconditioners under which JD did not
+    // converge at all (W = 12, L = 60)
     SetupParams lp = prm;
-    constexpr double kKappaMax = 1e3;
+    constexpr double kKappaMax = 20.0;
     while (S.n > prm.coarse_max && int(pend.size()) < prm.max_levels) {
         double ta = now_s();
         MatchResult mr = max_product_matching(S);

@@ -277,5 +277,5 @@ def test_multilevel_stalled_recursion_terminates(jd):
             assert r["gmin"][l] >= drop / k_l * (1 - 1e-12)
         if r["nB"][l] * 100 < rest:
             assert rest > 8192  # below that the recursion stops instead
-            k_l, stalls = min(2 * k_l, 1e3), stalls + 1
+            k_l, stalls = min(2 * k_l, max(20.0, kappa)), stalls + 1
     assert stalls >= 1  # the case does exercise the rule
