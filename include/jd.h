@@ -74,11 +74,12 @@ enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
  *             inverse of the unit lower triangular factor of all levels; entries of Z
  *             below z_drop (scaled domain) are dropped (0 -> min(1e-2, 10 drop_tol);
  *             < 0 -> none).
- *  jmin, jmax search-space sizes after / before a restart (0 -> for n >= 2^19
- *             max(k+20,30) and min(3 jmin, 120), else max(k+5,10) and min(2 jmin, 120));
- *             jmax <= 120.
+ *  jmin, jmax search-space sizes after / before a restart (0 -> for n >= 2^19 or a
+ *             setup that stalled (see kappa): max(k+20,30) and min(3 jmin, 120), else
+ *             max(k+5,10) and min(2 jmin, 120)); jmax <= 120.
  *  max_outer  outer Jacobi-Davidson iterations (0 -> 60 k + 200).
- *  max_inner  SQMR steps per correction equation (0 -> 40).
+ *  max_inner  SQMR steps per correction equation (0 -> 40, or 80 after a setup that
+ *             stalled).
  *  switch_tol the correction operator uses sigma until ||r|| < switch_tol ||A||_inf,
  *             then the Ritz value theta; < 0: always sigma (0 -> 1e-3, and always
  *             sigma for JD_MIXED, whose binary32 inner solves lose accuracy on the

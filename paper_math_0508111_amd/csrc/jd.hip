@@ -257,10 +257,12 @@ struct Setup {
 // ~1 / (n rho) apart and a larger space carries the outer iteration further per
 // correction (at L = 100: 153 instead of 262 outer iterations with binary32 inner
 // solves, 76 instead of 83 in binary64); on small ones the host Rayleigh-Ritz of the
-// larger space costs more than it saves.
-void default_search_space(int k, int64_t n, int &jmin, int &jmax)
+// larger space costs more than it saves, unless the problem is hard: a multilevel
+// setup that stalled (W = 12 near the band centre) leaves a weaker preconditioner,
+// and there the larger space (with longer inner solves) is what converges at all.
+void default_search_space(int k, int64_t n, int &jmin, int &jmax, bool hard = false)
 {
-    if (n >= (int64_t(1) << 19)) {
+    if (hard || n >= (int64_t(1) << 19)) {
         jmin = std::max(k + 20, 30);
         jmax = std::min(3 * jmin, 120);
     } else {
@@ -282,7 +284,6 @@ void fill_defaults(jd_options &o, int n)
     // fixed 1e-2 left the preconditioner too coarse (L = 150: 626 instead of 158 outer
     // iterations)
     if (o.z_drop == 0) o.z_drop = o.drop_tol < 0 ? -1.0 : std::min(1e-2, 10.0 * o.drop_tol);
-    if (o.max_inner == 0) o.max_inner = 40;
 }
 
 void check_problem_args(int L, double W, double sigma, const jd_options *opt)
@@ -643,9 +644,11 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
     const int n = S.n;
     hipStream_t s = S.stream;
     jd_options o = S.opt;
+    const bool hard = S.ml.stalls > 0;
     int jmin, jmax;
-    default_search_space(k, n, jmin, jmax);
+    default_search_space(k, n, jmin, jmax, hard);
     if (o.jmin > 0) jmin = o.jmin;
+    const int max_inner = o.max_inner > 0 ? o.max_inner : (hard ? 80 : 40);
     if (o.jmax > 0) jmax = std::max(o.jmax, jmin + 1);
     // the correction operator's shift moves from sigma to theta once ||r|| < switch_tol
     // ||A||; binary32 inner solves keep sigma (near convergence A - theta I is singular
@@ -842,7 +845,7 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
         jdmi::launch_sub_qc<T>(n, p, Qt, n, red, sv.B.b, s);
         ++solves_this_pair;
         const double rtol = std::max(std::pow(2.0, -double(solves_this_pair)), 1e-10);
-        inner_total += sv.sqmr(shift, Qt, Y, p, dM, rtol, o.max_inner);
+        inner_total += sv.sqmr(shift, Qt, Y, p, dM, rtol, max_inner);
         jdmi::launch_convert<T, double>(n, sv.B.x, t64, 1.0, s);
     }
     HIPCHK(hipStreamSynchronize(s));
@@ -999,7 +1002,7 @@ int jd_problem_set_solve_options(jd_problem *p, const jd_options *opt)
         o.jmin = opt->jmin;
         o.jmax = opt->jmax;
         o.max_outer = opt->max_outer;
-        o.max_inner = opt->max_inner ? opt->max_inner : 40;
+        o.max_inner = opt->max_inner;
         o.switch_tol = opt->switch_tol;
         o.flags = (o.flags & ~JD_FLAG_GRAPHS) | (opt->flags & JD_FLAG_GRAPHS);
         return JD_OK;
@@ -1355,8 +1358,8 @@ struct ServerReq {
 size_t footprint_estimate(const jd_request &r)
 {
     const double n = double(r.L) * r.L * r.L;
-    int jmin, jmax;
-    default_search_space(r.k, int64_t(n), jmin, jmax);
+    int jmin, jmax;  // the larger space of a hard problem: it is not known before the setup
+    default_search_space(r.k, int64_t(n), jmin, jmax, true);
     const double nc = std::min(n, 8192.0);
     // factors in both precisions (inverse factor ~ 100 entries per unknown, twice,
     // with padding), search space V, AV and restart buffer, projection blocks, SQMR

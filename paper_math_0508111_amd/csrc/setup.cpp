@@ -756,7 +756,10 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
         // no acceptable pivot, or the level barely shrinks and the rest fits the
         // exactly inverted last level: stop the recursion here
         if (pl.lv.B.empty() || (int64_t(pl.lv.B.size()) * 100 < S.n && S.n <= 8192)) break;
-        if (int64_t(pl.lv.B.size()) * 100 < S.n && lp.drop_tol >= 0) lp.kappa = std::min(2.0 * lp.kappa, std::max(kKappaMax, prm.kappa));
+        if (int64_t(pl.lv.B.size()) * 100 < S.n && lp.drop_tol >= 0) {
+            lp.kappa = std::min(2.0 * lp.kappa, std::max(kKappaMax, prm.kappa));
+            ++out.stalls;
+        }
         pl.cum.resize(S.n);
         for (int i = 0; i < S.n; ++i) pl.cum[i] = cum_prev[i] * d[i];
         pl.off = off;

@@ -95,6 +95,7 @@ struct Multilevel {
     std::vector<double> pos_scale;  // cumulative symmetric scaling of each position (pivots ~ +-1)
     std::vector<Level> levels;
     int coarse_off = 0, coarse_n = 0;
+    int stalls = 0;               // levels after which kappa was raised (the recursion stalled)
     std::vector<double> coarse_inv;  // coarse_n x coarse_n row-major, scalings folded in
     std::vector<double> coarse_mat;  // the last Schur complement itself (when inverted on the device)
     std::vector<double> coarse_scale;  // its cumulative scaling: inverse = diag(s) S^{-1} diag(s)
