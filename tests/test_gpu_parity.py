@@ -282,3 +282,26 @@ def test_solve_options_setter():
     with pytest.raises(jd.JdError):
         p.set_solve_options(jmax=121)
     p.close()
+
+
+def test_solve_after_a_stalled_setup():
+    # W = 12 near the band centre: the multilevel setup stalls (kappa is raised) and the
+    # solve takes the larger search space and longer inner solves.  Checked by the
+    # properties that hold at any size: residuals recomputed by the oracle's own product,
+    # orthonormal vectors, and the eigenvalues are the k nearest sigma among those the
+    # oracle's exact inertia counts in a window around sigma.
+    L, W, seed, sigma, k = 40, 12.0, 1000009, 0.9233143873275735, 4
+    evals, evecs, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, vectors=True, precision="mixed")
+    assert info["status"] == 0 and info["n_converged"] == k
+    eps = generator.disorder(L, W, seed)
+    anorm = lattice.inf_norm(eps)
+    for c in range(k):
+        x = evecs[:, c]
+        r = np.linalg.norm(lattice.matvec(L, eps, x) - evals[c] * x)
+        assert r <= 1e-10 * anorm * 1.0001
+    assert np.abs(evecs.T @ evecs - np.eye(k)).max() <= 1e-8
+    # no eigenvalue is missing between sigma and the farthest returned one: the exact
+    # LDL^T inertia counts as many eigenvalues in that window as were returned
+    lo, hi = np.min(evals) - 1e-9, np.max(evals) + 1e-9
+    radius = max(sigma - lo, hi - sigma)
+    assert eig.count_in_window(L, eps, sigma - radius, sigma + radius) == k
