@@ -128,8 +128,8 @@ typedef struct jd_problem jd_problem;
 typedef struct jd_precond jd_precond;
 
 /*
- * jd_solve -- the k eigenpairs of A nearest sigma (abstract; section 4.2;
- * section 8.2: "five eigenvalues closest to lambda = 0").
+ * jd_solve -- the k eigenpairs of A nearest sigma (abstract; section 4.2; the
+ * experiments of section 8.2 ask for the five eigenvalues nearest 0).
  *  L >= 2 with L^3 < 2^31; W >= 0 finite; sigma finite; 1 <= k <= min(n, 64);
  *  tol in [1e-14, 1): a pair is accepted when ||A x - lambda x||_2 <= tol ||A||_inf
  *  with ||x||_2 = 1.

@@ -195,8 +195,8 @@ MatchResult max_product_matching(const Csr &A)
 }
 
 // ---------------------------------------------------------------------------------
-// Cycle split (section 6.2).  Tie rules (the paper's "structural metric" is not
-// spelled out): minimise the summed size of the union of the two rows' patterns
+// Cycle split (section 6.2).  Tie rules (the paper names a structural criterion for
+// choosing the pairs without defining it): minimise the summed size of the union of the two rows' patterns
 // over the pairs, then maximise the product of the pairs' scaled couplings, then
 // take the first candidate; in odd cycles the 1x1 element must have a nonzero
 // diagonal when possible.
