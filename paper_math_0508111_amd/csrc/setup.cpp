@@ -205,67 +205,89 @@ std::vector<std::pair<int, int>> split_cycles(const Csr &A, const std::vector<in
                                               const std::vector<double> &logd)
 {
     const int n = A.n;
-    std::vector<std::pair<int, int>> blocks;
-    std::vector<char> seen(n, 0);
-    std::vector<int> mark(n, -1);
-    int stamp = 0;
-    auto union_size = [&](int a, int b) {
-        ++stamp;
-        int c = 0;
-        for (int64_t p = A.ptr[a]; p < A.ptr[a + 1]; ++p) { mark[A.col[p]] = stamp; ++c; }
-        for (int64_t p = A.ptr[b]; p < A.ptr[b + 1]; ++p)
-            if (mark[A.col[p]] != stamp) { mark[A.col[p]] = stamp; ++c; }
-        return c;
-    };
+    // the cycles (and open chains) of the matching, in order of their first unknown
+    std::vector<int> nodes, cstart{0};
+    std::vector<char> closed;
+    {
+        std::vector<char> seen(n, 0);
+        for (int s = 0; s < n; ++s) {
+            if (seen[s]) continue;
+            int t = s;
+            while (t >= 0 && !seen[t]) { seen[t] = 1; nodes.push_back(t); t = match[t]; }
+            cstart.push_back(int(nodes.size()));
+            closed.push_back(t == s);
+        }
+    }
+    const int ncyc = int(closed.size());
+    // blocks per cycle, known from its length and kind: the output keeps cycle order
+    std::vector<int64_t> boff(ncyc + 1, 0);
+    for (int c = 0; c < ncyc; ++c) {
+        const int m = cstart[c + 1] - cstart[c];
+        boff[c + 1] = boff[c] + (m == 1 ? 1 : (!closed[c] || m % 2 == 0) ? (m + 1) / 2 : 1 + (m - 1) / 2);
+    }
+    std::vector<std::pair<int, int>> blocks(boff[ncyc]);
     auto coupling = [&](int a, int b) {
         return std::fabs(get(A, a, b)) * std::exp(logd[a] + logd[b]);
     };
-    std::vector<int> cyc;
-    for (int s = 0; s < n; ++s) {
-        if (seen[s]) continue;
-        cyc.clear();
-        int t = s;
-        while (t >= 0 && !seen[t]) { seen[t] = 1; cyc.push_back(t); t = match[t]; }
-        const int m = int(cyc.size());
-        if (m == 1) { blocks.push_back({cyc[0], -1}); continue; }
-        if (t != s) {
-            // an open chain (only when the matching is not perfect): pair consecutively
-            int q = 0;
-            for (; q + 1 < m; q += 2) blocks.push_back({cyc[q], cyc[q + 1]});
-            if (q < m) blocks.push_back({cyc[q], -1});
-            continue;
-        }
-        // pair metrics for consecutive positions q -> q+1 (mod m)
-        std::vector<double> pu(m), pc(m);
-        for (int q = 0; q < m; ++q) {
-            const int a = cyc[q], b = cyc[(q + 1) % m];
-            pu[q] = union_size(a, b);
-            pc[q] = std::log(std::max(coupling(a, b), 1e-300));
-        }
-        if (m % 2 == 0) {
-            double u0 = 0, u1 = 0, c0 = 0, c1 = 0;
-            for (int q = 0; q < m; q += 2) { u0 += pu[q]; c0 += pc[q]; }
-            for (int q = 1; q < m; q += 2) { u1 += pu[q]; c1 += pc[q]; }
-            const int st = (u1 < u0 || (u1 == u0 && c1 > c0)) ? 1 : 0;
-            for (int q = st; q < m + st; q += 2) blocks.push_back({cyc[q % m], cyc[(q + 1) % m]});
-        } else {
-            int best = -1;
-            double bu = kInf, bc = -kInf;
-            bool bnz = false;
-            const int lim = std::min(m, 257);  // very long cycles: first choices only
-            for (int sgl = 0; sgl < lim; ++sgl) {
-                const bool nz = get(A, cyc[sgl], cyc[sgl]) != 0.0;
-                double us = 0, cs = 0;
-                for (int q = sgl + 1; q < sgl + m; q += 2) { us += pu[q % m]; cs += pc[q % m]; }
-                bool better;
-                if (best < 0) better = true;
-                else if (nz != bnz) better = nz;
-                else if (us != bu) better = us < bu;
-                else better = cs > bc;
-                if (better) { best = sgl; bu = us; bc = cs; bnz = nz; }
+#pragma omp parallel
+    {
+        std::vector<int> mark(n, -1);
+        int stamp = 0;
+        auto union_size = [&](int a, int b) {
+            ++stamp;
+            int c = 0;
+            for (int64_t p = A.ptr[a]; p < A.ptr[a + 1]; ++p) { mark[A.col[p]] = stamp; ++c; }
+            for (int64_t p = A.ptr[b]; p < A.ptr[b + 1]; ++p)
+                if (mark[A.col[p]] != stamp) { mark[A.col[p]] = stamp; ++c; }
+            return c;
+        };
+        std::vector<double> pu, pc;
+#pragma omp for schedule(dynamic, 256)
+        for (int ci = 0; ci < ncyc; ++ci) {
+            const int *cyc = nodes.data() + cstart[ci];
+            const int m = cstart[ci + 1] - cstart[ci];
+            std::pair<int, int> *out = blocks.data() + boff[ci];
+            if (m == 1) { out[0] = {cyc[0], -1}; continue; }
+            if (!closed[ci]) {
+                // an open chain (only when the matching is not perfect): pair consecutively
+                int q = 0;
+                for (; q + 1 < m; q += 2) *out++ = {cyc[q], cyc[q + 1]};
+                if (q < m) *out++ = {cyc[q], -1};
+                continue;
             }
-            blocks.push_back({cyc[best], -1});
-            for (int q = best + 1; q < best + m; q += 2) blocks.push_back({cyc[q % m], cyc[(q + 1) % m]});
+            // pair metrics for consecutive positions q -> q+1 (mod m)
+            pu.assign(m, 0.0);
+            pc.assign(m, 0.0);
+            for (int q = 0; q < m; ++q) {
+                const int a = cyc[q], b = cyc[(q + 1) % m];
+                pu[q] = union_size(a, b);
+                pc[q] = std::log(std::max(coupling(a, b), 1e-300));
+            }
+            if (m % 2 == 0) {
+                double u0 = 0, u1 = 0, c0 = 0, c1 = 0;
+                for (int q = 0; q < m; q += 2) { u0 += pu[q]; c0 += pc[q]; }
+                for (int q = 1; q < m; q += 2) { u1 += pu[q]; c1 += pc[q]; }
+                const int st = (u1 < u0 || (u1 == u0 && c1 > c0)) ? 1 : 0;
+                for (int q = st; q < m + st; q += 2) *out++ = {cyc[q % m], cyc[(q + 1) % m]};
+            } else {
+                int best = -1;
+                double bu = kInf, bc = -kInf;
+                bool bnz = false;
+                const int lim = std::min(m, 257);  // very long cycles: first choices only
+                for (int sgl = 0; sgl < lim; ++sgl) {
+                    const bool nz = get(A, cyc[sgl], cyc[sgl]) != 0.0;
+                    double us = 0, cs = 0;
+                    for (int q = sgl + 1; q < sgl + m; q += 2) { us += pu[q % m]; cs += pc[q % m]; }
+                    bool better;
+                    if (best < 0) better = true;
+                    else if (nz != bnz) better = nz;
+                    else if (us != bu) better = us < bu;
+                    else better = cs > bc;
+                    if (better) { best = sgl; bu = us; bc = cs; bnz = nz; }
+                }
+                *out++ = {cyc[best], -1};
+                for (int q = best + 1; q < best + m; q += 2) *out++ = {cyc[q % m], cyc[(q + 1) % m]};
+            }
         }
     }
     return blocks;
