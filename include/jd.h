@@ -50,12 +50,13 @@ enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
 
 /*
  * Options; a zero-initialised struct selects every default.
- *  precision  JD_FP64: every step in binary64.  JD_MIXED: stencil SpMV,
- *             preconditioner factors and the inner SQMR iteration in binary32
- *             (binary32 accumulation); Gram-Schmidt, Rayleigh-Ritz, residual
- *             norms and acceptance in binary64.  JD_MIXED_FACTORS: only the
- *             preconditioner factors (and their application) in binary32; stencil
- *             product and SQMR vectors in binary64.
+ *  precision  JD_FP64: every step in binary64.  JD_MIXED: stencil SpMV in
+ *             binary32; preconditioner factors and the inner SQMR vectors stored in
+ *             binary32, with dot products and factor products accumulated in
+ *             binary64 and rounded once (the level-by-level apply of JD_FLAG_LEVELS
+ *             accumulates in binary32); Gram-Schmidt, Rayleigh-Ritz, residual norms
+ *             and acceptance in binary64.  JD_MIXED_FACTORS: only the preconditioner
+ *             factors stored in binary32; stencil product and SQMR vectors in binary64.
  *  drop_tol   epsilon of section 7.2: an entry of a factor column is dropped when
  *             its modulus is below drop_tol / kappa (0 -> 1/sqrt(n), the paper's
  *             choice in section 8.2; < 0 -> nothing dropped, exact factorisation).
