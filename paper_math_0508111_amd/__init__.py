@@ -93,6 +93,7 @@ def lib():
         "jd_problem_solve": (I, [P, I, D, P, P, P, P, IP]),
         "jd_problem_info": (I, [P, IP]),
         "jd_problem_set_precision": (I, [P, I]),
+        "jd_problem_set_solve_options": (I, [P, OP]),
         "jd_problem_free": (None, [P]),
         "jd_gen_diag": (I, [I, D, U64, P, P, P]),
         "jd_stencil_spmv": (I, [I, I, P, D, P, P, P]),
@@ -146,8 +147,26 @@ def _stream_ptr(stream):
     return int(stream.cuda_stream)
 
 
-def _ptr(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+# element type of the device vectors of the step entry points, per precision code
+_VEC_DTYPE = {JD_FP64: "torch.float64", JD_MIXED: "torch.float32"}
+
+
+def _dev(t, dtype, numel, name):
+    """Device pointer of tensor t after checking what the kernels will assume of it: a
+    contiguous GPU tensor of `dtype` ("torch.float64"/"torch.float32"; None: the ABI
+    rejects the precision itself) holding at least `numel` elements.  A wrong element
+    type or a short tensor would otherwise send the kernels past the allocation."""
+    if t is None:
+        return None
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name}: a GPU tensor is required")
+    if dtype is not None and str(t.dtype) != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: {t.numel()} elements, at least {numel} needed")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _host(a):
@@ -187,10 +206,12 @@ class Problem:
         _check(lib().jd_problem_set_solve_options(self._h, ctypes.byref(o)))
 
     def precond(self):
-        """A view of the problem's preconditioner (keep the problem alive while using it)."""
+        """A view of the problem's preconditioner (it holds a reference to the problem)."""
         h = ctypes.c_void_p()
         _check(lib().jd_problem_precond(self._h, ctypes.byref(h)))
-        return Precond(self.L, 0.0, 0, 0.0, _handle=h)
+        v = Precond(self.L, 0.0, 0, 0.0, _handle=h)
+        v._owner = self  # the view reads the problem's factors: keep the problem alive
+        return v
 
     def info(self):
         i = Info()
@@ -202,7 +223,8 @@ class Problem:
         resid = np.full(k, np.nan)
         evecs = np.empty((k, self.n)) if vectors else None
         info = Info()
-        rc = lib().jd_problem_solve(self._h, k, float(tol), _host(evals), _host(evecs), _ptr(device_out),
+        d_out = _dev(device_out, "torch.float64", self.n * k, "device_out")
+        rc = lib().jd_problem_solve(self._h, k, float(tol), _host(evals), _host(evecs), d_out,
                                     _host(resid), ctypes.byref(info))
         _check(rc, allow_partial=True)
         return evals, (evecs.T if vectors else None), resid, dict(info.as_dict(), status=rc)
@@ -210,10 +232,14 @@ class Problem:
     def linear_solve(self, shift, b, x, Q=None, rtol=1e-8, maxit=200):
         """Q: (n, p) device tensor of orthonormal columns (laid out column-major for the ABI)."""
         its = ctypes.c_int(0)
+        if Q is not None and (len(Q.shape) != 2 or int(Q.shape[0]) != self.n):
+            raise ValueError(f"Q: shape {tuple(Q.shape)}, expected ({self.n}, p)")
         p = 0 if Q is None else int(Q.shape[1])
         Qc = None if Q is None else Q.t().contiguous()
-        qp = None if Qc is None else ctypes.c_void_p(Qc.data_ptr())
-        _check(lib().jd_problem_linear_solve(self._h, float(shift), qp, p, _ptr(b), _ptr(x), float(rtol),
+        qp = _dev(Qc, "torch.float64", self.n * p, "Q")
+        bp = _dev(b, "torch.float64", self.n, "b")
+        xp = _dev(x, "torch.float64", self.n, "x")
+        _check(lib().jd_problem_linear_solve(self._h, float(shift), qp, p, bp, xp, float(rtol),
                                              int(maxit), ctypes.byref(its)))
         return its.value
 
@@ -248,20 +274,28 @@ class Precond:
         return nnz.value
 
     def factor_product(self, x, y, transpose=False, precision="mixed", stream=None):
-        _check(lib().jd_precond_factor_product(self._h, _PREC[precision], int(transpose), _ptr(x), _ptr(y),
-                                               _stream_ptr(stream)))
+        pr = _PREC[precision]
+        dt = _VEC_DTYPE.get(pr)
+        _check(lib().jd_precond_factor_product(self._h, pr, int(transpose), _dev(x, dt, self.n, "x"),
+                                               _dev(y, dt, self.n, "y"), _stream_ptr(stream)))
 
     def apply(self, x, y, precision="fp64", stream=None):
-        _check(lib().jd_precond_apply(self._h, _PREC[precision], _ptr(x), _ptr(y), _stream_ptr(stream)))
+        pr = _PREC[precision]
+        dt = _VEC_DTYPE.get(pr)
+        _check(lib().jd_precond_apply(self._h, pr, _dev(x, dt, self.n, "x"), _dev(y, dt, self.n, "y"),
+                                      _stream_ptr(stream)))
 
     def levels(self, cap=256):
-        sizes = np.zeros(cap, np.int32)
-        nb = np.zeros(cap, np.int32)
-        nnz = np.zeros(cap, np.int64)
-        nl = lib().jd_precond_levels(self._h, cap, _host(sizes), _host(nb), _host(nnz))
-        if nl < 0:
-            _check(nl)
-        return dict(levels=nl, sizes=sizes[:nl + 1].tolist(), nB=nb[:nl].tolist(), nnzG=nnz[:nl].tolist())
+        while True:
+            sizes = np.zeros(cap, np.int32)
+            nb = np.zeros(cap, np.int32)
+            nnz = np.zeros(cap, np.int64)
+            nl = lib().jd_precond_levels(self._h, cap, _host(sizes), _host(nb), _host(nnz))
+            if nl < 0:
+                _check(nl)
+            if nl + 1 <= cap:
+                return dict(levels=nl, sizes=sizes[:nl + 1].tolist(), nB=nb[:nl].tolist(), nnzG=nnz[:nl].tolist())
+            cap = nl + 1
 
     def close(self):
         if self._h:
@@ -276,12 +310,17 @@ class Precond:
 
 
 def gen_diag(L, W, seed, eps64, eps32=None, stream=None):
-    _check(lib().jd_gen_diag(L, float(W), seed, _ptr(eps64), _ptr(eps32), _stream_ptr(stream)))
+    n = int(L) ** 3
+    _check(lib().jd_gen_diag(L, float(W), seed, _dev(eps64, "torch.float64", n, "eps64"),
+                             _dev(eps32, "torch.float32", n, "eps32"), _stream_ptr(stream)))
 
 
 def stencil_spmv(L, eps, shift, x, y, precision="fp64", stream=None):
-    _check(lib().jd_stencil_spmv(L, _PREC[precision], _ptr(eps), float(shift), _ptr(x), _ptr(y),
-                                 _stream_ptr(stream)))
+    n = int(L) ** 3
+    pr = _PREC[precision]
+    dt = _VEC_DTYPE.get(pr)
+    _check(lib().jd_stencil_spmv(L, pr, _dev(eps, dt, n, "eps"), float(shift), _dev(x, dt, n, "x"),
+                                 _dev(y, dt, n, "y"), _stream_ptr(stream)))
 
 
 def version():
