@@ -219,6 +219,9 @@ int jd_precond_factor_product(jd_precond *p, int precision, int transpose, const
  * Q the p orthonormal binary64 columns of d_Q (p may be 0, d_Q then NULL).
  * d_b, d_x: device binary64 n-vectors.  Stops when the quasi-residual bound
  * reaches rtol ||b|| or after maxit steps; *its receives the step count.
+ * pcols <= 64.  Runs on the problem's stream (jd_options.stream at jd_setup) and
+ * synchronises it before returning; the caller orders its writes of d_Q and d_b
+ * before the call.
  */
 int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int pcols,
                             const double *d_b, double *d_x, double rtol, int maxit, int *its);
