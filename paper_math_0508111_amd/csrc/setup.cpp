@@ -19,7 +19,6 @@
 #include <cstring>
 #include <limits>
 #include <numeric>
-#include <queue>
 #include <utility>
 #include <cstdio>
 #include <cstdlib>
@@ -103,30 +102,43 @@ MatchResult max_product_matching(const Csr &A)
     const int n = A.n;
     std::vector<double> lmax(n, -kInf);
     std::vector<double> cost(A.val.size());
+    std::vector<int64_t> first_tight(n);  // first entry of each row with zero cost (or -1)
 #pragma omp parallel for schedule(dynamic, 4096)
     for (int i = 0; i < n; ++i) {
-        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p)
-            if (A.val[p] != 0.0) lmax[i] = std::max(lmax[i], std::log(std::fabs(A.val[p])));
-        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p)
-            cost[p] = (A.val[p] != 0.0) ? lmax[i] - std::log(std::fabs(A.val[p])) : kInf;
+        double m = -kInf;
+        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+            cost[p] = (A.val[p] != 0.0) ? std::log(std::fabs(A.val[p])) : -kInf;
+            m = std::max(m, cost[p]);
+        }
+        lmax[i] = m;
+        first_tight[i] = -1;
+        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+            cost[p] = (A.val[p] != 0.0) ? m - cost[p] : kInf;
+            if (cost[p] == 0.0 && first_tight[i] < 0) first_tight[i] = p;
+        }
     }
     std::vector<double> u(n, 0.0), v(n, 0.0);  // c_ij >= 0 and min_j c_ij = 0: feasible
     std::vector<int> rmatch(n, -1), cmatch(n, -1);
-    // greedy start on tight edges
-    for (int i = 0; i < n; ++i)
-        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+    // greedy start on tight edges: each row, in order, takes its first tight entry whose
+    // column is still free
+    for (int i = 0; i < n; ++i) {
+        if (first_tight[i] < 0) continue;
+        for (int64_t p = first_tight[i]; p < A.ptr[i + 1]; ++p) {
             const int j = A.col[p];
             if (cost[p] == 0.0 && cmatch[j] < 0) { rmatch[i] = j; cmatch[j] = i; break; }
         }
+    }
     std::vector<double> d(n, kInf);
     std::vector<int> pred(n, -1);
     std::vector<char> scanned(n, 0);
     std::vector<int> touched, scanned_list;
     using HE = std::pair<double, int>;
+    std::vector<HE> heap;  // binary min-heap on (distance, column), reused by every search
+    const std::greater<HE> later;
     int unmatched = 0;
     for (int i0 = 0; i0 < n; ++i0) {
         if (rmatch[i0] >= 0) continue;
-        std::priority_queue<HE, std::vector<HE>, std::greater<HE>> heap;
+        heap.clear();
         touched.clear();
         scanned_list.clear();
         auto relax_row = [&](int i, double base) {
@@ -139,7 +151,8 @@ MatchResult max_product_matching(const Csr &A)
                     if (d[j] == kInf) touched.push_back(j);
                     d[j] = nd;
                     pred[j] = i;
-                    heap.push({nd, j});
+                    heap.push_back({nd, j});
+                    std::push_heap(heap.begin(), heap.end(), later);
                 }
             }
         };
@@ -147,8 +160,9 @@ MatchResult max_product_matching(const Csr &A)
         int sink = -1;
         double delta = 0.0;
         while (!heap.empty()) {
-            auto [dj, j] = heap.top();
-            heap.pop();
+            std::pop_heap(heap.begin(), heap.end(), later);
+            const auto [dj, j] = heap.back();
+            heap.pop_back();
             if (scanned[j] || dj > d[j]) continue;
             scanned[j] = 1;
             if (cmatch[j] < 0) { sink = j; delta = dj; break; }
