@@ -381,8 +381,8 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
     int *dperm = S.mem.upload(S.ml.perm, S.stream);
     jdmi::HybHost zsh, ztsh;
     if (!S.ml.z.ptr.empty()) {
-        zsh = jdmi::to_hyb(S.n, S.ml.z.ptr, S.ml.z.col, S.ml.z.val);
-        ztsh = jdmi::to_hyb(S.n, S.ml.z.tptr, S.ml.z.tcol, S.ml.z.tval);
+        zsh = jdmi::to_hyb(S.n, S.ml.z.ptr.data(), S.ml.z.col.data(), S.ml.z.val.data());
+        ztsh = jdmi::to_hyb(S.n, S.ml.z.tptr.data(), S.ml.z.tcol.data(), S.ml.z.tval.data());
     }
     S.pc64.upload(S.ml, dperm, S.mem, S.stream, &zsh, &ztsh);
     S.pc32.upload(S.ml, dperm, S.mem, S.stream, &zsh, &ztsh);

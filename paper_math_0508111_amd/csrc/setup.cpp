@@ -379,15 +379,13 @@ struct Scaled {
 
 }  // namespace
 
-// (S + S^T) / 2 on the union pattern, rows sorted.  The transpose is built in parallel
-// from per-thread column counts over fixed row ranges, so its rows keep increasing row
-// order; the merge counts each output row, then writes it.
-static Csr symmetrize(const Csr &S)
+// Transpose of an n x n CSR matrix, built in parallel from per-thread column counts
+// over fixed row ranges: the rows of the transpose list their entries in increasing
+// row order, exactly as a serial pass over the rows would.
+static void transpose(int n, const BigVec<int64_t> &ptr, const BigVec<int> &col, const BigVec<double> &val,
+                      BigVec<int64_t> &tptr, BigVec<int> &tcol, BigVec<double> &tval)
 {
-    const int n = S.n;
-    Csr T;
-    T.n = n;
-    T.ptr.assign(n + 1, 0);
+    tptr.assign(n + 1, 0);
     int nt = 1;
 #ifdef _OPENMP
     nt = omp_get_max_threads();
@@ -404,32 +402,42 @@ static Csr symmetrize(const Csr &S)
         range(t, a, b);
         auto &c = cnt[t];
         for (int r = a; r < b; ++r)
-            for (int64_t p = S.ptr[r]; p < S.ptr[r + 1]; ++p) ++c[S.col[p]];
+            for (int64_t p = ptr[r]; p < ptr[r + 1]; ++p) ++c[col[p]];
     }
     // offsets: column c of thread t starts after the entries of c from threads < t
     for (int c = 0; c < n; ++c) {
-        int64_t o = T.ptr[c];
+        int64_t o = tptr[c];
         for (int t = 0; t < nt; ++t) {
             const int64_t k = cnt[t][c];
             cnt[t][c] = o;
             o += k;
         }
-        T.ptr[c + 1] = o;
+        tptr[c + 1] = o;
     }
-    T.col.resize(T.ptr[n]);
-    T.val.resize(T.ptr[n]);
+    tcol.resize(tptr[n]);
+    tval.resize(tptr[n]);
 #pragma omp parallel for schedule(static, 1)
     for (int t = 0; t < nt; ++t) {
         int a, b;
         range(t, a, b);
         auto &fp = cnt[t];
         for (int r = a; r < b; ++r)
-            for (int64_t p = S.ptr[r]; p < S.ptr[r + 1]; ++p) {
-                const int c = S.col[p];
-                T.col[fp[c]] = r;
-                T.val[fp[c]++] = S.val[p];
+            for (int64_t p = ptr[r]; p < ptr[r + 1]; ++p) {
+                const int c = col[p];
+                tcol[fp[c]] = r;
+                tval[fp[c]++] = val[p];
             }
     }
+}
+
+// (S + S^T) / 2 on the union pattern, rows sorted; the merge counts each output row,
+// then writes it.
+static Csr symmetrize(const Csr &S)
+{
+    const int n = S.n;
+    Csr T;
+    T.n = n;
+    transpose(n, S.ptr, S.col, S.val, T.ptr, T.col, T.val);
     Csr U;
     U.n = n;
     U.ptr.assign(n + 1, 0);
@@ -1015,27 +1023,18 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L)
     for (int q = 0; q < n; ++q) Z.ptr[q + 1] = Z.ptr[q] + int64_t(rows[pos_of[q]].size());
     Z.col.resize(Z.ptr[n]);
     Z.val.resize(Z.ptr[n]);
-    Z.tptr.assign(n + 1, 0);
+    // rows are independent once their offsets are known (columns within a row are
+    // distinct, so the sort order does not depend on the thread)
+#pragma omp parallel for schedule(dynamic, 256)
     for (int q = 0; q < n; ++q) {
         auto &row = rows[pos_of[q]];
         for (auto &e : row) e.first = newidx[e.first];
         std::sort(row.begin(), row.end());
         int64_t p = Z.ptr[q];
-        for (auto &e : row) { Z.col[p] = e.first; Z.val[p] = e.second; ++p; ++Z.tptr[e.first + 1]; }
+        for (auto &e : row) { Z.col[p] = e.first; Z.val[p] = e.second; ++p; }
         std::vector<std::pair<int, double>>().swap(row);
     }
-    for (int r = 0; r < n; ++r) Z.tptr[r + 1] += Z.tptr[r];
-    Z.tcol.resize(Z.tptr[n]);
-    Z.tval.resize(Z.tptr[n]);
-    {
-        std::vector<int64_t> fp(Z.tptr.begin(), Z.tptr.end() - 1);
-        for (int r = 0; r < n; ++r)
-            for (int64_t p = Z.ptr[r]; p < Z.ptr[r + 1]; ++p) {
-                const int c = Z.col[p];
-                Z.tcol[fp[c]] = r;
-                Z.tval[fp[c]++] = Z.val[p];
-            }
-    }
+    transpose(n, Z.ptr, Z.col, Z.val, Z.tptr, Z.tcol, Z.tval);
     Z.dd.assign(n, 0.0);
     Z.dof.assign(n, 0.0);
     Z.dp.resize(n);
@@ -1053,7 +1052,7 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L)
 }
 
 // CSR -> the hybrid device layout (see HybHost).
-HybHost to_hyb(int n, const std::vector<int64_t> &ptr, const std::vector<int> &col, const std::vector<double> &val)
+HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val)
 {
     constexpr int P = kHybParts, C = kSliceRows, G = kSliceLanes;
     constexpr size_t kWindow = 2048;
@@ -1073,8 +1072,8 @@ HybHost to_hyb(int n, const std::vector<int64_t> &ptr, const std::vector<int> &c
         for (int r : longr) {
             h.task.push_back(int(h.long_row.size()));
             h.long_row.push_back(r);
-            h.long_col.insert(h.long_col.end(), col.begin() + ptr[r], col.begin() + ptr[r + 1]);
-            h.long_val.insert(h.long_val.end(), val.begin() + ptr[r], val.begin() + ptr[r + 1]);
+            h.long_col.insert(h.long_col.end(), col + ptr[r], col + ptr[r + 1]);
+            h.long_val.insert(h.long_val.end(), val + ptr[r], val + ptr[r + 1]);
             h.long_ptr.push_back(int64_t(h.long_col.size()));
         }
         for (size_t w0 = 0; w0 < shortr.size(); w0 += kWindow) {

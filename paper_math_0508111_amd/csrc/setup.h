@@ -4,18 +4,50 @@
 // the device kernels.
 #pragma once
 #include <cstdint>
+#include <memory>
+#include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace jdmi {
 
+// Allocator whose resize(n) leaves new elements uninitialised: the arrays of a
+// matrix built level by level are filled by parallel loops right after they are
+// sized, so zeroing them first would only add a serial pass over fresh pages.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+    template <typename U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() noexcept = default;
+    template <typename U>
+    NoInitAlloc(const NoInitAlloc<U> &) noexcept {}
+    template <typename U>
+    void construct(U *p) noexcept
+    {
+        ::new (static_cast<void *>(p)) U;
+    }
+    template <typename U, typename... Args>
+    void construct(U *p, Args &&...args)
+    {
+        ::new (static_cast<void *>(p)) U(std::forward<Args>(args)...);
+    }
+};
+
+// Large arrays filled in parallel right after they are sized.
+template <typename T>
+using BigVec = std::vector<T, NoInitAlloc<T>>;
+
 // Symmetric sparse matrix, CSR with sorted column indices and an explicit
-// (possibly zero) diagonal entry in every row.
+// (possibly zero) diagonal entry in every row.  resize() of its arrays does not
+// initialise: every writer fills what it sizes.
 struct Csr {
     int n = 0;
-    std::vector<int64_t> ptr;
-    std::vector<int> col;
-    std::vector<double> val;
+    BigVec<int64_t> ptr;
+    BigVec<int> col;
+    BigVec<double> val;
 };
 
 struct MatchResult {
@@ -59,9 +91,9 @@ struct SetupParams {
 constexpr int kMidBlock = 128;
 struct InverseFactor {
     std::vector<int> site_of;         // n: input index -> lattice site
-    std::vector<int64_t> ptr, tptr;   // CSR of Z (rows: middle, columns: input numbering) and of Z^T
-    std::vector<int> col, tcol;
-    std::vector<double> val, tval;
+    BigVec<int64_t> ptr, tptr;        // CSR of Z (rows: middle, columns: input numbering) and of Z^T
+    BigVec<int> col, tcol;
+    BigVec<double> val, tval;
     std::vector<double> dd, dof;      // D^{-1} (middle numbering): z[q] = dd[q] y[q] + dof[q] y[dp[q]] (0 on the last level)
     std::vector<int> dp;
     std::vector<int> coarse_idx;      // coarse_n: middle index of each unknown of the last level
@@ -145,6 +177,6 @@ struct HybHost {
     std::vector<int> rowidx, col;          // rowidx: kSliceRows per slice, -1 for padding rows
     std::vector<double> val;
 };
-HybHost to_hyb(int n, const std::vector<int64_t> &ptr, const std::vector<int> &col, const std::vector<double> &val);
+HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val);
 
 }  // namespace jdmi
