@@ -489,64 +489,77 @@ static std::string factor_level(const Csr &A, const SetupParams &prm, const std:
     // collected in block order
     std::vector<std::array<Cand, 2>> per(blocks.size());
     std::vector<int> nper(blocks.size(), 0);
-#pragma omp parallel for schedule(dynamic, 2048)
-    for (int64_t bi = 0; bi < int64_t(blocks.size()); ++bi) {
-        const int a = blocks[bi].first, b = blocks[bi].second;
-        auto put = [&](const Cand &c) { per[bi][nper[bi]++] = c; };
-        auto push1l = [&](int i) {
-            const double dii = sget(i, i);
-            if (!(std::fabs(dii) > 0.0)) return;
-            put({i, -1, colsum1(i) / std::fabs(dii), int(A.ptr[i + 1] - A.ptr[i]), 1.0 / dii, 0.0, 0.0});
-        };
-        if (b < 0) { push1l(a); continue; }
-        const double saa = sget(a, a), sab = sget(a, b), sbb = sget(b, b);
-        const double det = saa * sbb - sab * sab;
-        const double scale = std::max({std::fabs(saa), std::fabs(sbb), std::fabs(sab)});
-        double d2 = kInf, cs_a = 0, cs_b = 0;
-        double i00 = 0, i01 = 0, i11 = 0;
-        if (std::fabs(det) > 1e-12 * scale * scale) {
-            i00 = sbb / det; i01 = -sab / det; i11 = saa / det;
-            // rows of (s_r,a  s_r,b) S2^{-1} over the union of both columns' rows
-            d2 = 0;
-            std::vector<std::pair<int, double>> ra, rb;
-            for (int64_t p = A.ptr[a]; p < A.ptr[a + 1]; ++p)
-                if (A.col[p] != a && A.col[p] != b) ra.push_back({A.col[p], sv(p, a)});
-            for (int64_t p = A.ptr[b]; p < A.ptr[b + 1]; ++p)
-                if (A.col[p] != a && A.col[p] != b) rb.push_back({A.col[p], sv(p, b)});
-            size_t x = 0, y = 0;
-            while (x < ra.size() || y < rb.size()) {
-                int r;
-                double va = 0, vb = 0;
-                if (y >= rb.size() || (x < ra.size() && ra[x].first < rb[y].first)) { r = ra[x].first; va = ra[x++].second; }
-                else if (x >= ra.size() || rb[y].first < ra[x].first) { r = rb[y].first; vb = rb[y++].second; }
-                else { r = ra[x].first; va = ra[x++].second; vb = rb[y++].second; }
-                (void)r;
-                const double za = va * i00 + vb * i01, zb = va * i01 + vb * i11;
-                d2 += std::max(std::fabs(za), std::fabs(zb));  // infinity norm of the row
-                cs_a += std::fabs(za);
-                cs_b += std::fabs(zb);
+#pragma omp parallel
+    {
+        std::vector<std::pair<int, double>> ra, rb;  // per-thread buffers, reused by every block
+#pragma omp for schedule(dynamic, 2048)
+        for (int64_t bi = 0; bi < int64_t(blocks.size()); ++bi) {
+            const int a = blocks[bi].first, b = blocks[bi].second;
+            auto put = [&](const Cand &c) { per[bi][nper[bi]++] = c; };
+            auto push1l = [&](int i) {
+                const double dii = sget(i, i);
+                if (!(std::fabs(dii) > 0.0)) return;
+                put({i, -1, colsum1(i) / std::fabs(dii), int(A.ptr[i + 1] - A.ptr[i]), 1.0 / dii, 0.0, 0.0});
+            };
+            if (b < 0) { push1l(a); continue; }
+            const double saa = sget(a, a), sab = sget(a, b), sbb = sget(b, b);
+            const double det = saa * sbb - sab * sab;
+            const double scale = std::max({std::fabs(saa), std::fabs(sbb), std::fabs(sab)});
+            double d2 = kInf, cs_a = 0, cs_b = 0;
+            double i00 = 0, i01 = 0, i11 = 0;
+            if (std::fabs(det) > 1e-12 * scale * scale) {
+                i00 = sbb / det; i01 = -sab / det; i11 = saa / det;
+                // rows of (s_r,a  s_r,b) S2^{-1} over the union of both columns' rows
+                d2 = 0;
+                ra.clear();
+                rb.clear();
+                for (int64_t p = A.ptr[a]; p < A.ptr[a + 1]; ++p)
+                    if (A.col[p] != a && A.col[p] != b) ra.push_back({A.col[p], sv(p, a)});
+                for (int64_t p = A.ptr[b]; p < A.ptr[b + 1]; ++p)
+                    if (A.col[p] != a && A.col[p] != b) rb.push_back({A.col[p], sv(p, b)});
+                size_t x = 0, y = 0;
+                while (x < ra.size() || y < rb.size()) {
+                    int r;
+                    double va = 0, vb = 0;
+                    if (y >= rb.size() || (x < ra.size() && ra[x].first < rb[y].first)) { r = ra[x].first; va = ra[x++].second; }
+                    else if (x >= ra.size() || rb[y].first < ra[x].first) { r = rb[y].first; vb = rb[y++].second; }
+                    else { r = ra[x].first; va = ra[x++].second; vb = rb[y++].second; }
+                    (void)r;
+                    const double za = va * i00 + vb * i01, zb = va * i01 + vb * i11;
+                    d2 += std::max(std::fabs(za), std::fabs(zb));  // infinity norm of the row
+                    cs_a += std::fabs(za);
+                    cs_b += std::fabs(zb);
+                }
             }
-        }
-        const double d1a = (saa != 0.0) ? colsum1(a) / std::fabs(saa) : kInf;
-        const double d1b = (sbb != 0.0) ? colsum1(b) / std::fabs(sbb) : kInf;
-        if (d2 < std::min(d1a, d1b)) {
-            int deg = int(A.ptr[a + 1] - A.ptr[a] + A.ptr[b + 1] - A.ptr[b]);
-            put({a, b, std::max(cs_a, cs_b), deg, i00, i01, i11});
-        } else {
-            push1l(a);
-            push1l(b);
+            const double d1a = (saa != 0.0) ? colsum1(a) / std::fabs(saa) : kInf;
+            const double d1b = (sbb != 0.0) ? colsum1(b) / std::fabs(sbb) : kInf;
+            if (d2 < std::min(d1a, d1b)) {
+                int deg = int(A.ptr[a + 1] - A.ptr[a] + A.ptr[b + 1] - A.ptr[b]);
+                put({a, b, std::max(cs_a, cs_b), deg, i00, i01, i11});
+            } else {
+                push1l(a);
+                push1l(b);
+            }
         }
     }
     for (size_t bi = 0; bi < blocks.size(); ++bi)
         for (int t = 0; t < nper[bi]; ++t) cands.push_back(per[bi][t]);
-    // greedy independent set of the compressed graph: fewest couplings first
+    // greedy independent set of the compressed graph: fewest couplings first, ties by
+    // the smallest member.  Every unknown belongs to exactly one candidate, so the key
+    // (couplings, smallest member) is distinct per candidate and fixes the order.
     std::vector<int> order(cands.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        if (cands[x].deg != cands[y].deg) return cands[x].deg < cands[y].deg;
-        return std::min(cands[x].a, cands[x].b < 0 ? cands[x].a : cands[x].b) <
-               std::min(cands[y].a, cands[y].b < 0 ? cands[y].a : cands[y].b);
-    });
+    {
+        std::vector<int> cand_of_first(n, -1);
+        std::vector<uint64_t> keyed(cands.size());
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+            const Cand &c = cands[ci];
+            const int first = c.b < 0 ? c.a : std::min(c.a, c.b);
+            cand_of_first[first] = int(ci);
+            keyed[ci] = (uint64_t(uint32_t(c.deg)) << 32) | uint32_t(first);
+        }
+        std::sort(keyed.begin(), keyed.end());
+        for (size_t k = 0; k < keyed.size(); ++k) order[k] = cand_of_first[uint32_t(keyed[k])];
+    }
     enum : char { FREE = 0, INB = 1, INC = 2 };
     std::vector<char> state(n, FREE);
     std::vector<int> cand_of(n, -1);
