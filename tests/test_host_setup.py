@@ -279,3 +279,26 @@ def test_multilevel_stalled_recursion_terminates(jd):
             assert rest > 8192  # below that the recursion stops instead
             k_l, stalls = min(2 * k_l, max(20.0, kappa)), stalls + 1
     assert stalls >= 1  # the case does exercise the rule
+
+
+def test_multilevel_identical_for_any_thread_count(jd):
+    # the parallel steps of the setup (pivot tests, Schur rows, transposes, cycle split,
+    # tight-entry scan) write to fixed places, so the factorisation must not depend on
+    # the number of host threads
+    from oracle import generator, lattice
+    gomp = ctypes.CDLL("libgomp.so.1")
+    before = gomp.omp_get_max_threads()
+    L, W = 20, 16.5
+    A = lattice.hamiltonian(L, generator.disorder(L, W, 3)).tocsr()
+    runs = []
+    try:
+        for threads in (1, 3, 8):
+            gomp.omp_set_num_threads(threads)
+            runs.append(_host_factor(jd, A, drop_tol=1.0 / math.sqrt(L ** 3), coarse_max=200))
+    finally:
+        gomp.omp_set_num_threads(before)
+    assert runs[0]["levels"] >= 3
+    for r in runs[1:]:
+        assert r["levels"] == runs[0]["levels"] and r["coarse"] == runs[0]["coarse"]
+        for key in ("perm", "scale", "off", "nB", "n2x2", "gnnz", "gmin", "gcolsum"):
+            assert np.array_equal(r[key], runs[0][key]), key
