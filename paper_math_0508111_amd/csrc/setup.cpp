@@ -1064,23 +1064,30 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L)
     Z.seconds = now_s() - t0;
 }
 
-// CSR -> the hybrid device layout (see HybHost).
+// CSR -> the hybrid device layout (see HybHost).  The parts are built on their own
+// (in parallel) and then concatenated, with their long-row indices, slice codes and
+// offsets shifted to the global numbering.
 HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val)
 {
     constexpr int P = kHybParts, C = kSliceRows, G = kSliceLanes;
     constexpr size_t kWindow = 2048;
-    HybHost h;
     auto len = [&](int r) { return ptr[r + 1] - ptr[r]; };
     const int64_t nnz = ptr[n];
-    int r0 = 0;
+    // rows [rb[part], rb[part + 1]): the part's share of the nonzeros
+    int rb[P + 1];
+    rb[0] = 0;
     for (int part = 0; part < P; ++part) {
-        // rows [r0, r1): the part's share of the nonzeros
-        int r1 = r0;
+        int r1 = rb[part];
         const int64_t target = nnz * (part + 1) / P;
         while (r1 < n && (part == P - 1 || ptr[r1] < target)) ++r1;
-        h.tbeg[part] = int(h.task.size());
+        rb[part + 1] = r1;
+    }
+    HybHost parts[P];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int part = 0; part < P; ++part) {
+        HybHost &h = parts[part];
         std::vector<int> longr, shortr;
-        for (int r = r0; r < r1; ++r) (len(r) > kLongRow ? longr : shortr).push_back(r);
+        for (int r = rb[part]; r < rb[part + 1]; ++r) (len(r) > kLongRow ? longr : shortr).push_back(r);
         std::stable_sort(longr.begin(), longr.end(), [&](int a, int b) { return len(a) > len(b); });
         for (int r : longr) {
             h.task.push_back(int(h.long_row.size()));
@@ -1113,10 +1120,53 @@ HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val)
                     h.val[at] = val[ptr[r] + j];
                 }
             }
-            h.task.push_back(-int(h.slice_ptr.size() - 1));  // -1 - slice index
+            h.task.push_back(-int(h.slice_ptr.size() - 1));  // -1 - slice index within the part
         }
-        h.tend[part] = int(h.task.size());
-        r0 = r1;
+    }
+    // offsets of every part in the concatenated arrays
+    struct Off { size_t task, long_row, long_ent, slice, slice_ent; };
+    Off off[P + 1];
+    off[0] = {0, 0, 0, 0, 0};
+    for (int part = 0; part < P; ++part) {
+        const HybHost &q = parts[part];
+        off[part + 1] = {off[part].task + q.task.size(), off[part].long_row + q.long_row.size(),
+                         off[part].long_ent + q.long_col.size(), off[part].slice + (q.slice_ptr.size() - 1),
+                         off[part].slice_ent + q.col.size()};
+    }
+    HybHost h;
+    const Off &tot = off[P];
+    h.task.resize(tot.task);
+    h.long_row.resize(tot.long_row);
+    h.long_ptr.resize(tot.long_row + 1);
+    h.long_col.resize(tot.long_ent);
+    h.long_val.resize(tot.long_ent);
+    h.slice_ptr.resize(tot.slice + 1);
+    h.rowidx.resize(tot.slice * C);
+    h.col.resize(tot.slice_ent);
+    h.val.resize(tot.slice_ent);
+    h.long_ptr[0] = 0;
+    h.slice_ptr[0] = 0;
+    for (int part = 0; part < P; ++part) {
+        h.tbeg[part] = int(off[part].task);
+        h.tend[part] = int(off[part + 1].task);
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int part = 0; part < P; ++part) {
+        const HybHost &q = parts[part];
+        const Off &o = off[part];
+        for (size_t i = 0; i < q.task.size(); ++i) {
+            const int c = q.task[i];
+            h.task[o.task + i] = c >= 0 ? c + int(o.long_row) : c - int(o.slice);
+        }
+        std::copy(q.long_row.begin(), q.long_row.end(), h.long_row.begin() + o.long_row);
+        for (size_t i = 1; i < q.long_ptr.size(); ++i) h.long_ptr[o.long_row + i] = int64_t(o.long_ent) + q.long_ptr[i];
+        std::copy(q.long_col.begin(), q.long_col.end(), h.long_col.begin() + o.long_ent);
+        std::copy(q.long_val.begin(), q.long_val.end(), h.long_val.begin() + o.long_ent);
+        for (size_t i = 1; i < q.slice_ptr.size(); ++i)
+            h.slice_ptr[o.slice + i] = int64_t(o.slice_ent) + q.slice_ptr[i];
+        std::copy(q.rowidx.begin(), q.rowidx.end(), h.rowidx.begin() + o.slice * C);
+        std::copy(q.col.begin(), q.col.end(), h.col.begin() + o.slice_ent);
+        std::copy(q.val.begin(), q.val.end(), h.val.begin() + o.slice_ent);
     }
     return h;
 }
