@@ -77,7 +77,9 @@ enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
  *             < 0 -> none).
  *  jmin, jmax search-space sizes after / before a restart (0 -> for n >= 2^19 or a
  *             setup that stalled (see kappa): max(k+20,30) and min(3 jmin, 120), else
- *             max(k+5,10) and min(2 jmin, 120)); jmax <= 120.
+ *             max(k+5,10) and min(2 jmin, 120)); jmin < 120, jmax <= 120, and
+ *             jmin < jmax when both are given (JD_EINVAL otherwise); a jmin given
+ *             alone raises the default jmax to at least jmin + 1.
  *  max_outer  outer Jacobi-Davidson iterations (0 -> 60 k + 200).
  *  max_inner  SQMR steps per correction equation (0 -> 40, or 80 after a setup that
  *             stalled).

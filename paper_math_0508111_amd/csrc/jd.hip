@@ -286,6 +286,14 @@ void fill_defaults(jd_options &o, int n)
     if (o.z_drop == 0) o.z_drop = o.drop_tol < 0 ? -1.0 : std::min(1e-2, 10.0 * o.drop_tol);
 }
 
+// Search-space sizes of the options (0 = default): the space holds at most 120 columns
+// and a restart keeps jmin < jmax of them.
+void check_search_space(int jmin, int jmax)
+{
+    if (jmin < 0 || jmax < 0 || jmax > 120 || jmin >= 120) throw JdError(JD_EINVAL, "jmin/jmax out of range");
+    if (jmax > 0 && jmin >= jmax) throw JdError(JD_EINVAL, "jmin must be smaller than jmax");
+}
+
 void check_problem_args(int L, double W, double sigma, const jd_options *opt)
 {
     if (L < 2 || (long long)L * L * L >= (1LL << 31)) throw JdError(JD_EINVAL, "L must satisfy L >= 2 and L^3 < 2^31");
@@ -295,7 +303,7 @@ void check_problem_args(int L, double W, double sigma, const jd_options *opt)
         if (opt->precision != JD_FP64 && opt->precision != JD_MIXED && opt->precision != JD_MIXED_FACTORS)
             throw JdError(JD_EINVAL, "unknown precision");
         if (opt->coarse_max < 0 || opt->coarse_max > 8192) throw JdError(JD_EINVAL, "coarse_max must be in [0, 8192]");
-        if (opt->jmin < 0 || opt->jmax < 0 || opt->jmax > 120) throw JdError(JD_EINVAL, "jmin/jmax out of range");
+        check_search_space(opt->jmin, opt->jmax);
         if (opt->max_inner < 0 || opt->max_outer < 0 || opt->max_levels < 0) throw JdError(JD_EINVAL, "negative iteration cap");
         if (opt->flags & ~(JD_FLAG_GRAPHS | JD_FLAG_LEVELS)) throw JdError(JD_EINVAL, "unknown flag bits");
         if (!std::isfinite(opt->z_drop)) throw JdError(JD_EINVAL, "non-finite option");
@@ -648,8 +656,10 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
     int jmin, jmax;
     default_search_space(k, n, jmin, jmax, hard);
     if (o.jmin > 0) jmin = o.jmin;
+    if (o.jmax > 0) jmax = o.jmax;
+    // a restart keeps jmin of the jmax columns: a jmin given alone raises the default jmax
+    jmax = std::max(jmax, jmin + 1);
     const int max_inner = o.max_inner > 0 ? o.max_inner : (hard ? 80 : 40);
-    if (o.jmax > 0) jmax = std::max(o.jmax, jmin + 1);
     // the correction operator's shift moves from sigma to theta once ||r|| < switch_tol
     // ||A||; binary32 inner solves keep sigma (near convergence A - theta I is singular
     // to binary32 accuracy)
@@ -994,7 +1004,7 @@ int jd_problem_set_solve_options(jd_problem *p, const jd_options *opt)
 {
     return guarded([&] {
         if (!p || !opt) throw JdError(JD_EINVAL, "NULL argument");
-        if (opt->jmin < 0 || opt->jmax < 0 || opt->jmax > 120) throw JdError(JD_EINVAL, "jmin/jmax out of range");
+        check_search_space(opt->jmin, opt->jmax);
         if (opt->max_inner < 0 || opt->max_outer < 0) throw JdError(JD_EINVAL, "negative iteration cap");
         if (!std::isfinite(opt->switch_tol)) throw JdError(JD_EINVAL, "bad switch_tol");
         if (opt->flags & ~(JD_FLAG_GRAPHS | JD_FLAG_LEVELS)) throw JdError(JD_EINVAL, "unknown flag bits");

@@ -5,8 +5,10 @@
 Each JSON file holds the k eigenvalues of the Anderson matrix nearest sigma
 (section 3, eq. (eigenequation), periodic lattice, hopping -1, SplitMix64 box
 disorder), as computed by the FP64 oracle: shift-and-invert Lanczos on an exact
-multifrontal LDL^T (and, where n <= 1000, also dense Jacobi).  Large cases take
-minutes and several GB of host memory.
+multifrontal LDL^T (and, where n <= 1000, also dense Jacobi), with an inertia
+certificate: the exact LDL^T counts k eigenvalues in the window that the stored
+values and the next one delimit (``--certify NAME ...`` adds it to stored results).
+Large cases take minutes and several GB of host memory.
 """
 import json
 import os
@@ -34,6 +36,40 @@ CASES = {
 }
 
 
+def certify(out, eps):
+    """Inertia certificate of a stored result (Sylvester's law on the exact LDL^T).
+
+    rho is halfway between the k-th and the (k+1)-th distance to sigma; the window
+    [sigma - rho, sigma + rho) must hold exactly k eigenvalues.  Each returned value
+    theta_i with residual r_i (unit vector) has an eigenvalue within r_i; with the
+    window count and disjoint intervals that eigenvalue is the i-th nearest, and
+    Kato-Temple bounds its distance to theta_i by r_i^2 / delta_i, delta_i a lower
+    bound of the distance from theta_i to every other eigenvalue."""
+    sigma, k = out["sigma"], out["k"]
+    lams, res = np.array(out["lams"]), np.array(out["res"])
+    d_k, d_next = abs(lams[-1] - sigma), abs(out["next"] - sigma)
+    rho = 0.5 * (d_k + d_next)
+    t0 = time.time()
+    count = eig.count_in_window(out["L"], eps, sigma - rho, sigma + rho)
+    assert count == k, (count, k)
+    iv = [(lams[i] - res[i], lams[i] + res[i]) for i in range(k)]
+    kt = []
+    for i in range(k):
+        others = [abs(lams[i] - lams[j]) - res[j] for j in range(k) if j != i]
+        # eigenvalues outside the window are at least rho - |theta_i - sigma| away
+        delta = min(others + [rho - abs(lams[i] - sigma)])
+        assert res[i] < delta
+        kt.append(float(res[i] ** 2 / delta))
+    for i in range(k):
+        for j in range(i + 1, k):
+            assert iv[i][1] < iv[j][0] or iv[j][1] < iv[i][0], (i, j)
+    out["certificate"] = dict(rho=rho, window=[sigma - rho, sigma + rho], inertia_count=count,
+                              kato_temple=kt, seconds=round(time.time() - t0, 1),
+                              cite="section 5.1 (inertia of the LDL^T factors); section 4.1 "
+                                   "(shift-and-invert with exact factorisations)")
+    return out
+
+
 def run(name, c):
     t0 = time.time()
     eps = generator.disorder(c["L"], c["W"], c["seed"])
@@ -51,12 +87,30 @@ def run(name, c):
         idx = eig.select_nearest(w, c["sigma"], c["k"] + 1)
         out["lams_dense_jacobi"] = [float(v) for v in w[idx][:c["k"]]]
         assert np.allclose(out["lams_dense_jacobi"], out["lams"], atol=1e-12, rtol=0)
+    certify(out, eps)
     with open(os.path.join(HERE, name + ".json"), "w") as fh:
         json.dump(out, fh, indent=1)
     print(name, "done in", out["seconds"], "s", flush=True)
 
 
+def certify_stored(name):
+    """Add the inertia certificate to a stored result without recomputing its pairs."""
+    path = os.path.join(HERE, name + ".json")
+    with open(path) as fh:
+        out = json.load(fh)
+    eps = generator.disorder(out["L"], out["W"], out["seed"])
+    certify(out, eps)
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(name, "certified in", out["certificate"]["seconds"], "s", flush=True)
+
+
 if __name__ == "__main__":
-    names = sys.argv[1:] or [n for n in CASES if not n.startswith("L100")]
+    args = sys.argv[1:]
+    if args and args[0] == "--certify":
+        for n in args[1:] or list(CASES):
+            certify_stored(n)
+        sys.exit(0)
+    names = args or [n for n in CASES if not n.startswith("L100")]
     for n in names:
         run(n, CASES[n])

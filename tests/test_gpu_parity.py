@@ -281,7 +281,22 @@ def test_solve_options_setter():
     assert np.max(np.abs(np.sort(e0) - np.sort(ref))) <= 1e-9 and np.max(np.abs(np.sort(e1) - np.sort(ref))) <= 1e-9
     with pytest.raises(jd.JdError):
         p.set_solve_options(jmax=121)
+    for bad in (dict(jmin=120), dict(jmin=30, jmax=30)):
+        with pytest.raises(jd.JdError):
+            p.set_solve_options(**bad)
+    # jmin alone, above the default jmax of this size (2 * max(k + 5, 10) = 20): the
+    # restart then keeps 25 of at least 26 columns
+    p.set_solve_options(jmin=25)
+    e2, _, _, i2 = p.solve(4, 1e-10)
+    assert i2["status"] == 0 and np.max(np.abs(np.sort(e2) - np.sort(ref))) <= 1e-9
     p.close()
+
+
+def test_search_space_set_at_setup_with_jmin_alone():
+    # the same rule through jd_solve's options (L = 10, k = 5: default jmax 20)
+    ref = eig.anderson_nearest(10, 16.5, 0, 0.0, 5)[0]
+    evals, _, _, info = jd.solve(10, 16.5, 0, 0.0, 5, 1e-10, precision="mixed", jmin=25)
+    assert info["status"] == 0 and np.max(np.abs(evals - ref)) <= 1e-9
 
 
 def test_solve_after_a_stalled_setup():

@@ -68,6 +68,23 @@ def test_invalid_arguments_rejected(jd):
     assert rc == jd.JD_EINVAL
 
 
+@pytest.mark.parametrize("jmin,jmax", [(120, 0), (200, 0), (30, 30), (40, 20), (-1, 0), (0, 121)])
+def test_search_space_sizes_rejected(jd, jmin, jmax):
+    """A restart keeps jmin of at most jmax <= 120 columns: jmin >= 120, or jmin >= jmax
+    when both are given, would write past the search space; both option entry points
+    refuse them before any device call."""
+    lib = jd.lib()
+    ev = np.zeros(4)
+    p = ev.ctypes.data_as(ctypes.c_void_p)
+    o = jd.make_options(precision="fp64", jmin=jmin, jmax=jmax)
+    rc = lib.jd_solve(10, 16.5, 0, 0.0, 4, 1e-10, p, None, None, ctypes.byref(o), None)
+    assert rc == jd.JD_EINVAL, (jmin, jmax)
+    assert "jm" in lib.jd_last_error().decode()
+    h = ctypes.c_void_p()
+    rc = lib.jd_setup(10, 16.5, 0, 0.0, ctypes.byref(o), ctypes.byref(h))
+    assert rc == jd.JD_EINVAL and not h.value
+
+
 # --- host setup helpers --------------------------------------------------------------
 
 def _csr(A):

@@ -225,3 +225,41 @@ def test_planted_mistakes_are_caught(monkeypatch, mistake):
         return
     w = jacobi.eigh(A, vectors=False)[0]
     assert not np.allclose(w, np.sort(lattice.clean_spectrum(L)), atol=1e-9)
+
+
+@pytest.mark.parametrize("L,sigma", [(3, -6.0), (4, 6.0)])
+def test_singular_shift_retry_clean_lattice(L, sigma):
+    """The factorisation shift moves off sigma when A - sigma I is singular.
+
+    At W = 0 the extreme eigenvalues of the periodic lattice are simple: -6 (the
+    constant vector) and, for even L, +6 (the staggered vector (-1)^(i+j+k)); the
+    closed form -2 sum cos(2 pi a / L) puts the nearest other eigenvalue 2 (L = 4) or
+    3 (L = 3) away.  With sigma exactly on one of them the exact LDL^T of A - sigma I
+    meets a zero (or rounding-sized) pivot, factor_near retries at
+    sigma + 1e-9 (1 + |sigma|), solves with the retried factors are accurate, and
+    shift-and-invert Lanczos with that shift returns the eigenvalue sigma itself with
+    the closed-form eigenvector."""
+    eps = np.zeros(L ** 3)
+    anorm = lattice.inf_norm(eps)
+    spec = np.sort(lattice.clean_spectrum(L))
+    assert spec[0 if sigma < 0 else -1] == sigma
+    f = eig.factor_near(L, eps, sigma)
+    assert f.tau == sigma + 1e-9 * (1.0 + abs(sigma))
+    assert f.min_pivot > 1e-13 * anorm
+    b = np.random.default_rng(5).standard_normal(L ** 3)
+    x = f.solve(b)
+    # backward error of the solve with the retried shift, at rounding level
+    r = lattice.matvec(L, eps, x, shift=f.tau) - b
+    assert np.linalg.norm(r) <= 1e-12 * (anorm * np.linalg.norm(x) + np.linalg.norm(b))
+    # With the shift 1e-9 from the eigenvalue, (A - sigma_f I)^{-1} has condition ~1e9
+    # and the Lanczos vectors after the dominant one carry rounding of that size: the
+    # Ritz vector's residual stalls near 1e-9 ||A||, while its Rayleigh quotient is
+    # exact to rounding (the error is quadratic in the vector's)
+    lams, X, res = lanczos.si_lanczos(L, eps, sigma, 1, eig._Solver(f), tol=1e-8, extra=0)
+    assert abs(lams[0] - sigma) <= 1e-12
+    i, j, k = lattice.site_coords(L)
+    v = np.ones(L ** 3) if sigma < 0 else (-1.0) ** (i + j + k)
+    v /= np.linalg.norm(v)
+    c = abs(X[:, 0] @ v)
+    assert np.sqrt(max(0.0, 1.0 - c * c)) <= 1e-8  # sine of the angle to the closed form
+    assert res[0] <= 1e-8 * anorm
