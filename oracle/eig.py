@@ -5,13 +5,16 @@ Anderson matrix nearest a target sigma (the paper: the five nearest lambda = 0).
 Definition used here: the k eigenvalues of A = -T + diag(eps) on the periodic
 L^3 lattice with the smallest |lambda - sigma|, ties ordered by lambda, with unit
 eigenvectors whose largest-modulus component is positive (lowest index on ties).
-No preconditioner or iteration parameter enters this definition.
+No preconditioner or iteration parameter enters this definition.  With bc="hardwall"
+the same definition holds for the lattice with hard walls (section 8.2).
 
 * n <= DENSE_MAX: all eigenpairs by dense Jacobi (O3), then selection;
 * otherwise: shift-and-invert Lanczos (O5) on the exact multifrontal LDL^T (O4).
   If A - sigma I is numerically singular the factorisation shift becomes
   sigma_f = sigma + 1e-9 (1 + |sigma|); selection still uses sigma.
 """
+import time
+
 import numpy as np
 
 from . import generator, jacobi, lanczos, lattice, ldlt
@@ -45,12 +48,12 @@ class _Solver:
         return self.fact.solve(b)
 
 
-def factor_near(L, eps, sigma, leaf=256):
+def factor_near(L, eps, sigma, leaf=256, bc="periodic"):
     """Exact LDL^T of A - sigma_f I with the singular-shift retry."""
-    anorm = lattice.inf_norm(eps)
+    anorm = lattice.inf_norm(eps, L, bc)
     for sf in (sigma, sigma + 1e-9 * (1.0 + abs(sigma))):
         try:
-            f = ldlt.LDLT(L, eps, sf, leaf=leaf)
+            f = ldlt.LDLT(L, eps, sf, leaf=leaf, bc=bc)
         except ZeroDivisionError:
             continue
         if f.min_pivot > 1e-13 * anorm:
@@ -58,25 +61,33 @@ def factor_near(L, eps, sigma, leaf=256):
     return f
 
 
-def nearest_eigenpairs(L, eps, sigma, k, tol=1e-12, method=None):
-    """(lams[k], X[n, k], res[k], anorm) -- the result definition above."""
+def nearest_eigenpairs(L, eps, sigma, k, tol=1e-12, method=None, timings=None, bc="periodic"):
+    """(lams[k], X[n, k], res[k], anorm) -- the result definition above.
+
+    ``timings`` (a dict, optional) receives the seconds of the factorisation and of the
+    Lanczos iteration of the large path."""
     eps = np.asarray(eps, dtype=np.float64)
     n = L ** 3
-    anorm = lattice.inf_norm(eps)
+    anorm = lattice.inf_norm(eps, L, bc)
     if method is None:
         method = "dense" if n <= DENSE_MAX else "lanczos"
     if method == "dense":
-        A = lattice.hamiltonian(L, eps).toarray()
+        A = lattice.hamiltonian(L, eps, bc=bc).toarray()
         w, V = jacobi.eigh(A)
         idx = select_nearest(w, sigma, k)
         lams, X = w[idx], V[:, idx]
     else:
-        f = factor_near(L, eps, sigma)
-        lams, X, _ = lanczos.si_lanczos(L, eps, sigma, k, _Solver(f), tol=tol)
+        t0 = time.time()
+        f = factor_near(L, eps, sigma, bc=bc)
+        t1 = time.time()
+        lams, X, _ = lanczos.si_lanczos(L, eps, sigma, k, _Solver(f), tol=tol, bc=bc)
+        if timings is not None:
+            timings["factorisation_s"] = t1 - t0
+            timings["lanczos_s"] = time.time() - t1
         idx = select_nearest(lams, sigma, k)
         lams, X = lams[idx], X[:, idx]
     X = normalise_signs(X)
-    res = np.array([np.linalg.norm(lattice.matvec(L, eps, X[:, c]) - lams[c] * X[:, c])
+    res = np.array([np.linalg.norm(lattice.matvec(L, eps, X[:, c], bc=bc) - lams[c] * X[:, c])
                     for c in range(X.shape[1])])
     return lams, X, res, anorm
 
@@ -85,10 +96,10 @@ def anderson_nearest(L, W, seed, sigma, k, **kw):
     return nearest_eigenpairs(L, generator.disorder(L, W, seed), sigma, k, **kw)
 
 
-def count_in_window(L, eps, lo, hi):
+def count_in_window(L, eps, lo, hi, bc="periodic"):
     """Number of eigenvalues in [lo, hi) by two inertia counts (Sylvester)."""
-    n_hi, z_hi = ldlt.count_below(L, eps, hi)
-    n_lo, z_lo = ldlt.count_below(L, eps, lo)
+    n_hi, z_hi = ldlt.count_below(L, eps, hi, bc=bc)
+    n_lo, z_lo = ldlt.count_below(L, eps, lo, bc=bc)
     if z_hi or z_lo:
         raise ZeroDivisionError("window end is an eigenvalue")
     return n_hi - n_lo

@@ -10,6 +10,10 @@ other (U T U = -T), so the spectra coincide; the tests check this.
 Periodic boundary conditions (figure 1 caption; section 8.2): x_0 = x_L and
 x_{L+1} = x_1 in every direction.  For L = 2 the +1 and -1 neighbours of a site
 coincide, so the two couplings add up to one entry of -2.
+
+Hard-wall boundary conditions (section 8.2, the variant of Table 6): the lattice is
+embedded in zeros, x_0 = x_{L+1} = 0, so a site on a face has no coupling across it.
+``bc`` selects "periodic" (default) or "hardwall" everywhere below.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -22,37 +26,90 @@ def site_coords(L):
     return s % L, (s // L) % L, s // (L * L)
 
 
-def hamiltonian(L, eps, hopping=-1.0):
+def _check_bc(bc):
+    if bc not in ("periodic", "hardwall"):
+        raise ValueError(f"unknown boundary condition {bc!r}")
+
+
+def hamiltonian(L, eps, hopping=-1.0, bc="periodic"):
     """CSR of A = hopping * T + diag(eps); duplicate couplings accumulate."""
+    _check_bc(bc)
     n = L ** 3
     i, j, k = site_coords(L)
     s = np.arange(n)
     rows, cols = [s], [s]
     vals = [np.asarray(eps, dtype=np.float64)]
     for di, dj, dk in NEIGHBOURS:
-        rows.append(s)
-        cols.append(((i + di) % L) + L * (((j + dj) % L) + L * ((k + dk) % L)))
-        vals.append(np.full(n, hopping))
+        ii, jj, kk = i + di, j + dj, k + dk
+        if bc == "periodic":
+            keep = np.ones(n, bool)
+        else:  # a neighbour outside the box is a zero of the embedding: no coupling
+            keep = (ii >= 0) & (ii < L) & (jj >= 0) & (jj < L) & (kk >= 0) & (kk < L)
+        rows.append(s[keep])
+        cols.append(((ii % L) + L * ((jj % L) + L * (kk % L)))[keep])
+        vals.append(np.full(int(keep.sum()), hopping))
     A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(n, n))
     return A.tocsr()  # COO -> CSR sums duplicates
 
 
-def matvec(L, eps, x, shift=0.0, hopping=-1.0):
+def _shift(X, step, axis, bc):
+    """Y[.., m, ..] = X[.., m - step, ..] along axis: cyclic, or with zeros shifted in."""
+    if bc == "periodic":
+        return np.roll(X, step, axis)
+    Y = np.zeros_like(X)
+    src = [slice(None)] * 3
+    dst = [slice(None)] * 3
+    if step > 0:
+        src[axis], dst[axis] = slice(0, X.shape[axis] - step), slice(step, None)
+    else:
+        src[axis], dst[axis] = slice(-step, None), slice(0, X.shape[axis] + step)
+    Y[tuple(dst)] = X[tuple(src)]
+    return Y
+
+
+def matvec(L, eps, x, shift=0.0, hopping=-1.0, bc="periodic"):
     """y = (A - shift I) x, written out neighbour by neighbour."""
+    _check_bc(bc)
     x = np.asarray(x, dtype=np.float64)
     X = x.reshape(L, L, L)  # axes (k, j, i)
-    nb = (np.roll(X, 1, 2) + np.roll(X, -1, 2) + np.roll(X, 1, 1) + np.roll(X, -1, 1)
-          + np.roll(X, 1, 0) + np.roll(X, -1, 0)).reshape(-1)
+    nb = (_shift(X, 1, 2, bc) + _shift(X, -1, 2, bc) + _shift(X, 1, 1, bc) + _shift(X, -1, 1, bc)
+          + _shift(X, 1, 0, bc) + _shift(X, -1, 0, bc)).reshape(-1)
     return hopping * nb + (np.asarray(eps) - shift) * x
 
 
-def inf_norm(eps):
-    """||A||_inf = 6 + max|eps| (six couplings of modulus 1 per row, any L >= 2)."""
-    return 6.0 + float(np.max(np.abs(eps))) if len(eps) else 6.0
+def degree(L, bc="periodic"):
+    """Couplings of every site: 6 on the torus; 6 minus the faces a site lies on with
+    hard walls (for L = 1 every coupling leaves the box)."""
+    _check_bc(bc)
+    if bc == "periodic":
+        return np.full(L ** 3, 6)
+    i, j, k = site_coords(L)
+    d = np.zeros(L ** 3, dtype=np.int64)
+    for c in (i, j, k):
+        d += (c > 0).astype(np.int64) + (c < L - 1).astype(np.int64)
+    return d
 
 
-def clean_spectrum(L):
-    """Closed form at W = 0: -2 (cos(2 pi a/L) + cos(2 pi b/L) + cos(2 pi c/L))."""
-    c = np.cos(2.0 * np.pi * np.arange(L) / L)
+def inf_norm(eps, L=None, bc="periodic"):
+    """||A||_inf = max_s (couplings of s + |eps_s|): 6 + max|eps| on the torus (six
+    couplings of modulus 1 per row, any L >= 2); with hard walls the row sums differ
+    and L is needed."""
+    eps = np.asarray(eps, dtype=np.float64)
+    if bc == "periodic":
+        return 6.0 + float(np.max(np.abs(eps))) if len(eps) else 6.0
+    if L is None:
+        L = int(round(len(eps) ** (1.0 / 3.0)))
+    return float(np.max(degree(L, bc) + np.abs(eps)))
+
+
+def clean_spectrum(L, bc="periodic"):
+    """Closed form at W = 0: -2 (cos(2 pi a/L) + cos(2 pi b/L) + cos(2 pi c/L)),
+    a, b, c = 0 .. L-1 (periodic); -2 sum cos(pi a/(L+1)), a = 1 .. L (hard walls:
+    the sine modes of the open chain)."""
+    _check_bc(bc)
+    if bc == "periodic":
+        c = np.cos(2.0 * np.pi * np.arange(L) / L)
+    else:
+        c = np.cos(np.pi * np.arange(1, L + 1) / (L + 1))
     return -2.0 * (c[:, None, None] + c[None, :, None] + c[None, None, :]).reshape(-1)

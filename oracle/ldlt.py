@@ -46,8 +46,9 @@ def _region_sites(L, ivs):
     return (xs[None, None, :] + L * (ys[None, :, None] + L * zs[:, None, None])).reshape(-1)
 
 
-def nested_dissection(L, leaf=256):
-    """Postorder list of nodes of a geometric nested-dissection tree of the torus."""
+def nested_dissection(L, leaf=256, bc="periodic"):
+    """Postorder list of nodes of a geometric nested-dissection tree of the torus (or,
+    with hard walls, of the box: every direction open from the start)."""
     order = []
 
     def build(ivs, wrap):
@@ -92,17 +93,22 @@ def nested_dissection(L, leaf=256):
         order.append(node)
         return node
 
-    build([list(range(L))] * 3, [True, True, True])
+    periodic = bc == "periodic"
+    build([list(range(L))] * 3, [periodic] * 3)
     return order
 
 
-def _neighbours(L, v):
+def _neighbours(L, v, bc="periodic"):
     i = v % L
     j = (v // L) % L
     k = v // (L * L)
     out = []
     for di, dj, dk in lattice.NEIGHBOURS:
-        out.append(((i + di) % L) + L * (((j + dj) % L) + L * ((k + dk) % L)))
+        ii, jj, kk = i + di, j + dj, k + dk
+        nb = (ii % L) + L * ((jj % L) + L * (kk % L))
+        if bc != "periodic":
+            nb = nb[(ii >= 0) & (ii < L) & (jj >= 0) & (jj < L) & (kk >= 0) & (kk < L)]
+        out.append(nb)
     return np.concatenate(out)
 
 
@@ -145,15 +151,16 @@ class LDLT:
     soon as its Schur complement has been passed on.
     """
 
-    def __init__(self, L, eps, tau, leaf=256, keep_factors=True):
+    def __init__(self, L, eps, tau, leaf=256, keep_factors=True, bc="periodic"):
         self.L = L
         self.n = L ** 3
         self.tau = float(tau)
+        self.bc = bc
         self.eps = np.asarray(eps, dtype=np.float64)
-        A = lattice.hamiltonian(L, self.eps)
+        A = lattice.hamiltonian(L, self.eps, bc=bc)
         A = A - self.tau * _sp_eye(self.n)
         A = A.tocsr()
-        self.nodes = nested_dissection(L, leaf)
+        self.nodes = nested_dissection(L, leaf, bc)
         owner = np.empty(self.n, dtype=np.int64)
         for t, node in enumerate(self.nodes):
             owner[node.own] = t
@@ -165,7 +172,7 @@ class LDLT:
         self.neg = self.zero = self.pos = 0
         self.min_pivot = np.inf
         for t, node in enumerate(self.nodes):
-            cand = [_neighbours(L, node.own)] + [c.bnd for c in node.children]
+            cand = [_neighbours(L, node.own, bc)] + [c.bnd for c in node.children]
             cand = np.unique(np.concatenate(cand))
             node.bnd = cand[owner[cand] > t]
             front = np.concatenate([node.own, node.bnd])
@@ -226,7 +233,7 @@ class LDLT:
         b = np.asarray(b, dtype=np.float64)
         x = self._sweep(b)
         for _ in range(refine):
-            r = b - lattice.matvec(self.L, self.eps, x, shift=self.tau)
+            r = b - lattice.matvec(self.L, self.eps, x, shift=self.tau, bc=self.bc)
             x = x + self._sweep(r)
         return x
 
@@ -252,8 +259,8 @@ def _sp_eye(n):
     return sp.identity(n, format="csr")
 
 
-def count_below(L, eps, tau, leaf=256):
+def count_below(L, eps, tau, leaf=256, bc="periodic"):
     """Number of eigenvalues of A strictly below tau (inertia of A - tau I)."""
-    f = LDLT(L, eps, tau, leaf=leaf, keep_factors=False)
+    f = LDLT(L, eps, tau, leaf=leaf, keep_factors=False, bc=bc)
     neg, zero, _ = f.inertia()
     return neg, zero

@@ -33,7 +33,29 @@ CASES = {
     "L20_W12_s1000000_k7": dict(L=20, W=12.0, seed=1000000, sigma=0.35, k=7),
     "L30_W21_s1000001_k3": dict(L=30, W=21.0, seed=1000001, sigma=-0.62, k=3),
     "L40_W16.5_s1000002_k10": dict(L=40, W=16.5, seed=1000002, sigma=0.11, k=10),
+    # a hard serving request: W = 12 near the band centre, the largest lattice of the mix
+    "L60_W12_s1000041_k7": dict(L=60, W=12.0, seed=1000041, sigma=0.6205487042125981, k=7),
+    # hard-wall boundary conditions (section 8.2, Table 6)
+    "L30_W16.5_s0_k5_hardwall": dict(L=30, W=16.5, seed=0, sigma=0.0, k=5, bc="hardwall"),
 }
+
+
+def _machine():
+    import os
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except Exception:
+        threads = os.cpu_count()
+    return f"{threads} threads, {model}"
 
 
 def certify(out, eps):
@@ -50,7 +72,7 @@ def certify(out, eps):
     d_k, d_next = abs(lams[-1] - sigma), abs(out["next"] - sigma)
     rho = 0.5 * (d_k + d_next)
     t0 = time.time()
-    count = eig.count_in_window(out["L"], eps, sigma - rho, sigma + rho)
+    count = eig.count_in_window(out["L"], eps, sigma - rho, sigma + rho, bc=out.get("bc", "periodic"))
     assert count == k, (count, k)
     iv = [(lams[i] - res[i], lams[i] + res[i]) for i in range(k)]
     kt = []
@@ -73,16 +95,19 @@ def certify(out, eps):
 def run(name, c):
     t0 = time.time()
     eps = generator.disorder(c["L"], c["W"], c["seed"])
+    tm = {}
+    bc = c.get("bc", "periodic")
     lams, X, res, anorm = eig.nearest_eigenpairs(c["L"], eps, c["sigma"], c["k"] + 1,
-                                                 method="lanczos")
+                                                 method="lanczos", timings=tm, bc=bc)
     out = dict(c)
     out.pop("dense", None)
     out.update(lams=[float(v) for v in lams[:c["k"]]], next=float(lams[c["k"]]),
                res=[float(v) for v in res[:c["k"]]], anorm=anorm, method="si-lanczos",
-               seconds=round(time.time() - t0, 1),
+               seconds=round(time.time() - t0, 1), factor_seconds=round(tm["factorisation_s"], 1),
+               lanczos_seconds=round(tm["lanczos_s"], 1), machine=_machine(),
                cite="section 3 eq. (eigenequation); problem: k eigenvalues nearest sigma")
     if c.get("dense"):
-        A = lattice.hamiltonian(c["L"], eps).toarray()
+        A = lattice.hamiltonian(c["L"], eps, bc=bc).toarray()
         w = jacobi.eigh(A, vectors=False)[0]
         idx = eig.select_nearest(w, c["sigma"], c["k"] + 1)
         out["lams_dense_jacobi"] = [float(v) for v in w[idx][:c["k"]]]

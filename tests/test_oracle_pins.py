@@ -263,3 +263,99 @@ def test_singular_shift_retry_clean_lattice(L, sigma):
     c = abs(X[:, 0] @ v)
     assert np.sqrt(max(0.0, 1.0 - c * c)) <= 1e-8  # sine of the angle to the closed form
     assert res[0] <= 1e-8 * anorm
+
+
+# --- hard-wall boundary conditions (section 8.2, Table 6) ---------------------------
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5])
+def test_hardwall_clean_spectrum_closed_form(L):
+    # W = 0 with hard walls: the open chain's sine modes give -2 sum cos(pi a / (L+1)),
+    # a = 1..L; L = 1 is a single uncoupled site
+    A = lattice.hamiltonian(L, np.zeros(L ** 3), bc="hardwall").toarray()
+    w, V = jacobi.eigh(A)
+    assert np.allclose(w, np.sort(lattice.clean_spectrum(L, bc="hardwall")), atol=1e-12, rtol=0)
+    assert np.allclose(A @ V, V * w, atol=1e-12)
+
+
+def test_hardwall_structure_and_norm():
+    for L in (2, 3, 5):
+        e = generator.disorder(L, 12.0, 3)
+        A = lattice.hamiltonian(L, e, bc="hardwall")
+        assert abs(A - A.T).max() == 0
+        assert np.array_equal(A.diagonal(), e)
+        # 3 L^2 (L - 1) bonds, each stored twice
+        assert A.nnz - L ** 3 == 6 * L * L * (L - 1)
+        rowsum = np.asarray(abs(A).sum(axis=1)).ravel()
+        assert np.allclose(rowsum, lattice.degree(L, "hardwall") + np.abs(e))
+        assert np.isclose(lattice.inf_norm(e, L, "hardwall"), rowsum.max())
+        x = np.random.default_rng(L).standard_normal(L ** 3)
+        assert np.allclose(lattice.matvec(L, e, x, shift=0.3, bc="hardwall"), A @ x - 0.3 * x, atol=1e-13, rtol=0)
+
+
+@pytest.mark.parametrize("L", [3, 5])
+def test_hardwall_gauge_any_L(L):
+    # the box without wrap is bipartite for every L: spec H(eps) = -spec H(-eps), and the
+    # +1 and -1 hopping conventions share one spectrum (odd L too, unlike the torus)
+    e = generator.disorder(L, 16.5, 2)
+    w = jacobi.eigh(lattice.hamiltonian(L, e, bc="hardwall").toarray(), vectors=False)[0]
+    wm = jacobi.eigh(lattice.hamiltonian(L, -e, bc="hardwall").toarray(), vectors=False)[0]
+    wp = jacobi.eigh(lattice.hamiltonian(L, e, hopping=+1.0, bc="hardwall").toarray(), vectors=False)[0]
+    assert np.allclose(w, -wm[::-1], atol=1e-12)
+    assert np.allclose(w, wp, atol=1e-12)
+
+
+@pytest.mark.parametrize("L,seed", [(3, 0), (5, 1), (7, 3)])
+def test_hardwall_inertia_matches_dense_count(L, seed):
+    e = generator.disorder(L, 16.5, seed)
+    A = lattice.hamiltonian(L, e, bc="hardwall").toarray()
+    w = jacobi.eigh(A, vectors=False)[0]
+    for tau in (0.0, 0.41, -2.3):
+        f = ldlt.LDLT(L, e, tau, leaf=20, bc="hardwall")
+        neg, zero, pos = f.inertia()
+        assert neg == int((w < tau).sum()) and zero == 0 and neg + pos == L ** 3
+        b = np.random.default_rng(1).standard_normal(L ** 3)
+        x = f.solve(b)
+        assert np.linalg.norm(A @ x - tau * x - b) <= 1e-12 * np.linalg.norm(b) * lattice.inf_norm(e, L, "hardwall")
+
+
+def test_hardwall_lanczos_matches_dense_and_differs_from_periodic():
+    L = 8
+    e = generator.disorder(L, 16.5, 0)
+    l1, X1, r1, an = eig.nearest_eigenpairs(L, e, 0.0, 6, method="dense", bc="hardwall")
+    l2, X2, r2, _ = eig.nearest_eigenpairs(L, e, 0.0, 6, method="lanczos", bc="hardwall")
+    assert np.allclose(l1, l2, atol=1e-12, rtol=0)
+    assert np.allclose(X1, X2, atol=1e-8)
+    assert r1.max() <= 1e-12 * an and r2.max() <= 1e-12 * an
+    lp = eig.nearest_eigenpairs(L, e, 0.0, 6, method="dense")[0]
+    assert np.max(np.abs(lp - l1)) > 1e-3  # the boundary condition matters
+
+
+def _open_chain(f):
+    m = len(f)
+    H = np.diag(f)
+    for i in range(m - 1):
+        H[i, i + 1] = H[i + 1, i] = -1.0
+    return H
+
+
+def test_hardwall_separable_kronecker_sum():
+    # eps_{ijk} = f_i + g_j + h_k: a Kronecker sum of three open chains
+    L, sigma, k = 16, 0.2, 8
+    rng = np.random.default_rng(7)
+    f, g, h = (rng.uniform(-2.5, 2.5, L) for _ in range(3))
+    eps = (f[None, None, :] + g[None, :, None] + h[:, None, None]).reshape(-1)
+    ea, eb, ec = (jacobi.eigh(_open_chain(v), vectors=False)[0] for v in (f, g, h))
+    sums = (ea[None, None, :] + eb[None, :, None] + ec[:, None, None]).reshape(-1)
+    ref = sums[eig.select_nearest(sums, sigma, k)]
+    lams, X, res, an = eig.nearest_eigenpairs(L, eps, sigma, k, bc="hardwall")
+    assert np.allclose(lams, ref, atol=1e-11, rtol=0)
+    assert res.max() <= 1e-12 * an
+
+
+def test_hardwall_inertia_closed_form():
+    L = 12
+    spec = lattice.clean_spectrum(L, bc="hardwall")
+    for tau in (0.1234, -1.777):
+        assert np.min(np.abs(spec - tau)) > 1e-3
+        neg, zero = ldlt.count_below(L, np.zeros(L ** 3), tau, bc="hardwall")
+        assert zero == 0 and neg == int((spec < tau).sum())
