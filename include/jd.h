@@ -48,6 +48,11 @@ enum {
 
 enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
 
+/* Boundary conditions of the lattice (section 8.2): periodic (the paper's main
+ * experiments; figure 1) or hard walls (the Table 6 variant: the box is embedded in
+ * zeros, so a site on a face has no coupling across it). */
+enum { JD_BC_PERIODIC = 0, JD_BC_HARDWALL = 1 };
+
 /*
  * Options; a zero-initialised struct selects every default.
  *  precision  JD_FP64: every step in binary64.  JD_MIXED: stencil SpMV in
@@ -71,10 +76,13 @@ enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
  *             last Schur complement is inverted exactly (0 -> 1536); it also stops
  *             once a level accepts fewer than 1% of its unknowns and at most 8192 remain.
  *  max_levels cap on the number of levels (0 -> 400).
- *  z_drop     the preconditioner is applied as P^T Z^T D^{-1} Z P with Z the explicit
- *             inverse of the unit lower triangular factor of all levels; entries of Z
- *             below z_drop (scaled domain) are dropped (0 -> min(1e-2, 10 drop_tol);
- *             < 0 -> none).
+ *  z_drop     the preconditioner is applied as P^T Z^T D^{-1} Z P with Z the inverse
+ *             of the unit lower triangular factor of all levels, formed explicitly as a
+ *             product of segments Z = Z_{S-1} ... Z_0, each the inverse of the factor of a
+ *             consecutive range of levels; entries of each Z_s below z_drop (scaled
+ *             domain) are dropped (0 -> min(1e-2, 10 drop_tol); < 0 -> none).
+ *  z_parts    the number S of segments: level cuts at 1, 3, 9, 27, ... (0 -> 6 for
+ *             n >= 2^19, 4 for n >= 2^16, else 3; 1 -> a single explicit inverse).
  *  jmin, jmax search-space sizes after / before a restart (0 -> for n >= 2^19 or a
  *             setup that stalled (see kappa): max(k+20,30) and min(3 jmin, 120), else
  *             max(k+5,10) and min(2 jmin, 120)); jmin < 120, jmax <= 120, and
@@ -92,6 +100,8 @@ enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
  *             same results; the serving workers always launch kernel by kernel).
  *             bit 1 (JD_FLAG_LEVELS): apply the factorisation level by level (two
  *             dependent sparse passes per level) instead of through Z.
+ *  bc         JD_BC_PERIODIC (0) or JD_BC_HARDWALL; ||A||_inf is then the largest row
+ *             sum, couplings (6 on the torus, fewer on the faces of the box) plus |eps|.
  *  stream     stream for the solve's device work (NULL: a library-created blocking stream).
  */
 typedef struct jd_options {
@@ -107,6 +117,8 @@ typedef struct jd_options {
     int max_outer, max_inner;
     double switch_tol;
     int flags;
+    int z_parts;
+    int bc;
     void *stream;
 } jd_options;
 
@@ -154,6 +166,21 @@ int jd_setup(int L, double W, uint64_t seed, double sigma, const jd_options *opt
  * array of n*k binary64 values that receives the eigenvectors. */
 int jd_problem_solve(jd_problem *p, int k, double tol, double *evals, double *evecs_host,
                      void *evecs_device, double *resid, jd_info *info);
+/*
+ * jd_problem_lanczos -- the same k eigenpairs by shift-and-invert Lanczos (section 4.1;
+ * the ARPACK runs of section 8.2, Tables 2-3): Lanczos on (A - sigma I)^{-1} with full
+ * reorthogonalisation and restarts that keep the wanted Ritz vectors, each product an
+ * SQMR solve with the problem's multilevel preconditioner stopped when its quasi-residual
+ * bound reaches inner_tol times the right-hand side's norm (0 -> 1e-10, the paper's
+ * setting).  Outputs as jd_problem_solve (no device vectors); info->outer_its counts the
+ * products with (A - sigma I)^{-1}, info->inner_its the SQMR steps.  Options of the
+ * problem: jmax is the largest basis (0 -> min(max(2(k+5), k+25), 120)), max_outer the
+ * products (0 -> 60 k + 200), max_inner the SQMR steps of one product (0 -> 1000).
+ * Needs binary64 vectors: JD_ENOTIMPL for JD_MIXED (binary32 inner solves cannot reach
+ * 1e-10); JD_MIXED_FACTORS uses the binary32 factors with binary64 vectors.
+ */
+int jd_problem_lanczos(jd_problem *p, int k, double tol, double inner_tol, double *evals, double *evecs_host,
+                       double *resid, jd_info *info);
 /* Switch the precision of later jd_problem_solve calls (JD_FP64, JD_MIXED or
  * JD_MIXED_FACTORS); the setup keeps the factors in both precisions, so no new setup
  * is needed. */
@@ -176,11 +203,12 @@ void jd_problem_free(jd_problem *p);
 int jd_gen_diag(int L, double W, uint64_t seed, double *d_eps, float *d_eps32, void *stream);
 
 /*
- * jd_stencil_spmv -- y = (A - shift I) x on the periodic lattice (section 3,
+ * jd_stencil_spmv -- y = (A - shift I) x on the lattice (section 3,
  * eq. (eigenequation)); only eps is stored, the couplings are implicit.
+ *   bc JD_BC_PERIODIC or JD_BC_HARDWALL (section 8.2).
  *   precision JD_FP64: d_eps, d_x, d_y are double*; JD_MIXED: float*.
  */
-int jd_stencil_spmv(int L, int precision, const void *d_eps, double shift,
+int jd_stencil_spmv(int L, int bc, int precision, const void *d_eps, double shift,
                     const void *d_x, void *d_y, void *stream);
 
 /*
@@ -207,10 +235,20 @@ void jd_precond_free(jd_precond *p);
 /* A view of the preconditioner held by a problem (valid while the problem lives;
  * release the view with jd_precond_free). */
 int jd_problem_precond(jd_problem *p, jd_precond **out);
-/* Number of stored entries of the explicit inverse factor Z (and n). */
+/* Number of stored entries of the inverse factor, all segments (and n). */
 int jd_precond_factor_nnz(const jd_precond *p, long long *nnz, int *n);
-/* The dominant kernel of the apply on its own: y = Z x (transpose = 0, positions order)
- * or y[perm[r]] = (Z^T x)[r] (transpose = 1).  Device vectors of length n. */
+/* Segments of the inverse factor: lev_begin[s] = first level of segment s, rows[s] =
+ * rows of Z_s (unknowns entering that level), nnz[s] = its stored entries (arrays of
+ * length cap, host; NULL entries skipped).  Returns the number of segments. */
+int jd_precond_segments(const jd_precond *p, int cap, int *lev_begin, int *rows, long long *nnz);
+/* The dominant kernel of the apply on its own: the sparse products with the segments.
+ * transpose = 0: y = Z_{S-1} ... Z_0 x, x in the Morton order of the sites, y in the
+ * middle numbering of the factorisation; transpose = 1: y = P^T Z_0^T ... Z_{S-1}^T x,
+ * x in the middle numbering, y in site order.  Device vectors of length n (d_x is copied
+ * into the preconditioner's workspace, the result copied out for transpose = 0).  With
+ * d_x = d_y = NULL only the products run, on the values the workspace holds (timing
+ * form: the kernels of one apply's direction and nothing else).  The workspace is the
+ * one jd_precond_apply uses: calls on one preconditioner must not overlap. */
 int jd_precond_factor_product(jd_precond *p, int precision, int transpose, const void *d_x, void *d_y,
                               void *stream);
 
@@ -227,6 +265,7 @@ int jd_precond_factor_product(jd_precond *p, int precision, int transpose, const
  */
 int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int pcols,
                             const double *d_b, double *d_x, double rtol, int maxit, int *its);
+
 
 /*
  * Serving: continuous batching of independent solve requests (the disorder averaging
@@ -247,6 +286,7 @@ typedef struct jd_request {
     double tol;
     int precision;    /* JD_FP64, JD_MIXED or JD_MIXED_FACTORS */
     int flags;        /* jd_options flags (JD_FLAG_LEVELS; JD_FLAG_GRAPHS is ignored) */
+    int bc;           /* JD_BC_PERIODIC or JD_BC_HARDWALL */
 } jd_request;
 
 typedef struct jd_result {
@@ -313,6 +353,26 @@ int jd_host_split_cycles(int n, const int64_t *ptr, const int *col, const double
 int jd_host_factor(int n, const int64_t *ptr, const int *col, const double *val, const jd_options *opt,
                    int *perm, double *scale, int cap, int *level_off, int *level_nb, int *level_n2x2,
                    long long *g_nnz, double *g_min_scaled, double *g_max_colsum, int *coarse_n);
+
+/*
+ * jd_set_allocator -- device memory from the caller (for instance a framework's caching
+ * allocator), so that the library's buffers share the caller's memory pool.  Every device
+ * buffer the library allocates after the call -- a problem's operator and factors, the
+ * search space and work vectors of each solve, the buffers of serving requests -- comes
+ * from alloc(bytes, stream, ctx) and goes back through free_(ptr, stream, ctx); `stream`
+ * is the hipStream_t whose work uses the buffer.  alloc returns device memory on the
+ * current device, aligned to 256 bytes, or NULL (the calling entry point then fails with
+ * JD_ENOMEM).  Before a buffer is handed to free_ the library synchronises that stream,
+ * so free_ may reuse it at once.  Both functions may be called from any library thread
+ * (serving workers) and must be thread-safe; they must not call into this library.
+ * alloc = free_ = NULL restores hipMalloc / hipFree.  A buffer is always returned to the
+ * allocator it came from, also after a later jd_set_allocator call; ctx must stay valid
+ * while such buffers live.  JD_EINVAL if exactly one of alloc, free_ is NULL.
+ * Not a step of the paper's method: it lets the host framework (PyTorch in the Python
+ * binding) own the device memory.
+ */
+int jd_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
+                     void (*free_)(void *ptr, void *stream, void *ctx), void *ctx);
 
 const char *jd_last_error(void);
 /* Library version string. */

@@ -17,6 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libjdmi.so")
 
 JD_OK, JD_ENOCONV, JD_EINVAL, JD_ENOMEM, JD_EDEVICE, JD_ESETUP, JD_ENOTIMPL = 0, 1, -1, -2, -3, -4, -5
 JD_FP64, JD_MIXED, JD_MIXED_FACTORS = 0, 1, 2
+JD_BC_PERIODIC, JD_BC_HARDWALL = 0, 1
+_BC = {"periodic": JD_BC_PERIODIC, "hardwall": JD_BC_HARDWALL, JD_BC_PERIODIC: JD_BC_PERIODIC,
+       JD_BC_HARDWALL: JD_BC_HARDWALL}
 JD_FLAG_GRAPHS = 1
 JD_FLAG_LEVELS = 2
 _PREC = {"fp64": JD_FP64, "mixed": JD_MIXED, "mixed_factors": JD_MIXED_FACTORS, JD_FP64: JD_FP64,
@@ -34,12 +37,14 @@ class Options(ctypes.Structure):
                 ("agg_tau", ctypes.c_double), ("schur_tol", ctypes.c_double), ("coarse_max", ctypes.c_int),
                 ("max_levels", ctypes.c_int), ("z_drop", ctypes.c_double), ("jmin", ctypes.c_int), ("jmax", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int), ("switch_tol", ctypes.c_double),
-                ("flags", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("flags", ctypes.c_int), ("z_parts", ctypes.c_int), ("bc", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
 
 
 class Request(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int), ("W", ctypes.c_double), ("seed", ctypes.c_uint64), ("sigma", ctypes.c_double),
-                ("k", ctypes.c_int), ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("flags", ctypes.c_int)]
+                ("k", ctypes.c_int), ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("flags", ctypes.c_int),
+                ("bc", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -69,10 +74,11 @@ class Info(ctypes.Structure):
 
 EXPORTS = ["jd_solve", "jd_setup", "jd_problem_solve", "jd_problem_info", "jd_problem_set_precision", "jd_problem_set_solve_options", "jd_problem_free", "jd_gen_diag",
            "jd_stencil_spmv", "jd_precond_create", "jd_precond_apply", "jd_precond_levels", "jd_precond_free", "jd_problem_precond", "jd_precond_factor_nnz",
-           "jd_precond_factor_product",
+           "jd_precond_factor_product", "jd_precond_segments",
            "jd_problem_linear_solve", "jd_last_error", "jd_version", "jd_server_create", "jd_server_submit",
            "jd_server_poll", "jd_server_wait", "jd_server_footprint", "jd_server_destroy",
-           "jd_host_matching", "jd_host_split_cycles", "jd_host_factor"]
+           "jd_host_matching", "jd_host_split_cycles", "jd_host_factor", "jd_set_allocator",
+           "jd_problem_lanczos"]
 
 _lib = None
 
@@ -91,12 +97,13 @@ def lib():
         "jd_solve": (I, [I, D, U64, D, I, D, P, P, P, OP, IP]),
         "jd_setup": (I, [I, D, U64, D, OP, ctypes.POINTER(P)]),
         "jd_problem_solve": (I, [P, I, D, P, P, P, P, IP]),
+        "jd_problem_lanczos": (I, [P, I, D, D, P, P, P, IP]),
         "jd_problem_info": (I, [P, IP]),
         "jd_problem_set_precision": (I, [P, I]),
         "jd_problem_set_solve_options": (I, [P, OP]),
         "jd_problem_free": (None, [P]),
         "jd_gen_diag": (I, [I, D, U64, P, P, P]),
-        "jd_stencil_spmv": (I, [I, I, P, D, P, P, P]),
+        "jd_stencil_spmv": (I, [I, I, I, P, D, P, P, P]),
         "jd_precond_create": (I, [I, D, U64, D, OP, ctypes.POINTER(P)]),
         "jd_precond_apply": (I, [P, I, P, P, P]),
         "jd_precond_levels": (I, [P, I, P, P, P]),
@@ -104,6 +111,7 @@ def lib():
         "jd_problem_precond": (I, [P, ctypes.POINTER(P)]),
         "jd_precond_factor_nnz": (I, [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I)]),
         "jd_precond_factor_product": (I, [P, I, I, P, P, P]),
+        "jd_precond_segments": (I, [P, I, P, P, P]),
         "jd_problem_linear_solve": (I, [P, D, P, I, P, P, D, I, ctypes.POINTER(I)]),
         "jd_server_create": (I, [ctypes.c_size_t, I, I, ctypes.POINTER(P)]),
         "jd_server_submit": (I, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -111,6 +119,7 @@ def lib():
         "jd_server_wait": (I, [P, ctypes.c_uint64, ctypes.POINTER(Result)]),
         "jd_server_footprint": (ctypes.c_size_t, [ctypes.POINTER(Request)]),
         "jd_server_destroy": (None, [P]),
+        "jd_set_allocator": (I, [P, P, P]),
         "jd_last_error": (ctypes.c_char_p, []),
         "jd_version": (ctypes.c_char_p, []),
     }
@@ -133,7 +142,7 @@ def make_options(precision="fp64", stream=None, **kw):
     o.precision = _PREC[precision]
     for k, v in kw.items():
         if v is not None:
-            setattr(o, k, v)
+            setattr(o, k, _BC[v] if k == "bc" else v)
     if stream is not None:
         o.stream = ctypes.c_void_p(_stream_ptr(stream))
     return o
@@ -229,6 +238,17 @@ class Problem:
         _check(rc, allow_partial=True)
         return evals, (evecs.T if vectors else None), resid, dict(info.as_dict(), status=rc)
 
+    def lanczos(self, k, tol=1e-10, inner_tol=1e-10, vectors=False):
+        """jd_problem_lanczos: the same pairs by shift-and-invert Lanczos."""
+        evals = np.full(k, np.nan)
+        resid = np.full(k, np.nan)
+        evecs = np.empty((k, self.n)) if vectors else None
+        info = Info()
+        rc = lib().jd_problem_lanczos(self._h, k, float(tol), float(inner_tol), _host(evals), _host(evecs),
+                                      _host(resid), ctypes.byref(info))
+        _check(rc, allow_partial=True)
+        return evals, (evecs.T if vectors else None), resid, dict(info.as_dict(), status=rc)
+
     def linear_solve(self, shift, b, x, Q=None, rtol=1e-8, maxit=200):
         """Q: (n, p) device tensor of orthonormal columns (laid out column-major for the ABI)."""
         its = ctypes.c_int(0)
@@ -239,8 +259,8 @@ class Problem:
         qp = _dev(Qc, "torch.float64", self.n * p, "Q")
         bp = _dev(b, "torch.float64", self.n, "b")
         xp = _dev(x, "torch.float64", self.n, "x")
-        _check(lib().jd_problem_linear_solve(self._h, float(shift), qp, p, bp, xp, float(rtol),
-                                             int(maxit), ctypes.byref(its)))
+        _check(lib().jd_problem_linear_solve(self._h, float(shift), qp, p, bp, xp, float(rtol), int(maxit),
+                                             ctypes.byref(its)))
         return its.value
 
     def close(self):
@@ -274,10 +294,21 @@ class Precond:
         return nnz.value
 
     def factor_product(self, x, y, transpose=False, precision="mixed", stream=None):
+        """x = y = None: the timing form (the products on the workspace's values)."""
         pr = _PREC[precision]
         dt = _VEC_DTYPE.get(pr)
         _check(lib().jd_precond_factor_product(self._h, pr, int(transpose), _dev(x, dt, self.n, "x"),
                                                _dev(y, dt, self.n, "y"), _stream_ptr(stream)))
+
+    def segments(self, cap=64):
+        lb = np.zeros(cap, np.int32)
+        rows = np.zeros(cap, np.int32)
+        nnz = np.zeros(cap, np.int64)
+        ns = lib().jd_precond_segments(self._h, cap, _host(lb), _host(rows), _host(nnz))
+        if ns < 0:
+            _check(ns)
+        ns = min(ns, cap)
+        return dict(segments=ns, lev_begin=lb[:ns].tolist(), rows=rows[:ns].tolist(), nnz=nnz[:ns].tolist())
 
     def apply(self, x, y, precision="fp64", stream=None):
         pr = _PREC[precision]
@@ -315,16 +346,66 @@ def gen_diag(L, W, seed, eps64, eps32=None, stream=None):
                              _dev(eps32, "torch.float32", n, "eps32"), _stream_ptr(stream)))
 
 
-def stencil_spmv(L, eps, shift, x, y, precision="fp64", stream=None):
+def stencil_spmv(L, eps, shift, x, y, precision="fp64", stream=None, bc="periodic"):
     n = int(L) ** 3
     pr = _PREC[precision]
     dt = _VEC_DTYPE.get(pr)
-    _check(lib().jd_stencil_spmv(L, pr, _dev(eps, dt, n, "eps"), float(shift), _dev(x, dt, n, "x"),
+    _check(lib().jd_stencil_spmv(L, _BC[bc], pr, _dev(eps, dt, n, "eps"), float(shift), _dev(x, dt, n, "x"),
                                  _dev(y, dt, n, "y"), _stream_ptr(stream)))
 
 
 def version():
     return lib().jd_version().decode()
+
+
+# C signatures of jd_set_allocator's callbacks
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_allocator = None  # the installed callbacks (kept alive while the library may call them)
+_retired = []      # earlier callbacks: buffers obtained through them still return through them
+
+
+def set_allocator(alloc=None, free=None):
+    """jd_set_allocator with Python callables alloc(bytes, stream) -> int device pointer
+    (0 on failure) and free(ptr, stream); both None restores hipMalloc/hipFree.
+    The callables run on library threads too (serving workers) and must be thread-safe."""
+    global _allocator
+    if (alloc is None) != (free is None):
+        raise ValueError("alloc and free must be given together")
+    if alloc is None:
+        cb = (None, None)
+    else:
+        def _a(nbytes, stream, _ctx):
+            try:
+                return int(alloc(int(nbytes), int(stream or 0))) or None
+            except Exception:
+                return None
+
+        def _f(ptr, stream, _ctx):
+            free(int(ptr), int(stream or 0))
+        cb = (ALLOC_FN(_a), FREE_FN(_f))
+    _check(lib().jd_set_allocator(ctypes.cast(cb[0], ctypes.c_void_p) if cb[0] else None,
+                                  ctypes.cast(cb[1], ctypes.c_void_p) if cb[1] else None, None))
+    if _allocator is not None:
+        _retired.append(_allocator)
+    _allocator = cb if cb[0] else None
+
+
+def use_torch_allocator(enable=True):
+    """Route the library's device memory through PyTorch's caching allocator
+    (torch.cuda.caching_allocator_alloc / caching_allocator_delete), on the stream the
+    library's work uses; enable=False restores hipMalloc/hipFree."""
+    if not enable:
+        set_allocator(None, None)
+        return
+    import torch
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+
+    def free(ptr, _stream):
+        torch.cuda.caching_allocator_delete(ptr)
+    set_allocator(alloc, free)
 
 
 class Server:
@@ -336,8 +417,9 @@ class Server:
         self._h = h
 
     @staticmethod
-    def request(L, W, seed, sigma, k, tol=1e-10, precision="mixed", flags=0):
-        return Request(int(L), float(W), int(seed), float(sigma), int(k), float(tol), _PREC[precision], int(flags))
+    def request(L, W, seed, sigma, k, tol=1e-10, precision="mixed", flags=0, bc="periodic"):
+        return Request(int(L), float(W), int(seed), float(sigma), int(k), float(tol), _PREC[precision], int(flags),
+                       _BC[bc])
 
     def submit(self, req):
         t = ctypes.c_uint64()

@@ -61,19 +61,46 @@ std::mutex &dev_mutex()
     return m;
 }
 
-// Device allocation list owned by a handle.
+// Source of device memory: the caller's allocator (jd_set_allocator) or hipMalloc.
+// Read and replaced under dev_mutex; every block remembers the allocator it came from.
+struct Allocator {
+    void *(*alloc)(size_t, void *, void *) = nullptr;
+    void (*free_)(void *, void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+Allocator g_alloc;
+
+// Device allocation list owned by a handle.  `stream` is the stream whose work uses the
+// memory: it is handed to a caller's allocator, and synchronised before such memory is
+// given back (a caching allocator may hand the block out again at once).
 struct DevMem {
-    std::vector<void *> ptrs;
+    struct Block {
+        void *p;
+        Allocator from;
+    };
+    std::vector<Block> blocks;
     size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    DevMem() = default;
+    explicit DevMem(hipStream_t s) : stream(s) {}
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
     template <typename T>
     T *alloc(size_t count)
     {
         if (count == 0) count = 1;
+        const size_t nb = count * sizeof(T);
         void *p = nullptr;
         std::lock_guard<std::mutex> g(dev_mutex());
-        HIPCHK(hipMalloc(&p, count * sizeof(T)));
-        ptrs.push_back(p);
-        bytes += count * sizeof(T);
+        const Allocator a = g_alloc;
+        if (a.alloc) {
+            p = a.alloc(nb, static_cast<void *>(stream), a.ctx);
+            if (!p) throw JdError(JD_ENOMEM, "the caller's allocator returned no memory for " + std::to_string(nb) + " bytes");
+        } else {
+            HIPCHK(hipMalloc(&p, nb));
+        }
+        blocks.push_back({p, a});
+        bytes += nb;
         return static_cast<T *>(p);
     }
     // The copy is ordered on s, the stream whose kernels read the buffer: a copy on
@@ -90,11 +117,17 @@ struct DevMem {
         }
         return p;
     }
-    void release()
+    void release() noexcept
     {
+        bool caller = false;
+        for (const Block &b : blocks) caller |= b.from.alloc != nullptr;
+        if (caller) (void)hipStreamSynchronize(stream);
         std::lock_guard<std::mutex> g(dev_mutex());
-        for (void *p : ptrs) (void)hipFree(p);
-        ptrs.clear();
+        for (const Block &b : blocks) {
+            if (b.from.alloc) b.from.free_(b.p, static_cast<void *>(stream), b.from.ctx);
+            else (void)hipFree(b.p);
+        }
+        blocks.clear();
         bytes = 0;
     }
     ~DevMem() { release(); }
@@ -115,13 +148,14 @@ struct DevPrecond {
     int coarse_off = 0, coarse_n = 0;
     T *cinv = nullptr;
     int cld = 0;  // row stride of cinv: coarse_n rounded up to a multiple of kCoarseAlign
-    T *w = nullptr, *x = nullptr;  // workspaces
-    // explicit inverse factor form
+    T *w = nullptr, *x = nullptr;  // workspaces of the level-by-level form
+    // inverse factor form (segments Z_0 .. Z_{S-1}, see jdmi::InverseFactor)
     bool inv = false;
     const int *site_of = nullptr, *cidx = nullptr, *dp = nullptr;
     const T *dd = nullptr, *dof = nullptr;
     T *yc = nullptr;
-    jdmi::Hyb<T> zh, zth;   // hybrid layout (long rows per wave + sliced ELL)
+    T *buf = nullptr;                      // 3 n values: the regions the products address
+    std::vector<jdmi::Hyb<T>> zdown, zup;  // layouts of Z_s and Z_s^T
 
     static jdmi::Hyb<T> upload_hyb(const jdmi::HybHost &h, DevMem &mem, hipStream_t s)
     {
@@ -144,13 +178,12 @@ struct DevPrecond {
         return d;
     }
 
-    void upload(const jdmi::Multilevel &ml, const int *dperm, DevMem &mem, hipStream_t s,
-                const jdmi::HybHost *zsh = nullptr, const jdmi::HybHost *ztsh = nullptr)
+    void upload(const jdmi::Multilevel &ml, const int *dperm, DevMem &mem, hipStream_t s)
     {
         n = ml.n;
         perm = const_cast<int *>(dperm);
         levels.clear();
-        inv = !ml.z.ptr.empty();
+        inv = !ml.z.seg.empty();
         // the level-by-level factors are needed on the device only without Z
         for (const auto &L : ml.levels) {
             if (inv) break;
@@ -179,9 +212,8 @@ struct DevPrecond {
                     padded[size_t(i) * cld + j] = T(ml.coarse_inv[size_t(i) * ml.coarse_n + j]);
             cinv = mem.upload(padded, s);
         }
-        w = mem.alloc<T>(n);
-        x = mem.alloc<T>(n);
         if (inv) {
+            buf = mem.alloc<T>(3 * size_t(n));
             site_of = mem.upload(ml.z.site_of, s);
             cidx = mem.upload(ml.z.coarse_idx, s);
             yc = mem.alloc<T>(std::max(cld, 1));
@@ -189,8 +221,15 @@ struct DevPrecond {
             dd = mem.upload(cast_vec<T>(ml.z.dd), s);
             dof = mem.upload(cast_vec<T>(ml.z.dof), s);
             dp = mem.upload(ml.z.dp, s);
-            zh = upload_hyb(*zsh, mem, s);
-            zth = upload_hyb(*ztsh, mem, s);
+            zdown.clear();
+            zup.clear();
+            for (const auto &seg : ml.z.seg) {
+                zdown.push_back(upload_hyb(seg.down, mem, s));
+                zup.push_back(upload_hyb(seg.up, mem, s));
+            }
+        } else {
+            w = mem.alloc<T>(n);
+            x = mem.alloc<T>(n);
         }
         // keep the converted host vectors alive until the copies are done
         HIPCHK(hipStreamSynchronize(s));
@@ -200,13 +239,15 @@ struct DevPrecond {
     void apply(const T *in, T *out, hipStream_t s, const int *skip = nullptr) const
     {
         if (inv) {
-            // P^T Z^T D^{-1} Z P in: gather, sparse product, block diagonal (+ exact last
-            // level), transposed sparse product with the inverse permutation on output
-            jdmi::launch_gather<T>(n, site_of, in, w, s, skip);
-            jdmi::launch_hyb_spmv<T, T>(zh, w, x, nullptr, s, skip);
-            jdmi::launch_dinv<T>(n, dd, dof, dp, x, w, s, skip);
-            jdmi::launch_coarse_idx<T>(coarse_n, cld, cidx, cinv, x, yc, w, s, skip);
-            jdmi::launch_hyb_spmv<T, T>(zth, w, out, site_of, s, skip);
+            // gather into region 2, Z_0 .. Z_{S-1}, block diagonal and last level
+            // (region 0 -> 1), Z_{S-1}^T .. Z_1^T, Z_0^T with the output permutation
+            T *r1 = buf + size_t(n), *r2 = buf + 2 * size_t(n);
+            jdmi::launch_gather<T>(n, site_of, in, r2, s, skip);
+            for (const auto &z : zdown) jdmi::launch_hyb_spmv<T, T>(z, buf, buf, nullptr, s, skip);
+            jdmi::launch_dinv<T>(n, dd, dof, dp, buf, r1, s, skip);
+            jdmi::launch_coarse_idx<T>(coarse_n, cld, cidx, cinv, buf, yc, r1, s, skip);
+            for (int i = int(zup.size()) - 1; i >= 1; --i) jdmi::launch_hyb_spmv<T, T>(zup[i], buf, buf, nullptr, s, skip);
+            jdmi::launch_hyb_spmv<T, T>(zup[0], buf, out, site_of, s, skip);
             return;
         }
         jdmi::launch_gather<T>(n, perm, in, w, s, skip);
@@ -227,16 +268,21 @@ struct MixedPrecond {
     void apply(const double *in, double *out, hipStream_t s, const int *skip = nullptr) const
     {
         if (!pc.inv) throw JdError(JD_ENOTIMPL, "binary32 factors with binary64 vectors need the inverse factor form");
-        jdmi::launch_gather<double>(pd.n, pd.site_of, in, pd.w, s, skip);
-        jdmi::launch_hyb_spmv<float, double>(pc.zh, pd.w, pd.x, nullptr, s, skip);
-        jdmi::launch_dinv<double>(pd.n, pd.dd, pd.dof, pd.dp, pd.x, pd.w, s, skip);
-        jdmi::launch_coarse_idx<double>(pd.coarse_n, pd.cld, pd.cidx, pd.cinv, pd.x, pd.yc, pd.w, s, skip);
-        jdmi::launch_hyb_spmv<float, double>(pc.zth, pd.w, out, pd.site_of, s, skip);
+        const int n = pd.n;
+        double *buf = pd.buf, *r1 = buf + size_t(n), *r2 = buf + 2 * size_t(n);
+        jdmi::launch_gather<double>(n, pd.site_of, in, r2, s, skip);
+        for (const auto &z : pc.zdown) jdmi::launch_hyb_spmv<float, double>(z, buf, buf, nullptr, s, skip);
+        jdmi::launch_dinv<double>(n, pd.dd, pd.dof, pd.dp, buf, r1, s, skip);
+        jdmi::launch_coarse_idx<double>(pd.coarse_n, pd.cld, pd.cidx, pd.cinv, buf, pd.yc, r1, s, skip);
+        for (int i = int(pc.zup.size()) - 1; i >= 1; --i)
+            jdmi::launch_hyb_spmv<float, double>(pc.zup[i], buf, buf, nullptr, s, skip);
+        jdmi::launch_hyb_spmv<float, double>(pc.zup[0], buf, out, pd.site_of, s, skip);
     }
 };
 
 struct Setup {
     int L = 0, n = 0;
+    int bc = JD_BC_PERIODIC;
     double W = 0, sigma = 0;
     uint64_t seed = 0;
     jd_options opt{};
@@ -306,6 +352,8 @@ void check_problem_args(int L, double W, double sigma, const jd_options *opt)
         check_search_space(opt->jmin, opt->jmax);
         if (opt->max_inner < 0 || opt->max_outer < 0 || opt->max_levels < 0) throw JdError(JD_EINVAL, "negative iteration cap");
         if (opt->flags & ~(JD_FLAG_GRAPHS | JD_FLAG_LEVELS)) throw JdError(JD_EINVAL, "unknown flag bits");
+        if (opt->bc != JD_BC_PERIODIC && opt->bc != JD_BC_HARDWALL) throw JdError(JD_EINVAL, "unknown boundary condition");
+        if (opt->z_parts < 0 || opt->z_parts > 32) throw JdError(JD_EINVAL, "z_parts must be in [0, 32]");
         if (!std::isfinite(opt->z_drop)) throw JdError(JD_EINVAL, "non-finite option");
         if (!std::isfinite(opt->drop_tol) || !std::isfinite(opt->kappa) || opt->kappa < 0 ||
             !std::isfinite(opt->agg_tau) || !std::isfinite(opt->schur_tol) || !std::isfinite(opt->switch_tol))
@@ -320,7 +368,7 @@ void invert_coarse_on_device(Setup &S)
     jdmi::Multilevel &ml = S.ml;
     const int nc = ml.coarse_n;
     if (nc == 0 || !ml.coarse_inv.empty()) return;
-    DevMem tmp;
+    DevMem tmp(S.stream);
     double *a = tmp.upload(ml.coarse_mat, S.stream);
     double *inv = tmp.alloc<double>(size_t(nc) * nc);
     double *colc = tmp.alloc<double>(nc);
@@ -359,6 +407,7 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
         HIPCHK(hipStreamCreate(&S.stream));
         S.own_stream = true;
     }
+    S.mem.stream = S.stream;
     const int n = S.n;
     S.eps64 = S.mem.alloc<double>(n);
     S.eps32 = S.mem.alloc<float>(n);
@@ -367,10 +416,20 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
     std::vector<double> eps(n);
     HIPCHK(hipMemcpyAsync(eps.data(), S.eps64, n * sizeof(double), hipMemcpyDeviceToHost, S.stream));
     HIPCHK(hipStreamSynchronize(S.stream));
-    double emax = 0;
-    for (double e : eps) emax = std::max(emax, std::fabs(e));
-    S.anorm = 6.0 + emax;
-    jdmi::Csr A = jdmi::anderson_shifted(L, eps.data(), sigma);
+    // ||A||_inf: the largest row sum, couplings (6 on the torus; fewer on the faces of a
+    // box with hard walls) plus |eps|
+    S.bc = S.opt.bc;
+    double anorm = 0;
+    for (int s = 0; s < n; ++s) {
+        int deg = 6;
+        if (S.bc == JD_BC_HARDWALL) {
+            const int i = s % L, j = (s / L) % L, k = s / (L * L);
+            deg = (i > 0) + (i < L - 1) + (j > 0) + (j < L - 1) + (k > 0) + (k < L - 1);
+        }
+        anorm = std::max(anorm, deg + std::fabs(eps[s]));
+    }
+    S.anorm = anorm;
+    jdmi::Csr A = jdmi::anderson_shifted(L, eps.data(), sigma, S.bc);
     jdmi::SetupParams prm;
     prm.drop_tol = S.opt.drop_tol;
     prm.kappa = S.opt.kappa;
@@ -379,6 +438,7 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
     prm.coarse_max = S.opt.coarse_max;
     prm.max_levels = S.opt.max_levels;
     prm.z_drop = S.opt.z_drop;
+    prm.z_parts = S.opt.z_parts;
     prm.inverse_factor = (S.opt.flags & JD_FLAG_LEVELS) == 0;
     prm.host_coarse_inverse = false;
     std::string err = jdmi::build_multilevel(A, prm, S.ml);
@@ -387,13 +447,8 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
     S.n2x2 = 0;
     for (auto &lv : S.ml.levels) S.n2x2 += lv.n2x2;
     int *dperm = S.mem.upload(S.ml.perm, S.stream);
-    jdmi::HybHost zsh, ztsh;
-    if (!S.ml.z.ptr.empty()) {
-        zsh = jdmi::to_hyb(S.n, S.ml.z.ptr.data(), S.ml.z.col.data(), S.ml.z.val.data());
-        ztsh = jdmi::to_hyb(S.n, S.ml.z.tptr.data(), S.ml.z.tcol.data(), S.ml.z.tval.data());
-    }
-    S.pc64.upload(S.ml, dperm, S.mem, S.stream, &zsh, &ztsh);
-    S.pc32.upload(S.ml, dperm, S.mem, S.stream, &zsh, &ztsh);
+    S.pc64.upload(S.ml, dperm, S.mem, S.stream);
+    S.pc32.upload(S.ml, dperm, S.mem, S.stream);
     HIPCHK(hipStreamSynchronize(S.stream));
     S.setup_s = now_s() - t0;
 }
@@ -445,10 +500,11 @@ void small_symeig(int m, std::vector<double> H /* m*m col-major */, std::vector<
     for (int i = 0; i < m; ++i) w[i] = at(i, i);
 }
 
-bool small_inverse(int p, std::vector<double> &A /* p*p col-major, overwritten by inverse */)
+// In place: A (p x p column-major) is overwritten by its inverse; I is p*p workspace.
+bool small_inverse(int p, double *A, double *I)
 {
-    std::vector<double> I(size_t(p) * p, 0.0);
-    for (int i = 0; i < p; ++i) I[i + size_t(i) * p] = 1.0;
+    for (int j = 0; j < p; ++j)
+        for (int i = 0; i < p; ++i) I[i + size_t(j) * p] = i == j ? 1.0 : 0.0;
     auto a = [&](int i, int j) -> double & { return A[i + size_t(j) * p]; };
     auto b = [&](int i, int j) -> double & { return I[i + size_t(j) * p]; };
     for (int c = 0; c < p; ++c) {
@@ -466,8 +522,14 @@ bool small_inverse(int p, std::vector<double> &A /* p*p col-major, overwritten b
             for (int k = 0; k < p; ++k) { a(r, k) -= f * a(c, k); b(r, k) -= f * b(c, k); }
         }
     }
-    A.swap(I);
+    std::copy(I, I + size_t(p) * p, A);
     return true;
+}
+
+bool small_inverse(int p, std::vector<double> &A /* p*p col-major, overwritten by inverse */)
+{
+    std::vector<double> I(size_t(p) * p);
+    return small_inverse(p, A.data(), I.data());
 }
 
 // Work buffers of one solve.
@@ -498,7 +560,7 @@ struct Solver {
     std::vector<Pair> cache;
 
     Solver(Setup &S_, const P &pc_, const T *eps_, bool graphs_)
-        : S(S_), pc(pc_), eps(eps_), s(S_.stream), n(S_.n), graphs(graphs_)
+        : S(S_), pc(pc_), eps(eps_), s(S_.stream), n(S_.n), graphs(graphs_), mem(S_.stream)
     {
         B.r = mem.alloc<T>(n);
         B.q = mem.alloc<T>(n);
@@ -547,7 +609,7 @@ struct Solver {
         const int *skip_a = &B.st->done;
         const int *skip_b = &B.st->done_next;
         // t = (I - Qt Qt^T)(A - shift I) q
-        jdmi::launch_stencil_state<T>(S.L, eps, B.st, B.q, B.t, s);
+        jdmi::launch_stencil_state<T>(S.L, S.bc, eps, B.st, B.q, B.t, s);
         if (p > 0) {
             jdmi::launch_multidot<T>(n, p, Qt, n, B.t, B.partial, B.coef, s, skip_a);
             jdmi::launch_sub_qc<T>(n, p, Qt, n, B.coef, B.t, s, skip_a);
@@ -645,6 +707,80 @@ struct Outputs {
     void *evecs_device;
 };
 
+// The nq pairs (Q: n x nq on the device, lam) as outputs: sorted by (|lambda - sigma|,
+// lambda), residuals from a fresh binary64 product, eigenvectors with the sign
+// convention (largest-modulus component positive, lowest index on ties); NaN past nq.
+// Au, partial, red: device work space (n, reduction partials, 1 value).
+void emit_outputs(Setup &S, const double *Q, const std::vector<double> &lam, int nq, int k, Outputs out, double *Au,
+                  double *partial, double *red)
+{
+    const int n = S.n;
+    hipStream_t s = S.stream;
+    auto d2h = [&](double *h, const double *d, size_t cnt) {
+        HIPCHK(hipMemcpyAsync(h, d, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    };
+    const double sigma = S.sigma;
+    std::vector<int> idx(nq);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+        const double da = std::fabs(lam[a] - sigma), db = std::fabs(lam[b] - sigma);
+        return da != db ? da < db : lam[a] < lam[b];
+    });
+    std::vector<double> hostQ;
+    const bool want_vec = out.evecs_host || out.evecs_device;
+    if (want_vec) {
+        hostQ.resize(size_t(n) * std::max(nq, 1));
+        if (nq > 0) d2h(hostQ.data(), Q, size_t(n) * nq);
+    }
+    for (int c = 0; c < k; ++c) {
+        if (c >= nq) {
+            out.evals[c] = std::nan("");
+            if (out.resid) out.resid[c] = std::nan("");
+            continue;
+        }
+        const int q = idx[c];
+        out.evals[c] = lam[q];
+        if (out.resid) {
+            jdmi::launch_stencil<double>(S.L, S.bc, S.eps64, 0.0, Q + size_t(q) * n, Au, s);
+            jdmi::launch_axpby_d(n, -lam[q], Q + size_t(q) * n, 1.0, Au, s);
+            jdmi::launch_dot<double>(n, Au, Au, partial, red, s);
+            double rr;
+            d2h(&rr, red, 1);
+            out.resid[c] = std::sqrt(std::max(rr, 0.0)) / S.anorm;
+        }
+    }
+    if (want_vec) {
+        std::vector<double> col(n);
+        for (int c = 0; c < std::min(k, nq); ++c) {
+            const double *src = &hostQ[size_t(idx[c]) * n];
+            int imax = 0;
+            for (int i = 1; i < n; ++i)
+                if (std::fabs(src[i]) > std::fabs(src[imax])) imax = i;
+            const double sg = src[imax] < 0 ? -1.0 : 1.0;
+            for (int i = 0; i < n; ++i) col[i] = sg * src[i];
+            if (out.evecs_host) std::memcpy(out.evecs_host + size_t(c) * n, col.data(), n * sizeof(double));
+            if (out.evecs_device)
+                HIPCHK(hipMemcpyAsync(static_cast<double *>(out.evecs_device) + size_t(c) * n, col.data(),
+                                      n * sizeof(double), hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        for (int c = nq; c < k; ++c) {
+            if (out.evecs_host) std::fill(out.evecs_host + size_t(c) * n, out.evecs_host + size_t(c + 1) * n, std::nan(""));
+        }
+    }
+}
+
+void fill_setup_info(const Setup &S, jd_info *info)
+{
+    info->setup_s = S.setup_s;
+    info->levels = int(S.ml.levels.size());
+    info->n_2x2 = S.n2x2;
+    info->coarse_n = S.ml.coarse_n;
+    info->fill = S.ml.fill;
+    info->anorm = S.anorm;
+}
+
 template <typename T, typename P>
 int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, jd_info *info)
 {
@@ -670,7 +806,7 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
     const double sigma = S.sigma;
 
     Solver<T, P> sv(S, pc, eps, (o.flags & JD_FLAG_GRAPHS) != 0);
-    DevMem mem;
+    DevMem mem(s);
     double *V = mem.alloc<double>(size_t(n) * jmax);
     double *AV = mem.alloc<double>(size_t(n) * jmax);
     double *V2 = mem.alloc<double>(size_t(n) * jmax);  // restart / deflation target
@@ -729,7 +865,7 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
         }
         jdmi::launch_scale_by_inv_sqrt(n, red, t64, s);
         HIPCHK(hipMemcpyAsync(V + size_t(m) * n, t64, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        jdmi::launch_stencil<double>(S.L, S.eps64, 0.0, V + size_t(m) * n, AV + size_t(m) * n, s);
+        jdmi::launch_stencil<double>(S.L, S.bc, S.eps64, 0.0, V + size_t(m) * n, AV + size_t(m) * n, s);
         jdmi::launch_multidot<double>(n, m + 1, V, n, AV + size_t(m) * n, partial, red, s);
         d2h(hcol.data(), red, m + 1);
         for (int i = 0; i <= m; ++i) {
@@ -768,7 +904,7 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
             bool locked = false;
             if (rnorm <= tol * anorm) {
                 // acceptance on a freshly computed residual and Rayleigh quotient
-                jdmi::launch_stencil<double>(S.L, S.eps64, 0.0, u64, Au64, s);
+                jdmi::launch_stencil<double>(S.L, S.bc, S.eps64, 0.0, u64, Au64, s);
                 jdmi::launch_dot<double>(n, u64, Au64, partial, red, s);
                 jdmi::launch_dot<double>(n, u64, u64, partial, red + 1, s);
                 double q2[2];
@@ -862,69 +998,201 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
     HIPCHK(hipGetLastError());
     const double solve_s = now_s() - t0;
 
-    // ---- outputs: sorted pairs, residuals from a fresh product, sign convention ----
-    std::vector<int> idx(nq);
-    std::iota(idx.begin(), idx.end(), 0);
-    std::sort(idx.begin(), idx.end(), [&](int a, int b) {
-        const double da = std::fabs(lam[a] - sigma), db = std::fabs(lam[b] - sigma);
-        return da != db ? da < db : lam[a] < lam[b];
-    });
-    std::vector<double> hostQ;
-    const bool want_vec = out.evecs_host || out.evecs_device;
-    if (want_vec) {
-        hostQ.resize(size_t(n) * std::max(nq, 1));
-        if (nq > 0) d2h(hostQ.data(), Q, size_t(n) * nq);
-    }
-    for (int c = 0; c < k; ++c) {
-        if (c >= nq) {
-            out.evals[c] = std::nan("");
-            if (out.resid) out.resid[c] = std::nan("");
-            continue;
-        }
-        const int q = idx[c];
-        out.evals[c] = lam[q];
-        if (out.resid) {
-            jdmi::launch_stencil<double>(S.L, S.eps64, 0.0, Q + size_t(q) * n, Au64, s);
-            jdmi::launch_axpby_d(n, -lam[q], Q + size_t(q) * n, 1.0, Au64, s);
-            jdmi::launch_dot<double>(n, Au64, Au64, partial, red, s);
-            double rr;
-            d2h(&rr, red, 1);
-            out.resid[c] = std::sqrt(std::max(rr, 0.0)) / anorm;
-        }
-    }
-    if (want_vec) {
-        std::vector<double> col(n);
-        for (int c = 0; c < std::min(k, nq); ++c) {
-            const double *src = &hostQ[size_t(idx[c]) * n];
-            int imax = 0;
-            for (int i = 1; i < n; ++i)
-                if (std::fabs(src[i]) > std::fabs(src[imax])) imax = i;
-            const double sg = src[imax] < 0 ? -1.0 : 1.0;
-            for (int i = 0; i < n; ++i) col[i] = sg * src[i];
-            if (out.evecs_host) std::memcpy(out.evecs_host + size_t(c) * n, col.data(), n * sizeof(double));
-            if (out.evecs_device)
-                HIPCHK(hipMemcpyAsync(static_cast<double *>(out.evecs_device) + size_t(c) * n, col.data(),
-                                      n * sizeof(double), hipMemcpyHostToDevice, s));
-            HIPCHK(hipStreamSynchronize(s));
-        }
-        for (int c = nq; c < k; ++c) {
-            if (out.evecs_host) std::fill(out.evecs_host + size_t(c) * n, out.evecs_host + size_t(c + 1) * n, std::nan(""));
-        }
-    }
+    emit_outputs(S, Q, lam, nq, k, out, Au64, partial, red);
     if (info) {
         info->n_converged = nq;
         info->outer_its = outer;
         info->inner_its = inner_total;
         info->solve_s = solve_s;
-        info->setup_s = S.setup_s;
-        info->levels = int(S.ml.levels.size());
-        info->n_2x2 = S.n2x2;
-        info->coarse_n = S.ml.coarse_n;
-        info->fill = S.ml.fill;
-        info->anorm = anorm;
+        fill_setup_info(S, info);
         info->device_bytes = S.mem.bytes + mem.bytes + sv.mem.bytes;
     }
     return nq == k ? JD_OK : JD_ENOCONV;
+}
+
+// Shift-and-invert Lanczos (section 4.1): Lanczos on (A - sigma I)^{-1}, each product an
+// SQMR solve of (A - sigma I) w = v with the multilevel preconditioner, stopped when the
+// quasi-residual bound reaches inner_tol ||v|| (section 8.2 uses 1e-10); full
+// reorthogonalisation (classical Gram-Schmidt twice, binary64); restarted by keeping the
+// wanted Ritz vectors (a thick restart: in exact arithmetic the same subspace as the
+// implicitly shifted QR restart of section 4.1); a Ritz pair is accepted on a freshly
+// computed residual of A and its Rayleigh quotient.  Binary64 vectors only: the inner
+// solves must reach inner_tol.
+template <typename P>
+int si_lanczos_run(Setup &S, const P &pc, int k, double tol, double inner_tol, Outputs out, jd_info *info)
+{
+    const double t0 = now_s();
+    const int n = S.n;
+    hipStream_t s = S.stream;
+    const jd_options &o = S.opt;
+    int mmax = o.jmax > 0 ? o.jmax : std::min(std::max(2 * (k + 5), k + 25), 120);
+    const bool whole = n <= mmax;  // the Krylov space can grow to the whole space
+    if (whole) mmax = n;
+    const int keep = whole ? mmax : std::min(k + std::max(5, k / 2), mmax - 2);
+    if (!whole && keep < k) throw JdError(JD_EINVAL, "jmax too small for k wanted Ritz vectors plus a restart margin");
+    const int max_steps = o.max_outer > 0 ? o.max_outer : 60 * k + 200;
+    const int max_inner = o.max_inner > 0 ? o.max_inner : 1000;
+    const double anorm = S.anorm;
+    const double shift_norm = anorm + std::fabs(S.sigma);  // >= ||A - sigma I||_inf
+    Solver<double, P> sv(S, pc, S.eps64, false);
+    DevMem mem(s);
+    const int ld = mmax + 1;
+    double *V = mem.alloc<double>(size_t(n) * ld);
+    double *V2 = mem.alloc<double>(size_t(n) * ld);
+    double *Q = mem.alloc<double>(size_t(n) * k);
+    double *Au = mem.alloc<double>(n);
+    double *r64 = mem.alloc<double>(n);
+    double *dsm = mem.alloc<double>(size_t(ld) * ld);
+    double *red = mem.alloc<double>(256);
+    double *partial = sv.B.partial;
+    auto d2h = [&](double *h, const double *d, size_t cnt) {
+        HIPCHK(hipMemcpyAsync(h, d, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    };
+    auto h2d = [&](double *d, const double *h, size_t cnt) {
+        HIPCHK(hipMemcpyAsync(d, h, cnt * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    };
+    // x <- x / ||x||, orthogonalised first against the first `cols` columns of V
+    auto orth_normalise = [&](double *x, int cols, double *coef) {
+        for (int pass = 0; pass < 2; ++pass)
+            if (cols > 0) {
+                jdmi::launch_multidot<double>(n, cols, V, n, x, partial, red, s);
+                if (coef) {
+                    double hc[128];
+                    d2h(hc, red, cols);
+                    for (int i = 0; i < cols; ++i) coef[i] += hc[i];
+                }
+                jdmi::launch_sub_qc<double>(n, cols, V, n, red, x, s);
+            }
+        jdmi::launch_dot<double>(n, x, x, partial, red, s);
+        double nn;
+        d2h(&nn, red, 1);
+        return std::sqrt(std::max(nn, 0.0));
+    };
+    std::vector<double> H(size_t(ld) * ld, 0.0);
+    auto Hat = [&](int i, int j) -> double & { return H[i + size_t(j) * ld]; };
+    jdmi::launch_random_vector(n, S.seed ^ 0x2545F4914F6CDD1Dull, V, s);
+    {
+        const double nv = orth_normalise(V, 0, nullptr);
+        jdmi::launch_convert<double, double>(n, V, V, 1.0 / nv, s);
+    }
+    int m = 0, steps = 0, inner_total = 0, nconv = 0, fresh = 0;
+    std::vector<double> lam(k, 0.0), hw, hZ;
+    while (steps < max_steps && nconv < k) {
+        // w = (A - sigma I)^{-1} v_m by preconditioned SQMR
+        jdmi::launch_copy<double>(n, V + size_t(m) * n, sv.B.b, s);
+        inner_total += sv.sqmr(S.sigma, nullptr, nullptr, 0, nullptr, inner_tol, max_inner);
+        ++steps;
+        double *w = sv.B.x;
+        double h[128] = {0.0};
+        const double beta = orth_normalise(w, m + 1, h);
+        for (int i = 0; i <= m; ++i) Hat(i, m) = h[i];
+        double hnorm = 0;
+        for (int i = 0; i <= m; ++i) hnorm = std::max(hnorm, std::fabs(h[i]));
+        ++m;
+        bool breakdown = !(beta > 1e-13 * std::max(hnorm, 1e-300)) || !std::isfinite(beta);
+        if (m < mmax || whole) {
+            if (!breakdown && m < ld) {
+                Hat(m, m - 1) = beta;
+                jdmi::launch_convert<double, double>(n, w, V + size_t(m) * n, 1.0 / beta, s);
+            } else if (m < mmax) {
+                // invariant subspace: continue from a fresh direction orthogonal to V
+                Hat(m, m - 1) = 0.0;
+                jdmi::launch_random_vector(n, S.seed + 7919ull * uint64_t(++fresh), V + size_t(m) * n, s);
+                const double nv = orth_normalise(V + size_t(m) * n, m, nullptr);
+                jdmi::launch_convert<double, double>(n, V + size_t(m) * n, V + size_t(m) * n, 1.0 / nv, s);
+            }
+        } else {
+            Hat(m, m - 1) = breakdown ? 0.0 : beta;
+            if (!breakdown) jdmi::launch_convert<double, double>(n, w, V + size_t(m) * n, 1.0 / beta, s);
+        }
+        const bool check = breakdown || m == mmax || (m >= std::min(keep, mmax) && m % 5 == 0);
+        if (!check) continue;
+        // Ritz pairs of the symmetrised projection; the wanted ones have the largest |mu|
+        std::vector<double> Hm(size_t(m) * m);
+        for (int j = 0; j < m; ++j)
+            for (int i = 0; i < m; ++i) Hm[i + size_t(j) * m] = 0.5 * (Hat(i, j) + Hat(j, i));
+        small_symeig(m, Hm, hw, hZ);
+        std::vector<int> ord(m);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+            return std::fabs(hw[a]) != std::fabs(hw[b]) ? std::fabs(hw[a]) > std::fabs(hw[b]) : hw[a] > hw[b];
+        });
+        const int want = std::min(k, m);
+        const double bcur = Hat(std::min(m, mmax), m - 1);
+        // ||A u - lambda u|| <= ||A - sigma I|| |beta z_m| / |mu| for an exact inverse
+        bool all = want == k;
+        for (int c = 0; c < want && all; ++c) {
+            const int i = ord[c];
+            if (hw[i] == 0.0) { all = false; break; }
+            const double est = shift_norm * std::fabs(bcur * hZ[(m - 1) + size_t(i) * m]) / std::fabs(hw[i]);
+            all = est <= tol * anorm;
+        }
+        if (all || steps >= max_steps) {
+            // direct check of the wanted pairs: Ritz vectors, Rayleigh quotients, residuals
+            std::vector<double> Sw(size_t(m) * want);
+            for (int c = 0; c < want; ++c)
+                for (int i = 0; i < m; ++i) Sw[i + size_t(c) * m] = hZ[i + size_t(ord[c]) * m];
+            h2d(dsm, Sw.data(), Sw.size());
+            jdmi::launch_gemm_vs(n, m, want, V, n, dsm, m, V2, n, s);
+            int ok = 0;
+            std::vector<double> rq(want);
+            for (int c = 0; c < want; ++c) {
+                double *u = V2 + size_t(c) * n;
+                jdmi::launch_stencil<double>(S.L, S.bc, S.eps64, 0.0, u, Au, s);
+                jdmi::launch_dot<double>(n, u, Au, partial, red, s);
+                jdmi::launch_dot<double>(n, u, u, partial, red + 1, s);
+                double q2[2];
+                d2h(q2, red, 2);
+                rq[c] = q2[0] / q2[1];
+                HIPCHK(hipMemcpyAsync(r64, Au, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                jdmi::launch_axpby_d(n, -rq[c], u, 1.0, r64, s);
+                jdmi::launch_dot<double>(n, r64, r64, partial, red, s);
+                double rr;
+                d2h(&rr, red, 1);
+                if (std::sqrt(std::max(rr, 0.0) / q2[1]) <= tol * anorm) {
+                    jdmi::launch_convert<double, double>(n, u, Q + size_t(ok) * n, 1.0 / std::sqrt(q2[1]), s);
+                    lam[ok++] = rq[c];
+                } else {
+                    break;  // the wanted pairs converge nearest first
+                }
+            }
+            if (ok == k) { nconv = k; break; }
+            if (steps >= max_steps) { nconv = ok; break; }
+        }
+        if (whole && m == mmax) break;  // the whole space is spanned: the pairs are exact
+        if (m == mmax && !whole) {
+            // restart: keep the `keep` wanted Ritz vectors and the last Lanczos vector
+            std::vector<double> Sk(size_t(m) * keep);
+            for (int c = 0; c < keep; ++c)
+                for (int i = 0; i < m; ++i) Sk[i + size_t(c) * m] = hZ[i + size_t(ord[c]) * m];
+            h2d(dsm, Sk.data(), Sk.size());
+            jdmi::launch_gemm_vs(n, m, keep, V, n, dsm, m, V2, n, s);
+            HIPCHK(hipMemcpyAsync(V, V2, size_t(n) * keep * sizeof(double), hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(V + size_t(keep) * n, V + size_t(m) * n, size_t(n) * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+            const double bm = Hat(m, m - 1);
+            std::fill(H.begin(), H.end(), 0.0);
+            for (int c = 0; c < keep; ++c) {
+                Hat(c, c) = hw[ord[c]];
+                Hat(keep, c) = Hat(c, keep) = bm * hZ[(m - 1) + size_t(ord[c]) * m];
+            }
+            m = keep;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    const double solve_s = now_s() - t0;
+    emit_outputs(S, Q, lam, nconv, k, out, Au, partial, red);
+    if (info) {
+        info->n_converged = nconv;
+        info->outer_its = steps;
+        info->inner_its = inner_total;
+        info->solve_s = solve_s;
+        fill_setup_info(S, info);
+        info->device_bytes = S.mem.bytes + mem.bytes + sv.mem.bytes;
+    }
+    return nconv == k ? JD_OK : JD_ENOCONV;
 }
 
 template <typename F>
@@ -957,6 +1225,56 @@ void check_solve_args(int n, int k, double tol, const double *evals)
 struct jd_problem {
     Setup S;
 };
+
+namespace {
+
+void check_linear_solve_args(jd_problem *p, double shift, const double *d_Q, int pcols, const double *d_b,
+                             const double *d_x, double rtol, int maxit)
+{
+    if (!p || !d_b || !d_x) throw JdError(JD_EINVAL, "NULL argument");
+    if (pcols < 0 || pcols > 64 || (pcols > 0 && !d_Q)) throw JdError(JD_EINVAL, "bad projection block");
+    if (!(rtol > 0) || maxit < 1) throw JdError(JD_EINVAL, "rtol must be > 0 and maxit >= 1");
+    if (!std::isfinite(shift)) throw JdError(JD_EINVAL, "shift must be finite");
+}
+
+// The projected linear solve on the solver's buffers: Qt, Y = K^{-1} Qt (n x pcols in the
+// inner precision), dM (pcols x pcols) on the device; Mh, work, h host arrays of at least
+// pcols^2, pcols^2 and pcols entries.  Returns the number of SQMR steps.
+template <typename T, typename PC>
+int linear_solve_core(Solver<T, PC> &sv, double shift, const double *d_Q, int pcols, const double *d_b, double *d_x,
+                      double rtol, int maxit, T *Qt, T *Y, double *dM, double *Mh, double *work, double *h)
+{
+    const int n = sv.n;
+    hipStream_t s = sv.s;
+    for (int c = 0; c < pcols; ++c) {
+        jdmi::launch_convert<double, T>(n, d_Q + size_t(c) * n, Qt + size_t(c) * n, 1.0, s);
+        sv.pc.apply(Qt + size_t(c) * n, Y + size_t(c) * n, s);
+    }
+    for (int c = 0; c < pcols; ++c) {
+        jdmi::launch_multidot<T>(n, pcols, Qt, n, Y + size_t(c) * n, sv.B.partial, sv.B.red, s);
+        HIPCHK(hipMemcpyAsync(h, sv.B.red, pcols * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int i = 0; i < pcols; ++i) Mh[i + size_t(c) * pcols] = h[i];
+    }
+    if (pcols > 0) {
+        if (!small_inverse(pcols, Mh, work)) throw JdError(JD_EINVAL, "projection block is singular for K^{-1}");
+        HIPCHK(hipMemcpyAsync(dM, Mh, size_t(pcols) * pcols * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    jdmi::launch_convert<double, T>(n, d_b, sv.B.b, 1.0, s);
+    if (pcols > 0) {
+        jdmi::launch_multidot<T>(n, pcols, Qt, n, sv.B.b, sv.B.partial, sv.B.red, s);
+        jdmi::launch_sub_qc<T>(n, pcols, Qt, n, sv.B.red, sv.B.b, s);
+    }
+    const int k = sv.sqmr(shift, Qt, Y, pcols, dM, rtol, maxit);
+    jdmi::launch_convert<T, double>(n, sv.B.x, d_x, 1.0, s);
+    HIPCHK(hipStreamSynchronize(s));
+    return k;
+}
+
+
+
+}  // namespace
 struct jd_precond {
     std::unique_ptr<Setup> own;  // null for a view of a problem's preconditioner
     Setup *S = nullptr;
@@ -965,6 +1283,19 @@ struct jd_precond {
 extern "C" {
 
 const char *jd_last_error(void) { return g_err.c_str(); }
+
+int jd_set_allocator(void *(*alloc)(size_t, void *, void *), void (*free_)(void *, void *, void *), void *ctx)
+{
+    return guarded([&] {
+        if ((alloc == nullptr) != (free_ == nullptr))
+            throw JdError(JD_EINVAL, "alloc and free_ must be given together (or both NULL)");
+        std::lock_guard<std::mutex> g(dev_mutex());
+        g_alloc.alloc = alloc;
+        g_alloc.free_ = free_;
+        g_alloc.ctx = alloc ? ctx : nullptr;
+        return JD_OK;
+    });
+}
 const char *jd_version(void) { return "jdmi 0.1 (gfx950)"; }
 
 int jd_setup(int L, double W, uint64_t seed, double sigma, const jd_options *opt, jd_problem **out)
@@ -1051,6 +1382,28 @@ int jd_problem_solve(jd_problem *p, int k, double tol, double *evals, double *ev
     });
 }
 
+int jd_problem_lanczos(jd_problem *p, int k, double tol, double inner_tol, double *evals, double *evecs_host,
+                       double *resid, jd_info *info)
+{
+    return guarded([&] {
+        if (!p) throw JdError(JD_EINVAL, "NULL problem");
+        check_solve_args(p->S.n, k, tol, evals);
+        if (inner_tol == 0) inner_tol = 1e-10;
+        if (!(inner_tol > 0 && inner_tol < 1)) throw JdError(JD_EINVAL, "inner_tol must be in (0, 1)");
+        const jd_options &o = p->S.opt;
+        if (o.jmax > 120) throw JdError(JD_EINVAL, "jmax too large");
+        Outputs out{evals, evecs_host, resid, nullptr};
+        if (o.precision == JD_MIXED)
+            throw JdError(JD_ENOTIMPL, "shift-and-invert Lanczos needs inner solves to inner_tol: binary64 vectors "
+                                       "(JD_FP64 or JD_MIXED_FACTORS)");
+        if (o.precision == JD_MIXED_FACTORS) {
+            MixedPrecond mp{p->S.pc32, p->S.pc64};
+            return si_lanczos_run(p->S, mp, k, tol, inner_tol, out, info);
+        }
+        return si_lanczos_run(p->S, p->S.pc64, k, tol, inner_tol, out, info);
+    });
+}
+
 int jd_solve(int L, double W, uint64_t seed, double sigma, int k, double tol, double *evals, double *evecs,
              double *resid, const jd_options *opt, jd_info *info)
 {
@@ -1081,18 +1434,20 @@ int jd_gen_diag(int L, double W, uint64_t seed, double *d_eps, float *d_eps32, v
     });
 }
 
-int jd_stencil_spmv(int L, int precision, const void *d_eps, double shift, const void *d_x, void *d_y, void *stream)
+int jd_stencil_spmv(int L, int bc, int precision, const void *d_eps, double shift, const void *d_x, void *d_y,
+                    void *stream)
 {
     return guarded([&] {
         check_problem_args(L, 0.0, shift, nullptr);
+        if (bc != JD_BC_PERIODIC && bc != JD_BC_HARDWALL) throw JdError(JD_EINVAL, "unknown boundary condition");
         if (!d_eps || !d_x || !d_y) throw JdError(JD_EINVAL, "NULL device pointer");
         if (d_x == d_y) throw JdError(JD_EINVAL, "x and y must not alias");
         hipStream_t s = static_cast<hipStream_t>(stream);
         if (precision == JD_FP64)
-            jdmi::launch_stencil<double>(L, static_cast<const double *>(d_eps), shift, static_cast<const double *>(d_x),
+            jdmi::launch_stencil<double>(L, bc, static_cast<const double *>(d_eps), shift, static_cast<const double *>(d_x),
                                          static_cast<double *>(d_y), s);
         else if (precision == JD_MIXED)
-            jdmi::launch_stencil<float>(L, static_cast<const float *>(d_eps), shift, static_cast<const float *>(d_x),
+            jdmi::launch_stencil<float>(L, bc, static_cast<const float *>(d_eps), shift, static_cast<const float *>(d_x),
                                         static_cast<float *>(d_y), s);
         else
             throw JdError(JD_EINVAL, "unknown precision");
@@ -1173,21 +1528,45 @@ int jd_problem_precond(jd_problem *p, jd_precond **out)
 int jd_precond_factor_nnz(const jd_precond *p, long long *nnz, int *n)
 {
     if (!p || !nnz) { g_err = "NULL argument"; return JD_EINVAL; }
-    *nnz = (long long)p->S->ml.z.col.size();
+    *nnz = p->S->ml.z.nnz;
     if (n) *n = p->S->n;
     return JD_OK;
+}
+
+int jd_precond_segments(const jd_precond *p, int cap, int *lev_begin, int *rows, long long *nnz)
+{
+    if (!p) { g_err = "NULL precond"; return JD_EINVAL; }
+    const auto &seg = p->S->ml.z.seg;
+    for (int i = 0; i < int(seg.size()) && i < cap; ++i) {
+        if (lev_begin) lev_begin[i] = seg[i].lev_begin;
+        if (rows) rows[i] = seg[i].rows;
+        if (nnz) nnz[i] = seg[i].nnz;
+    }
+    return int(seg.size());
 }
 
 int jd_precond_factor_product(jd_precond *p, int precision, int transpose, const void *d_x, void *d_y, void *stream)
 {
     return guarded([&] {
-        if (!p || !d_x || !d_y) throw JdError(JD_EINVAL, "NULL argument");
-        if (d_x == d_y) throw JdError(JD_EINVAL, "x and y must not overlap");
-        if (p->S->ml.z.ptr.empty()) throw JdError(JD_EINVAL, "the factorisation has no explicit inverse factor");
+        if (!p) throw JdError(JD_EINVAL, "NULL argument");
+        if ((d_x == nullptr) != (d_y == nullptr)) throw JdError(JD_EINVAL, "d_x and d_y must both be given or both NULL");
+        if (d_x && d_x == d_y) throw JdError(JD_EINVAL, "x and y must not overlap");
+        if (p->S->ml.z.seg.empty()) throw JdError(JD_EINVAL, "the factorisation has no explicit inverse factor");
         hipStream_t s = static_cast<hipStream_t>(stream);
-        auto go = [&](const auto &pc, auto *x, auto *y) {
-            if (transpose) jdmi::launch_hyb_spmv(pc.zth, x, y, pc.site_of, s, nullptr);
-            else jdmi::launch_hyb_spmv(pc.zh, x, y, static_cast<const int *>(nullptr), s, nullptr);
+        auto go = [&](const auto &pc, const auto *x, auto *y) {
+            using T = std::remove_const_t<std::remove_pointer_t<decltype(x)>>;
+            const size_t n = size_t(pc.n);
+            T *buf = pc.buf;
+            if (!transpose) {
+                if (x) HIPCHK(hipMemcpyAsync(buf + 2 * n, x, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+                for (const auto &z : pc.zdown) jdmi::launch_hyb_spmv<T, T>(z, buf, buf, nullptr, s, nullptr);
+                if (y) HIPCHK(hipMemcpyAsync(y, buf, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+            } else {
+                if (x) HIPCHK(hipMemcpyAsync(buf + n, x, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+                for (int i = int(pc.zup.size()) - 1; i >= 1; --i)
+                    jdmi::launch_hyb_spmv<T, T>(pc.zup[i], buf, buf, nullptr, s, nullptr);
+                jdmi::launch_hyb_spmv<T, T>(pc.zup[0], buf, y ? y : buf, y ? pc.site_of : nullptr, s, nullptr);
+            }
         };
         if (precision == JD_FP64) go(p->S->pc64, static_cast<const double *>(d_x), static_cast<double *>(d_y));
         else if (precision == JD_MIXED) go(p->S->pc32, static_cast<const float *>(d_x), static_cast<float *>(d_y));
@@ -1290,10 +1669,7 @@ int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int 
                             double rtol, int maxit, int *its)
 {
     return guarded([&] {
-        if (!p || !d_b || !d_x) throw JdError(JD_EINVAL, "NULL argument");
-        if (pcols < 0 || pcols > 64 || (pcols > 0 && !d_Q)) throw JdError(JD_EINVAL, "bad projection block");
-        if (!(rtol > 0) || maxit < 1) throw JdError(JD_EINVAL, "rtol must be > 0 and maxit >= 1");
-        if (!std::isfinite(shift)) throw JdError(JD_EINVAL, "shift must be finite");
+        check_linear_solve_args(p, shift, d_Q, pcols, d_b, d_x, rtol, maxit);
         Setup &S = p->S;
         const int n = S.n;
         hipStream_t s = S.stream;
@@ -1301,35 +1677,13 @@ int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int 
             using T = decltype(tag);
             using PC = std::decay_t<decltype(pc)>;
             Solver<T, PC> sv(S, pc, eps, (S.opt.flags & JD_FLAG_GRAPHS) != 0);
-            DevMem mem;
-            const int pc_ = pcols;
-            T *Qt = mem.alloc<T>(size_t(n) * std::max(pc_, 1));
-            T *Y = mem.alloc<T>(size_t(n) * std::max(pc_, 1));
-            double *dM = mem.alloc<double>(size_t(std::max(pc_, 1)) * std::max(pc_, 1));
-            std::vector<double> Mh(size_t(pc_) * pc_);
-            for (int c = 0; c < pc_; ++c) {
-                jdmi::launch_convert<double, T>(n, d_Q + size_t(c) * n, Qt + size_t(c) * n, 1.0, s);
-                pc.apply(Qt + size_t(c) * n, Y + size_t(c) * n, s);
-            }
-            for (int c = 0; c < pc_; ++c) {
-                jdmi::launch_multidot<T>(n, pc_, Qt, n, Y + size_t(c) * n, sv.B.partial, sv.B.red, s);
-                std::vector<double> h(pc_);
-                HIPCHK(hipMemcpyAsync(h.data(), sv.B.red, pc_ * sizeof(double), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
-                for (int i = 0; i < pc_; ++i) Mh[i + size_t(c) * pc_] = h[i];
-            }
-            if (pc_ > 0) {
-                if (!small_inverse(pc_, Mh)) throw JdError(JD_EINVAL, "projection block is singular for K^{-1}");
-                HIPCHK(hipMemcpyAsync(dM, Mh.data(), Mh.size() * sizeof(double), hipMemcpyHostToDevice, s));
-            }
-            jdmi::launch_convert<double, T>(n, d_b, sv.B.b, 1.0, s);
-            if (pc_ > 0) {
-                jdmi::launch_multidot<T>(n, pc_, Qt, n, sv.B.b, sv.B.partial, sv.B.red, s);
-                jdmi::launch_sub_qc<T>(n, pc_, Qt, n, sv.B.red, sv.B.b, s);
-            }
-            const int k_ = sv.sqmr(shift, Qt, Y, pc_, dM, rtol, maxit);
-            jdmi::launch_convert<T, double>(n, sv.B.x, d_x, 1.0, s);
-            HIPCHK(hipStreamSynchronize(s));
+            DevMem mem(s);
+            T *Qt = mem.alloc<T>(size_t(n) * std::max(pcols, 1));
+            T *Y = mem.alloc<T>(size_t(n) * std::max(pcols, 1));
+            double *dM = mem.alloc<double>(size_t(std::max(pcols, 1)) * std::max(pcols, 1));
+            std::vector<double> Mh(size_t(pcols) * pcols + 1), work(size_t(pcols) * pcols + 1), h(pcols + 1);
+            const int k_ = linear_solve_core(sv, shift, d_Q, pcols, d_b, d_x, rtol, maxit, Qt, Y, dM, Mh.data(),
+                                             work.data(), h.data());
             if (its) *its = k_;
         };
         if (S.opt.precision == JD_MIXED) run(float(0), S.pc32, S.eps32);
@@ -1389,6 +1743,7 @@ void check_request(const jd_request &r)
     if (r.precision != JD_FP64 && r.precision != JD_MIXED && r.precision != JD_MIXED_FACTORS)
         throw JdError(JD_EINVAL, "unknown precision");
     if (r.flags & ~(JD_FLAG_GRAPHS | JD_FLAG_LEVELS)) throw JdError(JD_EINVAL, "unknown flag bits");
+    if (r.bc != JD_BC_PERIODIC && r.bc != JD_BC_HARDWALL) throw JdError(JD_EINVAL, "unknown boundary condition");
 }
 
 }  // namespace
@@ -1418,6 +1773,7 @@ struct jd_server {
         jdmi::set_setup_threads(setup_threads);
         jd_options o{};
         o.precision = q.r.precision;
+        o.bc = q.r.bc;
         o.flags = q.r.flags & ~JD_FLAG_GRAPHS;  // workers launch eagerly
         o.stream = stream;
         jd_problem *p = nullptr;

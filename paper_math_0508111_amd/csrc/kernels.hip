@@ -78,38 +78,50 @@ void launch_gen_diag(int L, double W, uint64_t seed, double *eps, float *eps32, 
 }
 
 // ---------------------------------------------------------------------------------
-// K2: y = (A - shift I) x with A = -T + diag(eps) on the periodic lattice.
+// K2: y = (A - shift I) x with A = -T + diag(eps) on the periodic lattice, or on the box
+// with hard walls (a neighbour outside the box contributes nothing).
 // ---------------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_stencil(int L, int n, const T *__restrict__ eps, T shift,
+__device__ inline T neighbour_sum(int L, int n, int s, const T *__restrict__ x, int bc)
+{
+    const int LL = L * L;
+    const int i = s % L, jk = s / L, j = jk % L, k = jk / L;
+    if (bc == 0) {
+        const int xm = (i == 0) ? s + L - 1 : s - 1;
+        const int xp = (i == L - 1) ? s - L + 1 : s + 1;
+        const int ym = (j == 0) ? s + LL - L : s - L;
+        const int yp = (j == L - 1) ? s - LL + L : s + L;
+        const int zm = (k == 0) ? s + n - LL : s - LL;
+        const int zp = (k == L - 1) ? s - n + LL : s + LL;
+        return ((x[xm] + x[xp]) + (x[ym] + x[yp])) + (x[zm] + x[zp]);
+    }
+    const T xm = i > 0 ? x[s - 1] : T(0), xp = i < L - 1 ? x[s + 1] : T(0);
+    const T ym = j > 0 ? x[s - L] : T(0), yp = j < L - 1 ? x[s + L] : T(0);
+    const T zm = k > 0 ? x[s - LL] : T(0), zp = k < L - 1 ? x[s + LL] : T(0);
+    return ((xm + xp) + (ym + yp)) + (zm + zp);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_stencil(int L, int n, int bc, const T *__restrict__ eps, T shift,
                                                     const T *__restrict__ x, T *__restrict__ y,
                                                     const int *skip)
 {
     if (skip && *skip) return;
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
-    const int LL = L * L;
-    const int i = s % L, jk = s / L, j = jk % L, k = jk / L;
-    const int xm = (i == 0) ? s + L - 1 : s - 1;
-    const int xp = (i == L - 1) ? s - L + 1 : s + 1;
-    const int ym = (j == 0) ? s + LL - L : s - L;
-    const int yp = (j == L - 1) ? s - LL + L : s + L;
-    const int zm = (k == 0) ? s + n - LL : s - LL;
-    const int zp = (k == L - 1) ? s - n + LL : s + LL;
-    const T nb = ((x[xm] + x[xp]) + (x[ym] + x[yp])) + (x[zm] + x[zp]);
-    y[s] = (eps[s] - shift) * x[s] - nb;
+    y[s] = (eps[s] - shift) * x[s] - neighbour_sum(L, n, s, x, bc);
 }
 
 template <typename T>
-void launch_stencil(int L, const T *eps, double shift, const T *x, T *y, hipStream_t s, const int *skip)
+void launch_stencil(int L, int bc, const T *eps, double shift, const T *x, T *y, hipStream_t s, const int *skip)
 {
     const int n = L * L * L;
-    hipLaunchKernelGGL(k_stencil<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, L, n, eps, T(shift), x, y, skip);
+    hipLaunchKernelGGL(k_stencil<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, L, n, bc, eps, T(shift), x, y, skip);
 }
 
 // the same product with the shift read from the solver state (graph-replayable)
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_stencil_state(int L, int n, const T *__restrict__ eps,
+__global__ void __launch_bounds__(kBlock) k_stencil_state(int L, int n, int bc, const T *__restrict__ eps,
                                                           const SqmrState *st, const T *__restrict__ x,
                                                           T *__restrict__ y)
 {
@@ -117,23 +129,14 @@ __global__ void __launch_bounds__(kBlock) k_stencil_state(int L, int n, const T 
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
     const T shift = T(st->shift);
-    const int LL = L * L;
-    const int i = s % L, jk = s / L, j = jk % L, k = jk / L;
-    const int xm = (i == 0) ? s + L - 1 : s - 1;
-    const int xp = (i == L - 1) ? s - L + 1 : s + 1;
-    const int ym = (j == 0) ? s + LL - L : s - L;
-    const int yp = (j == L - 1) ? s - LL + L : s + L;
-    const int zm = (k == 0) ? s + n - LL : s - LL;
-    const int zp = (k == L - 1) ? s - n + LL : s + LL;
-    const T nb = ((x[xm] + x[xp]) + (x[ym] + x[yp])) + (x[zm] + x[zp]);
-    y[s] = (eps[s] - shift) * x[s] - nb;
+    y[s] = (eps[s] - shift) * x[s] - neighbour_sum(L, n, s, x, bc);
 }
 
 template <typename T>
-void launch_stencil_state(int L, const T *eps, const SqmrState *st, const T *x, T *y, hipStream_t s)
+void launch_stencil_state(int L, int bc, const T *eps, const SqmrState *st, const T *x, T *y, hipStream_t s)
 {
     const int n = L * L * L;
-    hipLaunchKernelGGL(k_stencil_state<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, L, n, eps, st, x, y);
+    hipLaunchKernelGGL(k_stencil_state<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, L, n, bc, eps, st, x, y);
 }
 
 template <typename T>
@@ -910,8 +913,8 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
 
 // ---- explicit instantiations ------------------------------------------------------
 #define JD_INST(T)                                                                                        \
-    template void launch_stencil<T>(int, const T *, double, const T *, T *, hipStream_t, const int *);    \
-    template void launch_stencil_state<T>(int, const T *, const SqmrState *, const T *, T *, hipStream_t); \
+    template void launch_stencil<T>(int, int, const T *, double, const T *, T *, hipStream_t, const int *);    \
+    template void launch_stencil_state<T>(int, int, const T *, const SqmrState *, const T *, T *, hipStream_t); \
     template void launch_copy<T>(int, const T *, T *, hipStream_t);                                       \
     template void launch_gather<T>(int, const int *, const T *, T *, hipStream_t, const int *);            \
     template void launch_scatter<T>(int, const int *, const T *, T *, hipStream_t, const int *);           \

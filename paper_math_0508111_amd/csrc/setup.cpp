@@ -19,6 +19,7 @@
 #include <cstring>
 #include <limits>
 #include <numeric>
+#include <tuple>
 #include <utility>
 #include <cstdio>
 #include <cstdlib>
@@ -63,8 +64,9 @@ void set_setup_threads(int threads)
 #endif
 }
 
-Csr anderson_shifted(int L, const double *eps, double sigma)
+Csr anderson_shifted(int L, const double *eps, double sigma, int bc)
 {
+    const bool wall = bc != 0;
     const int n = L * L * L;
     Csr A;
     A.n = n;
@@ -81,12 +83,13 @@ Csr anderson_shifted(int L, const double *eps, double sigma)
             e[m++] = {c, v};
         };
         add(s, eps[s] - sigma);
-        add((i + 1) % L + L * (j + L * k), -1.0);
-        add((i + L - 1) % L + L * (j + L * k), -1.0);
-        add(i + L * ((j + 1) % L + L * k), -1.0);
-        add(i + L * ((j + L - 1) % L + L * k), -1.0);
-        add(i + L * (j + L * ((k + 1) % L)), -1.0);
-        add(i + L * (j + L * ((k + L - 1) % L)), -1.0);
+        // with hard walls a neighbour across a face of the box is absent
+        if (!wall || i < L - 1) add((i + 1) % L + L * (j + L * k), -1.0);
+        if (!wall || i > 0) add((i + L - 1) % L + L * (j + L * k), -1.0);
+        if (!wall || j < L - 1) add(i + L * ((j + 1) % L + L * k), -1.0);
+        if (!wall || j > 0) add(i + L * ((j + L - 1) % L + L * k), -1.0);
+        if (!wall || k < L - 1) add(i + L * (j + L * ((k + 1) % L)), -1.0);
+        if (!wall || k > 0) add(i + L * (j + L * ((k + L - 1) % L)), -1.0);
         std::sort(e, e + m);
         for (int t = 0; t < m; ++t) { A.col.push_back(e[t].first); A.val.push_back(e[t].second); }
         A.ptr[s + 1] = int64_t(A.col.size());
@@ -944,63 +947,35 @@ std::string build_multilevel(const Csr &A0, const SetupParams &prm, Multilevel &
     if (verbose)
         fprintf(stderr, "levels %zu coarse %d: match %.2fs split %.2fs factor %.2fs total %.2fs\n", out.levels.size(),
                 out.coarse_n, t_match, t_split, t_fact, now_s() - t0);
-    if (prm.inverse_factor) build_inverse_factor(out, prm.z_drop, L);
+    if (prm.inverse_factor) build_inverse_factor(out, prm.z_drop, L, prm.z_parts > 0 ? prm.z_parts : default_z_parts(n));
     out.seconds = now_s() - t0;
     return "";
 }
 
 // ---------------------------------------------------------------------------------
-// Explicit inverse factor.  Applying the levels one after the other needs one
-// dependent pass per level and direction; the product of those passes is itself a
-// unit lower triangular matrix Z = L^{-1}, which is formed here (with dropping in the
-// scaled domain) so that the device applies the whole preconditioner as
-// P^T Z^T D^{-1} Z P: two sparse products and a block-diagonal solve.
+// Explicit inverse factor, in segments.  Applying the levels one after the other needs
+// one dependent pass per level and direction; the product of the passes of a range of
+// levels is itself a unit lower triangular matrix, formed here (with dropping in the
+// scaled domain), so that the device applies the whole preconditioner as
+// P^T Z_0^T ... Z_{S-1}^T D^{-1} Z_{S-1} ... Z_0 P: 2 S sparse products, a block-diagonal
+// solve and the exact last level.
 // ---------------------------------------------------------------------------------
-void build_inverse_factor(Multilevel &ml, double z_drop, int L)
+int default_z_parts(int n)
+{
+    // measured on the MI355X: the segments save bytes, each costs two launches
+    if (n >= (1 << 19)) return 6;
+    if (n >= (1 << 16)) return 4;
+    return 3;
+}
+
+void build_inverse_factor(Multilevel &ml, double z_drop, int L, int parts)
 {
     const double t0 = now_s();
     const int n = ml.n;
     const int nl = int(ml.levels.size());
     InverseFactor &Z = ml.z;
-    std::vector<std::vector<std::pair<int, double>>> rows(n);
     const std::vector<double> &sc = ml.pos_scale;
-#pragma omp parallel
-    {
-        std::vector<double> acc(n, 0.0);
-        std::vector<int> mark(n, -1), list;
-        for (int m = 0; m <= nl; ++m) {
-            const int r0 = (m < nl) ? ml.levels[m].off : ml.coarse_off;
-            const int r1 = (m < nl) ? ml.levels[m].off + ml.levels[m].nB : n;
-#pragma omp for schedule(dynamic, 16)
-            for (int r = r0; r < r1; ++r) {
-                list.clear();
-                auto put = [&](int c, double v) {
-                    if (mark[c] != r) { mark[c] = r; acc[c] = 0.0; list.push_back(c); }
-                    acc[c] += v;
-                };
-                put(r, 1.0);
-                for (int l = 0; l < m; ++l) {
-                    const Level &Lv = ml.levels[l];
-                    const int q = r - (Lv.off + Lv.nB);
-                    for (int64_t p = Lv.g_ptr[q]; p < Lv.g_ptr[q + 1]; ++p) {
-                        const double g = Lv.g_val[p];
-                        for (const auto &e : rows[Lv.g_col[p]]) put(e.first, -g * e.second);
-                    }
-                }
-                // kept entries in any order: the assembly below renumbers and sorts each row
-                auto &out = rows[r];
-                size_t keep = 0;
-                for (int c : list)
-                    if (c == r || z_drop < 0 || std::fabs(acc[c]) * sc[r] / sc[c] >= z_drop) ++keep;
-                out.reserve(keep);
-                for (int c : list) {
-                    const double v = acc[c];
-                    if (c == r || z_drop < 0 || std::fabs(v) * sc[r] / sc[c] >= z_drop) out.push_back({c, v});
-                }
-            }
-            // implicit barrier of the worksharing loop: level m is complete
-        }
-    }
+    auto lev_off = [&](int l) { return l < nl ? ml.levels[l].off : ml.coarse_off; };
     // renumbering: position p -> Morton rank of its site
     std::vector<int> newidx(n);
     {
@@ -1013,15 +988,13 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L)
             Z.site_of[q] = ml.perm[keyed[q].second];
         }
     }
-    // numbering of the product's middle vector (Z's rows, Z^T's columns, D^{-1}): blocks
-    // of kMidBlock consecutive Morton ranks, by elimination level inside a block. The
-    // rows of Z^T (pivots) then find their later-level dependants packed together,
-    // which cuts the cache lines each of Z^T's gathers touches by about a third.
-    std::vector<int> midx(n), pos_of(n);
+    // middle numbering: blocks of kMidBlock consecutive Morton ranks, by elimination level
+    // inside a block (a pivot's later-level dependants are then packed together, which
+    // cuts the cache lines each gather of the transposed products touches)
+    std::vector<int> level(n, nl), midx(n), pos_of(n);
+    for (int l = 0; l < nl; ++l)
+        for (int t = 0; t < ml.levels[l].nB; ++t) level[ml.levels[l].off + t] = l;
     {
-        std::vector<int> level(n, int(ml.levels.size()));
-        for (size_t l = 0; l < ml.levels.size(); ++l)
-            for (int t = 0; t < ml.levels[l].nB; ++t) level[ml.levels[l].off + t] = int(l);
         std::vector<std::tuple<int, int, int>> keyed(n);
         for (int p = 0; p < n; ++p) keyed[p] = {newidx[p] / kMidBlock, level[p], newidx[p]};
         std::vector<int> order(n);
@@ -1032,22 +1005,142 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L)
             pos_of[m] = order[m];
         }
     }
-    Z.ptr.assign(n + 1, 0);
-    for (int q = 0; q < n; ++q) Z.ptr[q + 1] = Z.ptr[q] + int64_t(rows[pos_of[q]].size());
-    Z.col.resize(Z.ptr[n]);
-    Z.val.resize(Z.ptr[n]);
-    // rows are independent once their offsets are known (columns within a row are
-    // distinct, so the sort order does not depend on the thread)
+    // segment cuts at levels 1, 3, 9, 27, ...
+    std::vector<int> cuts{0};
+    for (int c = 1; int(cuts.size()) < std::max(parts, 1) && c < nl; c *= 3) cuts.push_back(c);
+    cuts.push_back(nl);
+    const int S = int(cuts.size()) - 1;
+    std::vector<int> seg_of(n, S);  // segment owning each position (S: the last level)
+    for (int s = 0; s < S; ++s)
+        for (int l = cuts[s]; l < cuts[s + 1]; ++l)
+            for (int t = 0; t < ml.levels[l].nB; ++t) seg_of[ml.levels[l].off + t] = s;
+    const int64_t n1 = n, n2 = 2 * int64_t(n);
+    Z.seg.assign(S, ZSegment());
+    Z.nnz = 0;
+    for (int s = 0; s < S; ++s) {
+        const int a = cuts[s], b = cuts[s + 1];
+        const int off_a = lev_off(a);
+        const int nr = n - off_a;
+        ZSegment &zs = Z.seg[s];
+        zs.lev_begin = a;
+        zs.lev_end = b;
+        zs.rows = nr;
+        // rows of Z_s by position (p - off_a), level by level: a row needs the rows of
+        // the segment's earlier pivots only
+        std::vector<std::vector<std::pair<int, double>>> rows(nr);
+#pragma omp parallel
+        {
+            std::vector<double> acc(n, 0.0);
+            std::vector<int> mark(n, -1), list;
+            for (int m = a; m <= nl; ++m) {
+                const int r0 = lev_off(m);
+                const int r1 = (m < nl) ? ml.levels[m].off + ml.levels[m].nB : n;
+                const int lmax = std::min(m, b);
+#pragma omp for schedule(dynamic, 16)
+                for (int r = r0; r < r1; ++r) {
+                    list.clear();
+                    auto put = [&](int c, double v) {
+                        if (mark[c] != r) { mark[c] = r; acc[c] = 0.0; list.push_back(c); }
+                        acc[c] += v;
+                    };
+                    put(r, 1.0);
+                    for (int l = a; l < lmax; ++l) {
+                        const Level &Lv = ml.levels[l];
+                        const int q = r - (Lv.off + Lv.nB);
+                        for (int64_t p = Lv.g_ptr[q]; p < Lv.g_ptr[q + 1]; ++p) {
+                            const double g = Lv.g_val[p];
+                            for (const auto &e : rows[Lv.g_col[p] - off_a]) put(e.first, -g * e.second);
+                        }
+                    }
+                    auto &out = rows[r - off_a];
+                    size_t keep = 0;
+                    for (int c : list)
+                        if (c == r || z_drop < 0 || std::fabs(acc[c]) * sc[r] / sc[c] >= z_drop) ++keep;
+                    out.reserve(keep);
+                    for (int c : list) {
+                        const double v = acc[c];
+                        if (c == r || z_drop < 0 || std::fabs(v) * sc[r] / sc[c] >= z_drop) out.push_back({c, v});
+                    }
+                }
+                // implicit barrier of the worksharing loop: level m is complete
+            }
+        }
+        // down product: rows in the middle order, offsets into the 3 n buffer
+        const int64_t w_off = (s % 2 == 0) ? n1 : n2;       // region of the rows passed on
+        const int64_t r_off = (s % 2 == 1) ? n1 : n2;       // region segment s - 1 wrote
+        std::vector<int> drow;                               // local row -> position
+        drow.reserve(nr);
+        for (int m = 0; m < n; ++m)
+            if (pos_of[m] >= off_a) drow.push_back(pos_of[m]);
+        BigVec<int64_t> ptr(nr + 1);
+        ptr[0] = 0;
+        for (int i = 0; i < nr; ++i) ptr[i + 1] = ptr[i] + int64_t(rows[drow[i] - off_a].size());
+        const int64_t nnz = ptr[nr];
+        BigVec<int> col(nnz);
+        BigVec<double> val(nnz);
+        std::vector<int> code(nr);
 #pragma omp parallel for schedule(dynamic, 256)
-    for (int q = 0; q < n; ++q) {
-        auto &row = rows[pos_of[q]];
-        for (auto &e : row) e.first = newidx[e.first];
-        std::sort(row.begin(), row.end());
-        int64_t p = Z.ptr[q];
-        for (auto &e : row) { Z.col[p] = e.first; Z.val[p] = e.second; ++p; }
-        std::vector<std::pair<int, double>>().swap(row);
+        for (int i = 0; i < nr; ++i) {
+            const int p = drow[i];
+            const bool final_row = seg_of[p] == s || (s == S - 1 && seg_of[p] == S);
+            code[i] = int(final_row ? midx[p] : w_off + midx[p]);
+            auto row = rows[p - off_a];  // copy: the transposed product reads positions
+            for (auto &e : row) e.first = int(s == 0 ? n2 + newidx[e.first] : r_off + midx[e.first]);
+            std::sort(row.begin(), row.end());
+            int64_t o = ptr[i];
+            for (auto &e : row) { col[o] = e.first; val[o] = e.second; ++o; }
+        }
+        zs.nnz = nnz;
+        Z.nnz += nnz;
+        zs.down = to_hyb(nr, ptr.data(), col.data(), val.data(), code.data());
+        // up product: Z_s^T restricted to this segment's pivots (segment 0: every position,
+        // for the output permutation), rows in the middle order (segment 0: Morton order)
+        std::vector<int> urow;  // up row -> position
+        std::vector<int> uat(n, -1);
+        if (s == 0) {
+            urow.resize(n);
+            for (int p = 0; p < n; ++p) urow[newidx[p]] = p;
+        } else {
+            for (int m = 0; m < n; ++m)
+                if (seg_of[pos_of[m]] == s) urow.push_back(pos_of[m]);
+        }
+        const int nu = int(urow.size());
+        for (int i = 0; i < nu; ++i) uat[urow[i]] = i;
+        BigVec<int64_t> tptr(nu + 1);
+        std::fill(tptr.begin(), tptr.end(), 0);
+        for (int i = 0; i < nr; ++i)
+            for (const auto &e : rows[drow[i] - off_a])
+                if (uat[e.first] >= 0) ++tptr[uat[e.first] + 1];
+        for (int i = 0; i < nu; ++i) tptr[i + 1] += tptr[i];
+        BigVec<int> tcol(tptr[nu]);
+        BigVec<double> tval(tptr[nu]);
+        {
+            std::vector<int64_t> fp(tptr.begin(), tptr.end() - 1);
+            for (int i = 0; i < nr; ++i) {
+                const int r = drow[i];
+                // a later segment's pivot has its final value in region 2; this segment's
+                // own pivots and the last level's unknowns are read from region 1
+                const bool later = seg_of[r] > s && seg_of[r] < S;
+                const int rc = int(later ? n2 + midx[r] : n1 + midx[r]);
+                for (const auto &e : rows[r - off_a]) {
+                    const int u = uat[e.first];
+                    if (u < 0) continue;
+                    tcol[fp[u]] = rc;
+                    tval[fp[u]++] = e.second;
+                }
+            }
+        }
+        std::vector<int> ucode(nu);
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int i = 0; i < nu; ++i) {
+            ucode[i] = int(s == 0 ? newidx[urow[i]] : n2 + midx[urow[i]]);
+            std::vector<std::pair<int, double>> row(size_t(tptr[i + 1] - tptr[i]));
+            for (int64_t o = tptr[i]; o < tptr[i + 1]; ++o) row[o - tptr[i]] = {tcol[o], tval[o]};
+            std::sort(row.begin(), row.end());
+            for (int64_t o = tptr[i]; o < tptr[i + 1]; ++o) { tcol[o] = row[o - tptr[i]].first; tval[o] = row[o - tptr[i]].second; }
+        }
+        zs.up = to_hyb(nu, tptr.data(), tcol.data(), tval.data(), ucode.data());
     }
-    transpose(n, Z.ptr, Z.col, Z.val, Z.tptr, Z.tcol, Z.tval);
     Z.dd.assign(n, 0.0);
     Z.dof.assign(n, 0.0);
     Z.dp.resize(n);
@@ -1067,11 +1160,12 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L)
 // CSR -> the hybrid device layout (see HybHost).  The parts are built on their own
 // (in parallel) and then concatenated, with their long-row indices, slice codes and
 // offsets shifted to the global numbering.
-HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val)
+HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val, const int *row_code)
 {
     constexpr int P = kHybParts, C = kSliceRows, G = kSliceLanes;
     constexpr size_t kWindow = 2048;
     auto len = [&](int r) { return ptr[r + 1] - ptr[r]; };
+    auto rcode = [&](int r) { return row_code ? row_code[r] : r; };
     const int64_t nnz = ptr[n];
     // rows [rb[part], rb[part + 1]): the part's share of the nonzeros
     int rb[P + 1];
@@ -1091,7 +1185,7 @@ HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val)
         std::stable_sort(longr.begin(), longr.end(), [&](int a, int b) { return len(a) > len(b); });
         for (int r : longr) {
             h.task.push_back(int(h.long_row.size()));
-            h.long_row.push_back(r);
+            h.long_row.push_back(rcode(r));
             h.long_col.insert(h.long_col.end(), col + ptr[r], col + ptr[r + 1]);
             h.long_val.insert(h.long_val.end(), val + ptr[r], val + ptr[r + 1]);
             h.long_ptr.push_back(int64_t(h.long_col.size()));
@@ -1104,8 +1198,10 @@ HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val)
             int64_t w = 0;
             for (size_t l = 0; l < size_t(C) && s0 + l < shortr.size(); ++l) w = std::max(w, len(shortr[s0 + l]));
             const int64_t base = h.slice_ptr.back(), groups = (w + G - 1) / G;
+            // padding reads the slice's first entry's location (a value the product reads anyway)
+            const int pad = len(shortr[s0]) > 0 ? col[ptr[shortr[s0]]] : 0;
             h.slice_ptr.push_back(base + groups * 64);
-            h.col.resize(size_t(base + groups * 64), 0);
+            h.col.resize(size_t(base + groups * 64), pad);
             h.val.resize(size_t(base + groups * 64), 0.0);
             for (int l = 0; l < C; ++l) {
                 if (s0 + l >= shortr.size()) {
@@ -1113,7 +1209,7 @@ HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val)
                     continue;
                 }
                 const int r = shortr[s0 + l];
-                h.rowidx.push_back(r);
+                h.rowidx.push_back(rcode(r));
                 for (int64_t j = 0; j < len(r); ++j) {
                     const int64_t at = base + (j / G) * 64 + (j % G) * C + l;
                     h.col[at] = col[ptr[r] + j];

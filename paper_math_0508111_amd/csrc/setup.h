@@ -76,27 +76,76 @@ struct SetupParams {
     int coarse_max = 1536;
     int max_levels = 64;
     double z_drop = 1e-2;     // relative drop tolerance of the explicit inverse factor (< 0: none)
+    int z_parts = 0;          // segments of the inverse factor (0: default_z_parts(n))
     bool inverse_factor = true;
     bool host_coarse_inverse = true;  // false: leave the dense last level for the device to invert
 };
 
-// Explicit inverse of the unit lower triangular factor of all levels, Z ~ L^{-1}
-// (global positions), and the block diagonal D^{-1}: K^{-1} = P^T Z^T D^{-1} Z P.
-// The apply does not need the elimination order, so the unknowns are renumbered:
-// K^{-1} b = S^T Z^T D^{-1} Z S b with (S b)[q] = b[site_of[q]].  Z's columns (the
-// input numbering, also Z^T's rows) follow the Morton order of the lattice sites, so
-// that the gathers of neighbouring rows share cache lines; Z's rows (the middle
-// numbering of D^{-1}, the last level and Z^T's columns) follow blocks of kMidBlock
-// Morton ranks with the unknowns of each block ordered by elimination level.
+// Device layout of a sparse product (built on the host; the kernel reads it as
+// jdmi::Hyb).  The rows are cut into kHybParts contiguous parts of equal nonzero count;
+// inside a part, rows with more than kLongRow entries are kept in CSR (longest first,
+// one wave each) and the other rows form slices of kSliceRows rows with kSliceLanes
+// lanes per row: entry j of the slice's row l sits at
+// slice_ptr[s] + (j / kSliceLanes) * 64 + (j % kSliceLanes) * kSliceRows + l
+// (padding: value 0 and the column of the slice's first entry, so that it reads a
+// location the product reads anyway).  Short rows are sorted by decreasing length
+// inside windows of 2048 consecutive rows, so a slice holds rows of similar length that
+// are also neighbours in row order.  Row and column numbers are the element offsets the
+// kernel writes and reads (see InverseFactor for the buffer they address).
+constexpr int kHybParts = 8;
+constexpr int kLongRow = 96;
+constexpr int kSliceRows = 8;
+constexpr int kSliceLanes = 64 / kSliceRows;
+struct HybHost {
+    int tbeg[kHybParts] = {}, tend[kHybParts] = {};  // task range of each part
+    std::vector<int> task;                 // >= 0: long row index; < 0: slice -1 - task
+    std::vector<int> long_row;
+    std::vector<int64_t> long_ptr{0};
+    std::vector<int> long_col;
+    std::vector<double> long_val;
+    std::vector<int64_t> slice_ptr{0};     // in entries (multiples of 64)
+    std::vector<int> rowidx, col;          // rowidx: kSliceRows per slice, -1 for padding rows
+    std::vector<double> val;
+};
+// CSR with nrows rows -> the hybrid layout; row i is written to row_code[i] (i when NULL).
+HybHost to_hyb(int nrows, const int64_t *ptr, const int *col, const double *val, const int *row_code = nullptr);
+
+// The inverse of the unit lower triangular factor of all levels, Z = L^{-1}, applied as
+// a product of segments: with the levels cut into consecutive ranges [a, b),
+// Z = Z_{S-1} ... Z_1 Z_0 and Z_s = (I - G_{b-1}) ... (I - G_a), each formed explicitly
+// (with dropping in the scaled domain).  One explicit Z (S = 1) needs no dependent passes
+// but its rows accumulate the fill of every chain through all levels (85 M entries at
+// L = 100); cutting the chains at a few level boundaries keeps the apply at 2 S + 4
+// launches and stores about a quarter of the entries.  K^{-1} = P^T Z^T D^{-1} Z P.
+//
+// Numbering.  The input vector is gathered in the Morton order of the lattice sites
+// (site_of: Morton index -> site); every other vector uses the middle numbering: blocks
+// of kMidBlock consecutive Morton ranks, the unknowns of a block ordered by elimination
+// level.  The device works in one buffer of 3 n values, regions [0, n), [n, 2n),
+// [2n, 3n):
+//   down, segment s: reads region (s == 0 ? 2 (the gathered input, Morton numbering)
+//     : the region segment s - 1 wrote); writes its own pivots (and, in the last
+//     segment, the last level's unknowns) to region 0, its other rows to region
+//     (s even ? 1 : 2);
+//   D^{-1} and the last level: region 0 -> region 1;
+//   up, segment s = S-1 .. 1: writes its pivots to region 2, reading a position from
+//     region 2 when a later segment owns it, else from region 1;
+//   up, segment 0: every position, written through site_of to the output vector.
+// The layouts store these element offsets directly as row and column numbers.
 constexpr int kMidBlock = 128;
+struct ZSegment {
+    int lev_begin = 0, lev_end = 0;   // levels [lev_begin, lev_end)
+    int rows = 0;                      // rows of the down product (unknowns entering lev_begin)
+    long long nnz = 0;                 // stored entries, unit diagonal included
+    HybHost down, up;
+};
 struct InverseFactor {
-    std::vector<int> site_of;         // n: input index -> lattice site
-    BigVec<int64_t> ptr, tptr;        // CSR of Z (rows: middle, columns: input numbering) and of Z^T
-    BigVec<int> col, tcol;
-    BigVec<double> val, tval;
+    std::vector<int> site_of;         // n: Morton index -> lattice site
+    std::vector<ZSegment> seg;
     std::vector<double> dd, dof;      // D^{-1} (middle numbering): z[q] = dd[q] y[q] + dof[q] y[dp[q]] (0 on the last level)
     std::vector<int> dp;
     std::vector<int> coarse_idx;      // coarse_n: middle index of each unknown of the last level
+    long long nnz = 0;                // stored entries of all segments
     double seconds = 0.0;
 };
 
@@ -137,9 +186,14 @@ struct Multilevel {
     InverseFactor z;               // filled when SetupParams::inverse_factor
 };
 
-// Z = L^{-1} row by row (row r = e_r - sum over earlier levels of G[r, c] z_c), dropping
-// entries with |z_rc| s_r / s_c < z_drop (s = pos_scale), and its transpose.
-void build_inverse_factor(Multilevel &ml, double z_drop, int L);
+// Default number of segments of the inverse factor for n unknowns.
+int default_z_parts(int n);
+
+// The segments of Z (see InverseFactor): level cuts at 1, 3, 9, 27, ... (at most
+// `parts` segments); row r of Z_s is e_r - sum over the segment's levels before r's of
+// G[r, c] (row c of Z_s), with entries |z_rc| s_r / s_c < z_drop dropped
+// (s = pos_scale; z_drop < 0: none), then the device layouts of Z_s and Z_s^T.
+void build_inverse_factor(Multilevel &ml, double z_drop, int L, int parts);
 
 // Build the multilevel factorisation of the symmetric matrix A.
 // Returns an empty string on success, else a message.
@@ -150,33 +204,9 @@ void set_setup_threads(int threads);
 // OpenMP threads available to the calling thread (OMP_NUM_THREADS when set).
 int setup_thread_budget();
 
-// A - sigma I for the periodic Anderson lattice (hopping -1), CSR.
-Csr anderson_shifted(int L, const double *eps, double sigma);
+// A - sigma I for the Anderson lattice (hopping -1), CSR; bc 0: periodic, 1: hard walls.
+Csr anderson_shifted(int L, const double *eps, double sigma, int bc = 0);
 
-// Device layout of the explicit inverse factor's products (built on the host; the
-// kernel reads it as jdmi::Hyb).  The rows (lattice sites in Morton order) are cut into
-// kHybParts contiguous parts of equal nonzero count; inside a part, rows with more than
-// kLongRow entries are kept in CSR (longest first, one wave each) and the other rows
-// form slices of kSliceRows rows with kSliceLanes lanes per row: entry j of the slice's
-// row l sits at slice_ptr[s] + (j / kSliceLanes) * 64 + (j % kSliceLanes) * kSliceRows + l
-// (padding: index 0, value 0).  Short rows are sorted by decreasing length inside
-// windows of 2048 consecutive rows, so a slice holds rows of similar length that are
-// also neighbours in position order.
-constexpr int kHybParts = 8;
-constexpr int kLongRow = 96;
-constexpr int kSliceRows = 8;
-constexpr int kSliceLanes = 64 / kSliceRows;
-struct HybHost {
-    int tbeg[kHybParts] = {}, tend[kHybParts] = {};  // task range of each part
-    std::vector<int> task;                 // >= 0: long row index; < 0: slice -1 - task
-    std::vector<int> long_row;
-    std::vector<int64_t> long_ptr{0};
-    std::vector<int> long_col;
-    std::vector<double> long_val;
-    std::vector<int64_t> slice_ptr{0};     // in entries (multiples of 64)
-    std::vector<int> rowidx, col;          // rowidx: kSliceRows per slice, -1 for padding rows
-    std::vector<double> val;
-};
-HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val);
+
 
 }  // namespace jdmi

@@ -1,0 +1,146 @@
+"""The full-size and closed-form configurations on the GPU, through the C ABI.
+
+* L = 100, W = 16.5, k = 10, binary32 inner solves (the benchmarked workload) against
+  the stored oracle result, whose window holds exactly k eigenvalues by the exact
+  LDL^T's inertia (section 5.1; written by tests/golden/make_golden.py);
+* W = 0, where the spectrum is the closed form -2 sum_d cos(2 pi a_d / L) with
+  degenerate clusters (section 3, eq. (eigenequation), periodic boundary conditions):
+  eigenvalues against the closed form and each cluster's eigenvectors against its
+  eigenspace by principal angles (the eigenspace of a cluster is spanned by the plane
+  waves of its wave vectors, so the projection is read off a unitary FFT).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_math_0508111_amd as jd  # noqa: E402
+from oracle import generator, lattice  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLD, name + ".json")) as fh:
+        return json.load(fh)
+
+
+def test_headline_workload_against_certified_oracle():
+    g = _golden("L100_W16.5_s0_k10")
+    cert = g["certificate"]
+    assert cert["inertia_count"] == g["k"]
+    L, W, seed, sigma, k = g["L"], g["W"], g["seed"], g["sigma"], g["k"]
+    evals, evecs, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, vectors=True, precision="mixed")
+    assert info["status"] == 0 and info["n_converged"] == k
+    assert np.max(np.abs(evals - np.array(g["lams"]))) <= 1e-9
+    eps = generator.disorder(L, W, seed)
+    anorm = lattice.inf_norm(eps)
+    for c in range(k):
+        x = evecs[:, c]
+        r = np.linalg.norm(lattice.matvec(L, eps, x) - evals[c] * x)
+        assert r <= 1e-10 * anorm * 1.0001, (c, r / anorm)
+    assert np.abs(evecs.T @ evecs - np.eye(k)).max() <= 1e-8
+    # every returned value lies in the certified window
+    lo, hi = cert["window"]
+    assert np.all((evals > lo) & (evals < hi))
+
+
+def _clusters(L, sigma, kmin, kmax=64, bc="periodic"):
+    """Closed-form spectrum: the smallest k >= kmin such that the k values nearest sigma
+    are whole clusters (no degenerate eigenvalue split by the cut)."""
+    lam = np.sort(lattice.clean_spectrum(L, bc))
+    vals, counts = [], []
+    for v in lam:
+        if vals and abs(v - vals[-1]) <= 1e-9:
+            counts[-1] += 1
+        else:
+            vals.append(v)
+            counts.append(1)
+    vals, counts = np.array(vals), np.array(counts)
+    order = np.lexsort((vals, np.abs(vals - sigma)))
+    k = 0
+    for i in order:
+        k += counts[i]
+        if k >= kmin:
+            break
+    assert k <= kmax
+    return k, vals, counts
+
+
+def _modes(evecs, L, bc):
+    """Coefficients of the vectors in the orthonormal eigenbasis of the clean lattice:
+    plane waves (unitary FFT) on the torus, products of the open chain's sine modes
+    sqrt(2/(L+1)) sin(pi a m/(L+1)) with hard walls (an orthogonal basis per axis)."""
+    k = evecs.shape[1]
+    V = evecs.T.reshape(k, L, L, L)
+    if bc == "periodic":
+        return np.fft.fftn(V, axes=(1, 2, 3), norm="ortho")
+    m = np.arange(1, L + 1)
+    S = np.sqrt(2.0 / (L + 1)) * np.sin(np.pi * np.outer(m, m) / (L + 1))  # symmetric, orthogonal
+    return np.einsum("ai,bj,ck,nkji->ncba", S, S, S, V, optimize=True)
+
+
+def _check_closed_form(L, sigma, k, evals, evecs, resid, vals, bc="periodic"):
+    n = L ** 3
+    eps = np.zeros(n)
+    anorm = lattice.inf_norm(eps, L, bc)
+    spec = np.sort(lattice.clean_spectrum(L, bc))
+    lam3 = lattice.clean_spectrum(L, bc).reshape(L, L, L)
+    # eigenvalues: each is a closed-form value, and the multiset is the k nearest
+    near = np.sort(spec[np.argsort(np.abs(spec - sigma), kind="stable")[:k]])
+    assert np.max(np.abs(np.sort(evals) - near)) <= 1e-9
+    for c in range(k):
+        x = evecs[:, c]
+        r = np.linalg.norm(lattice.matvec(L, eps, x, bc=bc) - evals[c] * x)
+        assert r <= 1e-10 * anorm * 1.0001
+    assert np.abs(evecs.T @ evecs - np.eye(k)).max() <= 1e-8
+    # principal angles between each cluster's vectors and its eigenspace
+    xhat = _modes(evecs, L, bc)
+    done = np.zeros(k, bool)
+    for c in range(k):
+        if done[c]:
+            continue
+        members = np.where(np.abs(evals - evals[c]) <= 1e-7)[0]
+        done[members] = True
+        mask = np.abs(lam3 - evals[c]) <= 1e-7
+        assert mask.sum() == len(members), (evals[c], mask.sum(), len(members))
+        Y = xhat[members][:, mask].T  # (wave vectors of the cluster) x (its vectors)
+        smin = np.linalg.svd(Y, compute_uv=False).min()
+        others = vals[np.abs(vals - evals[c]) > 1e-7]
+        gap = np.min(np.abs(others - evals[c]))
+        sin_max = np.sqrt(max(0.0, 1.0 - smin ** 2))
+        assert sin_max <= 10 * 1e-10 * anorm / gap + 1e-12, (evals[c], sin_max)
+
+
+def test_clean_lattice_band_edge_large():
+    # n = 81^3 >= 2^19 (the large-lattice search space); sigma just below the spectrum:
+    # the simple eigenvalue -6 and the six-fold cluster -4 - 2 cos(2 pi / 81)
+    L, sigma = 81, -6.001
+    k, vals, _ = _clusters(L, sigma, 7)
+    assert k == 7
+    evals, evecs, resid, info = jd.solve(L, 0.0, 0, sigma, k, 1e-10, vectors=True, precision="mixed")
+    assert info["status"] == 0 and info["n_converged"] == k
+    _check_closed_form(L, sigma, k, evals, evecs, resid, vals)
+
+
+@pytest.mark.parametrize("L,sigma,precision", [(12, 1.44, "fp64"), (16, -0.51, "mixed"), (10, -1.83, "mixed_factors")])
+def test_clean_lattice_interior_clusters(L, sigma, precision):
+    # an indefinite A - sigma I with a zero diagonal: degenerate clusters inside the band
+    k, vals, _ = _clusters(L, sigma, 4)
+    evals, evecs, resid, info = jd.solve(L, 0.0, 0, sigma, k, 1e-10, vectors=True, precision=precision)
+    assert info["status"] == 0 and info["n_converged"] == k
+    _check_closed_form(L, sigma, k, evals, evecs, resid, vals)
+
+
+@pytest.mark.parametrize("L,sigma,precision", [(14, 0.9, "mixed"), (9, -1.3, "fp64")])
+def test_clean_lattice_hardwall_clusters(L, sigma, precision):
+    # hard walls at W = 0: -2 sum cos(pi a / (L + 1)), clusters from permutations of (a, b, c)
+    k, vals, _ = _clusters(L, sigma, 3, bc="hardwall")
+    evals, evecs, resid, info = jd.solve(L, 0.0, 0, sigma, k, 1e-10, vectors=True, precision=precision,
+                                         bc="hardwall")
+    assert info["status"] == 0 and info["n_converged"] == k
+    _check_closed_form(L, sigma, k, evals, evecs, resid, vals, bc="hardwall")

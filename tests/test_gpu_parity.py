@@ -320,3 +320,97 @@ def test_solve_after_a_stalled_setup():
     lo, hi = np.min(evals) - 1e-9, np.max(evals) + 1e-9
     radius = max(sigma - lo, hi - sigma)
     assert eig.count_in_window(L, eps, sigma - radius, sigma + radius) == k
+
+
+# --- hard-wall boundary conditions (section 8.2, Table 6) ---------------------------------
+
+@pytest.mark.parametrize("L,shift", [(2, 0.0), (3, 0.7), (33, -0.25), (100, 0.0)])
+def test_stencil_parity_hardwall(L, shift):
+    n = L ** 3
+    eps = generator.disorder(L, 16.5, 1)
+    x = seeded_inputs.vector(n, 7)
+    ref = lattice.matvec(L, eps, x, shift=shift, bc="hardwall")
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    jd.stencil_spmv(L, dev(eps), shift, dev(x), y, "fp64", stream=stream(), bc="hardwall")
+    torch.cuda.synchronize()
+    scale = np.abs(eps - shift) * np.abs(x) + 6 * np.abs(x).max()
+    assert np.all(np.abs(y.cpu().numpy() - ref) <= 8 * np.finfo(float).eps * scale)
+    y32 = torch.empty(n, dtype=torch.float32, device="cuda")
+    jd.stencil_spmv(L, dev(eps, torch.float32), shift, dev(x, torch.float32), y32, "mixed", stream=stream(),
+                    bc="hardwall")
+    torch.cuda.synchronize()
+    assert np.all(np.abs(y32.cpu().numpy().astype(np.float64) - ref) <= 16 * U32 * scale)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_solve_hardwall_against_stored_oracle(precision):
+    g = _golden("L30_W16.5_s0_k5_hardwall")
+    assert g["bc"] == "hardwall" and g["certificate"]["inertia_count"] == g["k"]
+    L, W, seed, sigma, k = g["L"], g["W"], g["seed"], g["sigma"], g["k"]
+    evals, evecs, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, vectors=True, precision=precision,
+                                         bc="hardwall")
+    assert info["n_converged"] == k and np.max(np.abs(evals - np.array(g["lams"]))) <= 1e-9
+    eps = generator.disorder(L, W, seed)
+    for c in range(k):
+        r = np.linalg.norm(lattice.matvec(L, eps, evecs[:, c], bc="hardwall") - evals[c] * evecs[:, c])
+        assert r <= 1e-10 * g["anorm"] * 1.0001
+    assert abs(info["anorm"] - g["anorm"]) <= 1e-15 * g["anorm"]
+
+
+@pytest.mark.parametrize("L,W,seed,sigma,k,precision", [(8, 16.5, 3, 0.0, 5, "fp64"), (12, 12.0, 5, 0.3, 6, "mixed"),
+                                                        (15, 21.0, 8, -0.6, 4, "mixed_factors"),
+                                                        (7, 16.5, 1, 0.2, 64, "fp64")])
+def test_solve_hardwall_live_oracle(L, W, seed, sigma, k, precision):
+    eps = generator.disorder(L, W, seed)
+    ref, X, _, anorm = eig.nearest_eigenpairs(L, eps, sigma, k, bc="hardwall")
+    evals, evecs, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, vectors=True, precision=precision,
+                                         bc="hardwall")
+    assert info["n_converged"] == k and abs(info["anorm"] - anorm) <= 1e-15 * anorm
+    assert np.all(np.abs(evals - ref) <= 1e-9), (evals, ref)
+    for c in range(k):
+        x = evecs[:, c]
+        r = np.linalg.norm(lattice.matvec(L, eps, x, bc="hardwall") - evals[c] * x)
+        assert r <= 1e-10 * anorm * 1.0001
+    assert np.abs(evecs.T @ evecs - np.eye(k)).max() <= 1e-8
+    if k <= 8:
+        for c in range(k):
+            assert abs(abs(evecs[:, c] @ X[:, c]) - 1.0) <= 1e-8
+
+
+# --- shift-and-invert Lanczos on the same kernels (section 4.1; section 8.2, Tables 2-3) ----
+
+@pytest.mark.parametrize("L,W,seed,sigma,k,precision,bc", [(10, 16.5, 0, 0.0, 5, "fp64", "periodic"),
+                                                           (16, 12.0, 4, 0.35, 6, "mixed_factors", "periodic"),
+                                                           (12, 21.0, 7, -0.4, 4, "fp64", "hardwall"),
+                                                           (2, 16.5, 11, 0.0, 8, "fp64", "periodic")])
+def test_si_lanczos_against_oracle(L, W, seed, sigma, k, precision, bc):
+    eps = generator.disorder(L, W, seed)
+    ref, X, _, anorm = eig.nearest_eigenpairs(L, eps, sigma, k, bc=bc)
+    p = jd.Problem(L, W, seed, sigma, precision=precision, bc=bc)
+    evals, evecs, resid, info = p.lanczos(k, 1e-10, vectors=True)
+    p.close()
+    assert info["status"] == 0 and info["n_converged"] == k
+    assert np.all(np.abs(evals - ref) <= 1e-9), (evals, ref)
+    for c in range(k):
+        x = evecs[:, c]
+        r = np.linalg.norm(lattice.matvec(L, eps, x, bc=bc) - evals[c] * x)
+        assert r <= 1e-10 * anorm * 1.0001
+    assert np.abs(evecs.T @ evecs - np.eye(k)).max() <= 1e-8
+    # inner solves to 1e-10 take more steps per product than the correction equations of
+    # Jacobi-Davidson (the comparison of section 8.2)
+    assert info["outer_its"] >= 1 and info["inner_its"] >= info["outer_its"]
+
+
+def test_si_lanczos_restarts_and_rejects_binary32():
+    # a basis of 20 for k = 8 forces restarts
+    L, W, seed, sigma, k = 14, 16.5, 2, 0.1, 8
+    ref = eig.anderson_nearest(L, W, seed, sigma, k)[0]
+    p = jd.Problem(L, W, seed, sigma, precision="fp64", jmax=20)
+    evals, _, resid, info = p.lanczos(k)
+    assert info["status"] == 0 and np.max(np.abs(evals - ref)) <= 1e-9
+    assert info["outer_its"] > 20
+    p.set_precision("mixed")
+    with pytest.raises(jd.JdError) as e:
+        p.lanczos(k)
+    assert e.value.code == jd.JD_ENOTIMPL
+    p.close()

@@ -85,6 +85,18 @@ def test_search_space_sizes_rejected(jd, jmin, jmax):
     assert rc == jd.JD_EINVAL and not h.value
 
 
+def test_set_allocator_arguments(jd):
+    lib = jd.lib()
+    fa = jd.ALLOC_FN(lambda n, s, c: None)
+    ff = jd.FREE_FN(lambda p, s, c: None)
+    a = ctypes.cast(fa, ctypes.c_void_p)
+    f = ctypes.cast(ff, ctypes.c_void_p)
+    assert lib.jd_set_allocator(a, None, None) == jd.JD_EINVAL
+    assert lib.jd_set_allocator(None, f, None) == jd.JD_EINVAL
+    assert lib.jd_set_allocator(a, f, None) == jd.JD_OK
+    assert lib.jd_set_allocator(None, None, None) == jd.JD_OK
+
+
 # --- host setup helpers --------------------------------------------------------------
 
 def _csr(A):
