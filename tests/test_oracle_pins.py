@@ -359,3 +359,24 @@ def test_hardwall_inertia_closed_form():
         assert np.min(np.abs(spec - tau)) > 1e-3
         neg, zero = ldlt.count_below(L, np.zeros(L ** 3), tau, bc="hardwall")
         assert zero == 0 and neg == int((spec < tau).sum())
+
+
+def test_stored_results_carry_inertia_certificates():
+    """Every stored oracle result (tests/golden, written by make_golden.py from the oracle
+    only) holds the Sylvester count of its window: exactly k eigenvalues lie within the
+    half-way point between the k-th and the (k+1)-th distance to sigma (section 5.1)."""
+    import glob
+    import json
+    import os
+    files = sorted(glob.glob(os.path.join(os.path.dirname(__file__), "golden", "*.json")))
+    assert len(files) >= 7
+    for path in files:
+        with open(path) as fh:
+            g = json.load(fh)
+        c = g["certificate"]
+        assert c["inertia_count"] == g["k"], path
+        lo, hi = c["window"]
+        lams = np.array(g["lams"])
+        assert np.all((lams > lo) & (lams < hi)), path
+        assert not (lo < g["next"] < hi), path
+        assert len(c["kato_temple"]) == g["k"] and max(c["kato_temple"]) < 1e-12, path
