@@ -53,3 +53,23 @@ def disorder(L, W, seed):
     """eps_s = W * (u_s - 1/2) for the L^3 sites, site order x fastest."""
     n = L * L * L
     return W * (uniform01(seed, n) - 0.5)
+
+
+def hoppings(L, W, seed):
+    """Random couplings of the off-diagonal ("inverse") Anderson model (section 8.2,
+    Table 6): each bond of the lattice carries its own value, uniform on [-W/2, W/2)
+    (the paper: [-1/2, 1/2], W = 1).  The bond from site s to its +x, +y, +z neighbour
+    (d = 0, 1, 2) takes output n + 3 s + d + 1 of the same stream as the diagonal, so the
+    two never share an output.  Returns t[d, s], shape (3, n)."""
+    n = L * L * L
+    u = (splitmix64(seed, 3 * n, first=n + 1) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    return (W * (u - 0.5)).reshape(n, 3).T.copy()
+
+
+# the constant diagonal of the off-diagonal model (section 8.2): its transition value
+OFFDIAG_DIAGONAL = 1.28
+
+
+def offdiag_model(L, W, seed):
+    """(eps, hop) of the off-diagonal model: constant diagonal 1.28, random bonds."""
+    return np.full(L * L * L, OFFDIAG_DIAGONAL), hoppings(L, W, seed)

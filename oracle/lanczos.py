@@ -19,7 +19,7 @@ from . import jacobi, lattice
 
 
 def si_lanczos(L, eps, sigma, k, solve, tol=1e-12, max_steps=None, seed=12345,
-               extra=2, bc="periodic"):
+               extra=2, bc="periodic", hop=None):
     """k + extra eigenpairs of A nearest sigma.
 
     ``solve(b)`` must return (A - sigma_f I)^{-1} b for a fixed sigma_f near sigma;
@@ -29,7 +29,7 @@ def si_lanczos(L, eps, sigma, k, solve, tol=1e-12, max_steps=None, seed=12345,
     n = L ** 3
     want = min(k + extra, n)
     sf = solve.shift
-    anorm = lattice.inf_norm(eps, L, bc)
+    anorm = lattice.inf_norm(eps, L, bc, hop)
     max_steps = min(n, max_steps or max(4 * want + 40, 80))
     rng = np.random.default_rng(seed)
     V = np.zeros((n, max_steps + 1))
@@ -57,7 +57,7 @@ def si_lanczos(L, eps, sigma, k, solve, tol=1e-12, max_steps=None, seed=12345,
                     continue
                 x = V[:, :m] @ S[:, p]
                 x /= np.linalg.norm(x)
-                ax = lattice.matvec(L, eps, x, bc=bc)
+                ax = lattice.matvec(L, eps, x, bc=bc, hop=hop)
                 lam = x @ ax  # Rayleigh quotient
                 lams.append(lam)
                 X.append(x)

@@ -151,13 +151,14 @@ class LDLT:
     soon as its Schur complement has been passed on.
     """
 
-    def __init__(self, L, eps, tau, leaf=256, keep_factors=True, bc="periodic"):
+    def __init__(self, L, eps, tau, leaf=256, keep_factors=True, bc="periodic", hop=None):
         self.L = L
         self.n = L ** 3
         self.tau = float(tau)
         self.bc = bc
+        self.hop = hop
         self.eps = np.asarray(eps, dtype=np.float64)
-        A = lattice.hamiltonian(L, self.eps, bc=bc)
+        A = lattice.hamiltonian(L, self.eps, bc=bc, hop=hop)
         A = A - self.tau * _sp_eye(self.n)
         A = A.tocsr()
         self.nodes = nested_dissection(L, leaf, bc)
@@ -233,7 +234,7 @@ class LDLT:
         b = np.asarray(b, dtype=np.float64)
         x = self._sweep(b)
         for _ in range(refine):
-            r = b - lattice.matvec(self.L, self.eps, x, shift=self.tau, bc=self.bc)
+            r = b - lattice.matvec(self.L, self.eps, x, shift=self.tau, bc=self.bc, hop=self.hop)
             x = x + self._sweep(r)
         return x
 
@@ -259,8 +260,8 @@ def _sp_eye(n):
     return sp.identity(n, format="csr")
 
 
-def count_below(L, eps, tau, leaf=256, bc="periodic"):
+def count_below(L, eps, tau, leaf=256, bc="periodic", hop=None):
     """Number of eigenvalues of A strictly below tau (inertia of A - tau I)."""
-    f = LDLT(L, eps, tau, leaf=leaf, keep_factors=False, bc=bc)
+    f = LDLT(L, eps, tau, leaf=leaf, keep_factors=False, bc=bc, hop=hop)
     neg, zero, _ = f.inertia()
     return neg, zero

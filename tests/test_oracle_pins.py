@@ -380,3 +380,96 @@ def test_stored_results_carry_inertia_certificates():
         assert np.all((lams > lo) & (lams < hi)), path
         assert not (lo < g["next"] < hi), path
         assert len(c["kato_temple"]) == g["k"] and max(c["kato_temple"]) < 1e-12, path
+
+
+# --- the off-diagonal ("inverse") model: random bond values (section 8.2, Table 6) --------
+
+def test_hoppings_generator():
+    L, W, seed = 5, 1.0, 3
+    n = L ** 3
+    t = generator.hoppings(L, W, seed)
+    assert t.shape == (3, n)
+    # bond (s, d) takes output n + 3 s + d + 1 of the stream: after the diagonal's outputs
+    for s_, d in ((0, 0), (7, 2), (n - 1, 1)):
+        u = (generator.splitmix64_scalar(seed, n + 3 * s_ + d + 1) >> 11) * 2.0 ** -53
+        assert t[d, s_] == W * (u - 0.5)
+    big = generator.hoppings(40, 1.0, 1)
+    assert big.min() >= -0.5 and big.max() < 0.5 and abs(big.mean()) < 5e-3
+
+
+@pytest.mark.parametrize("L,bc", [(2, "periodic"), (3, "periodic"), (5, "periodic"), (4, "hardwall")])
+def test_bond_values_reduce_to_the_constant_coupling(L, bc):
+    # hop = -1 on every bond is the diagonal model, entry by entry and product by product
+    e = generator.disorder(L, 16.5, 6)
+    hop = -np.ones((3, L ** 3))
+    A0 = lattice.hamiltonian(L, e, bc=bc)
+    A1 = lattice.hamiltonian(L, e, bc=bc, hop=hop)
+    assert abs(A0 - A1).max() == 0
+    x = np.random.default_rng(2).standard_normal(L ** 3)
+    assert np.allclose(lattice.matvec(L, e, x, 0.2, bc=bc, hop=hop), lattice.matvec(L, e, x, 0.2, bc=bc),
+                       atol=1e-13, rtol=0)
+    assert lattice.inf_norm(e, L, bc, hop) == lattice.inf_norm(e, L, bc)
+
+
+@pytest.mark.parametrize("L,bc", [(4, "periodic"), (5, "periodic"), (5, "hardwall")])
+def test_bond_values_structure(L, bc):
+    eps, hop = generator.offdiag_model(L, 1.0, 4)
+    A = lattice.hamiltonian(L, eps, bc=bc, hop=hop)
+    assert abs(A - A.T).max() == 0 and np.all(A.diagonal() == 1.28)
+    x = np.random.default_rng(L).standard_normal(L ** 3)
+    assert np.allclose(lattice.matvec(L, eps, x, -0.3, bc=bc, hop=hop), A @ x + 0.3 * x, atol=1e-13, rtol=0)
+    # entry of the bond from site s to s + e_x is hop[0, s]
+    s_ = 1 + L * (2 + L * 1)
+    assert A[s_, s_ + 1] == hop[0, s_]
+    assert np.isclose(lattice.inf_norm(eps, L, bc, hop), np.asarray(abs(A).sum(axis=1)).max())
+
+
+def _open_chain_bonds(f, t):
+    H = np.diag(f)
+    for i in range(len(f) - 1):
+        H[i, i + 1] = H[i + 1, i] = t[i]
+    return H
+
+
+def test_bond_values_kronecker_sum():
+    # hard walls, eps_ijk = f_i + g_j + h_k and x-bonds depending on i only (y on j, z on k):
+    # A is the Kronecker sum of three open chains with random bonds
+    L, sigma, k = 14, 0.15, 6
+    rng = np.random.default_rng(11)
+    f, g, h = (rng.uniform(-1.5, 1.5, L) for _ in range(3))
+    tx, ty, tz = (rng.uniform(-0.5, 0.5, L) for _ in range(3))
+    eps = (f[None, None, :] + g[None, :, None] + h[:, None, None]).reshape(-1)
+    ones = np.ones((L, L, L))
+    hop = np.stack([(ones * tx[None, None, :]).reshape(-1), (ones * ty[None, :, None]).reshape(-1),
+                    (ones * tz[:, None, None]).reshape(-1)])
+    ea, eb, ec = (jacobi.eigh(_open_chain_bonds(v, t), vectors=False)[0] for v, t in ((f, tx), (g, ty), (h, tz)))
+    sums = (ea[None, None, :] + eb[None, :, None] + ec[:, None, None]).reshape(-1)
+    ref = sums[eig.select_nearest(sums, sigma, k)]
+    lams, X, res, an = eig.nearest_eigenpairs(L, eps, sigma, k, bc="hardwall", hop=hop)
+    assert np.allclose(lams, ref, atol=1e-11, rtol=0)
+    assert res.max() <= 1e-12 * an
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_offdiag_gauge_symmetry(L):
+    # bipartite lattice (even L): flipping every bond sign leaves the spectrum, and a
+    # constant diagonal c makes it symmetric about c
+    eps, hop = generator.offdiag_model(L, 1.0, 5)
+    w = jacobi.eigh(lattice.hamiltonian(L, eps, hop=hop).toarray(), vectors=False)[0]
+    wf = jacobi.eigh(lattice.hamiltonian(L, eps, hop=-hop).toarray(), vectors=False)[0]
+    assert np.allclose(w, wf, atol=1e-12)
+    assert np.allclose(w - 1.28, -(w[::-1] - 1.28), atol=1e-12)
+
+
+@pytest.mark.parametrize("L,seed", [(4, 0), (6, 2), (7, 3)])
+def test_offdiag_inertia_and_lanczos(L, seed):
+    eps, hop = generator.offdiag_model(L, 1.0, seed)
+    A = lattice.hamiltonian(L, eps, hop=hop).toarray()
+    w = jacobi.eigh(A, vectors=False)[0]
+    for tau in (0.0, 1.1, 2.3):
+        neg, zero, pos = ldlt.LDLT(L, eps, tau, leaf=20, hop=hop).inertia()
+        assert neg == int((w < tau).sum()) and zero == 0
+    l1, X1, r1, an = eig.nearest_eigenpairs(L, eps, 0.0, 4, method="dense", hop=hop)
+    l2, X2, r2, _ = eig.nearest_eigenpairs(L, eps, 0.0, 4, method="lanczos", hop=hop)
+    assert np.allclose(l1, l2, atol=1e-12, rtol=0) and np.allclose(X1, X2, atol=1e-8)
+    assert r2.max() <= 1e-12 * an
