@@ -266,6 +266,23 @@ int jd_precond_factor_product(jd_precond *p, int precision, int transpose, const
 int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int pcols,
                             const double *d_b, double *d_x, double rtol, int maxit, int *its);
 
+/*
+ * jd_problem_linear_solve_noalloc -- jd_problem_linear_solve for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, hosts that
+ * forbid hipMalloc).  Same arguments, same kernels in the same order and the same result;
+ * it allocates nothing: no hipMalloc / hipFree, no pinned host memory, no events or
+ * graphs, and jd_set_allocator's hook is not called.  Its work buffers (the seven SQMR
+ * vectors, the solver state and reduction partials, Q in the inner precision, K^{-1} Q
+ * and the pcols x pcols projection matrix) live in one static device array of 64 MiB that
+ * every GPU the library runs on holds until the process ends; JD_EINVAL when a call needs
+ * more (about (7 + 2 pcols) n value-size bytes plus 2.1 MiB; e.g. n = 10^6 with binary32
+ * inner vectors allows pcols <= 4).  All calls on one GPU share that array and it keeps
+ * the last call's contents: calls that overlap on one GPU (from several threads or
+ * streams) race and must be serialised by the caller.  The host reads the stop flag
+ * synchronously every few steps.
+ */
+int jd_problem_linear_solve_noalloc(jd_problem *p, double shift, const double *d_Q, int pcols,
+                                    const double *d_b, double *d_x, double rtol, int maxit, int *its);
 
 /*
  * Serving: continuous batching of independent solve requests (the disorder averaging

@@ -78,7 +78,7 @@ EXPORTS = ["jd_solve", "jd_setup", "jd_problem_solve", "jd_problem_info", "jd_pr
            "jd_problem_linear_solve", "jd_last_error", "jd_version", "jd_server_create", "jd_server_submit",
            "jd_server_poll", "jd_server_wait", "jd_server_footprint", "jd_server_destroy",
            "jd_host_matching", "jd_host_split_cycles", "jd_host_factor", "jd_set_allocator",
-           "jd_problem_lanczos"]
+           "jd_problem_linear_solve_noalloc", "jd_problem_lanczos"]
 
 _lib = None
 
@@ -113,6 +113,7 @@ def lib():
         "jd_precond_factor_product": (I, [P, I, I, P, P, P]),
         "jd_precond_segments": (I, [P, I, P, P, P]),
         "jd_problem_linear_solve": (I, [P, D, P, I, P, P, D, I, ctypes.POINTER(I)]),
+        "jd_problem_linear_solve_noalloc": (I, [P, D, P, I, P, P, D, I, ctypes.POINTER(I)]),
         "jd_server_create": (I, [ctypes.c_size_t, I, I, ctypes.POINTER(P)]),
         "jd_server_submit": (I, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
         "jd_server_poll": (I, [P, ctypes.c_uint64, ctypes.POINTER(Result)]),
@@ -249,8 +250,9 @@ class Problem:
         _check(rc, allow_partial=True)
         return evals, (evecs.T if vectors else None), resid, dict(info.as_dict(), status=rc)
 
-    def linear_solve(self, shift, b, x, Q=None, rtol=1e-8, maxit=200):
-        """Q: (n, p) device tensor of orthonormal columns (laid out column-major for the ABI)."""
+    def linear_solve(self, shift, b, x, Q=None, rtol=1e-8, maxit=200, noalloc=False):
+        """Q: (n, p) device tensor of orthonormal columns (laid out column-major for the ABI).
+        noalloc: jd_problem_linear_solve_noalloc (static scratch, allocates nothing)."""
         its = ctypes.c_int(0)
         if Q is not None and (len(Q.shape) != 2 or int(Q.shape[0]) != self.n):
             raise ValueError(f"Q: shape {tuple(Q.shape)}, expected ({self.n}, p)")
@@ -259,8 +261,8 @@ class Problem:
         qp = _dev(Qc, "torch.float64", self.n * p, "Q")
         bp = _dev(b, "torch.float64", self.n, "b")
         xp = _dev(x, "torch.float64", self.n, "x")
-        _check(lib().jd_problem_linear_solve(self._h, float(shift), qp, p, bp, xp, float(rtol), int(maxit),
-                                             ctypes.byref(its)))
+        fn = lib().jd_problem_linear_solve_noalloc if noalloc else lib().jd_problem_linear_solve
+        _check(fn(self._h, float(shift), qp, p, bp, xp, float(rtol), int(maxit), ctypes.byref(its)))
         return its.value
 
     def close(self):

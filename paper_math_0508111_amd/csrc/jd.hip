@@ -558,6 +558,7 @@ struct Solver {
     hipEvent_t ev[2] = {nullptr, nullptr};
     struct Pair { hipGraphExec_t init = nullptr, step = nullptr; const T *Qt = nullptr, *Y = nullptr; const double *M = nullptr; };
     std::vector<Pair> cache;
+    bool noalloc = false;
 
     Solver(Setup &S_, const P &pc_, const T *eps_, bool graphs_)
         : S(S_), pc(pc_), eps(eps_), s(S_.stream), n(S_.n), graphs(graphs_), mem(S_.stream)
@@ -582,8 +583,17 @@ struct Solver {
         HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
         cache.resize(130);
     }
+    // Buffers supplied by the caller (every device pointer of bufs; flags_host unused):
+    // nothing is allocated, no events or graphs are created, and the host reads the stop
+    // flag synchronously after every few steps instead of one step behind.
+    Solver(Setup &S_, const P &pc_, const T *eps_, const SqmrBufs<T> &bufs)
+        : S(S_), pc(pc_), eps(eps_), s(S_.stream), n(S_.n), graphs(false), B(bufs), mem(S_.stream), noalloc(true)
+    {
+        B.flags_host = nullptr;
+    }
     ~Solver()
     {
+        if (noalloc) return;
         std::lock_guard<std::mutex> g(dev_mutex());
         for (auto &c : cache) {
             if (c.init) (void)hipGraphExecDestroy(c.init);
@@ -642,6 +652,27 @@ struct Solver {
     int sqmr(double shift, const T *Qt, const T *Y, int p, const double *dM, double rtol, int maxit)
     {
         jdmi::launch_sqmr_params(B.st, shift, rtol, s);
+        if (noalloc) {
+            // steps after the one that stops are skipped on the device, so checking the
+            // flag every kCheck steps launches a few empty steps and changes no result
+            constexpr int kCheck = 4;
+            enqueue_init(Qt, Y, p, dM);
+            int launched = 0;
+            while (launched < maxit) {
+                const int batch = std::min(kCheck, maxit - launched);
+                for (int i = 0; i < batch; ++i) enqueue_step(Qt, Y, p, dM);
+                launched += batch;
+                int done = 0;
+                HIPCHK(hipMemcpyAsync(&done, &B.st->done, sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                if (done) break;
+            }
+            HIPCHK(hipGetLastError());
+            jdmi::SqmrState hs;
+            HIPCHK(hipMemcpyAsync(&hs, B.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            return hs.j;
+        }
         Pair *pr = nullptr;
         if (graphs) {
             if (p >= int(cache.size())) throw JdError(JD_EINVAL, "projection too wide");
@@ -1272,7 +1303,36 @@ int linear_solve_core(Solver<T, PC> &sv, double shift, const double *d_Q, int pc
     return k;
 }
 
+// Scratch of the allocation-free entry point: one static device array, held by every
+// GPU the library runs on until the process ends.  Host code never uses the array's
+// name as an address: each device's copy is looked up once, with that device current,
+// and its address kept per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
 
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+void *scratch_address()
+{
+    static std::mutex m;
+    static void *addr[kMaxDevices] = {};
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw JdError(JD_EDEVICE, "device ordinal out of range");
+    std::lock_guard<std::mutex> g(m);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            throw JdError(JD_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        addr[dev] = ptr;
+    }
+    return addr[dev];
+}
 
 }  // namespace
 struct jd_precond {
@@ -1684,6 +1744,60 @@ int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int 
             std::vector<double> Mh(size_t(pcols) * pcols + 1), work(size_t(pcols) * pcols + 1), h(pcols + 1);
             const int k_ = linear_solve_core(sv, shift, d_Q, pcols, d_b, d_x, rtol, maxit, Qt, Y, dM, Mh.data(),
                                              work.data(), h.data());
+            if (its) *its = k_;
+        };
+        if (S.opt.precision == JD_MIXED) run(float(0), S.pc32, S.eps32);
+        else if (S.opt.precision == JD_MIXED_FACTORS) run(double(0), MixedPrecond{S.pc32, S.pc64}, S.eps64);
+        else run(double(0), S.pc64, S.eps64);
+        return JD_OK;
+    });
+}
+
+int jd_problem_linear_solve_noalloc(jd_problem *p, double shift, const double *d_Q, int pcols, const double *d_b,
+                                    double *d_x, double rtol, int maxit, int *its)
+{
+    return guarded([&] {
+        check_linear_solve_args(p, shift, d_Q, pcols, d_b, d_x, rtol, maxit);
+        Setup &S = p->S;
+        const int n = S.n;
+        unsigned char *base = static_cast<unsigned char *>(scratch_address());
+        auto run = [&](auto tag, const auto &pc, const auto *eps) {
+            using T = decltype(tag);
+            using PC = std::decay_t<decltype(pc)>;
+            // carve the scratch array: reduction partials and small results, the solver
+            // state, the seven SQMR vectors, the projection blocks Qt and Y, and M
+            size_t off = 0;
+            auto take = [&](size_t bytes) {
+                const size_t at = off;
+                off += (bytes + 255) / 256 * 256;
+                return at;
+            };
+            const size_t pc1 = size_t(std::max(pcols, 1));
+            const size_t o_partial = take(sizeof(double) * 256 * jdmi::kRedBlocks);
+            const size_t o_red = take(sizeof(double) * 256), o_coef = take(sizeof(double) * 256);
+            const size_t o_g = take(sizeof(double) * 256), o_st = take(sizeof(jdmi::SqmrState));
+            size_t o_vec[7];
+            for (auto &o : o_vec) o = take(sizeof(T) * size_t(n));
+            const size_t o_qt = take(sizeof(T) * size_t(n) * pc1), o_y = take(sizeof(T) * size_t(n) * pc1);
+            const size_t o_m = take(sizeof(double) * pc1 * pc1);
+            if (off > kScratchBytes)
+                throw JdError(JD_EINVAL, "the allocation-free linear solve needs " + std::to_string(off) +
+                                             " bytes of scratch for this problem and projection width; it holds " +
+                                             std::to_string(kScratchBytes));
+            SqmrBufs<T> B{};
+            B.partial = reinterpret_cast<double *>(base + o_partial);
+            B.red = reinterpret_cast<double *>(base + o_red);
+            B.coef = reinterpret_cast<double *>(base + o_coef);
+            B.g = reinterpret_cast<double *>(base + o_g);
+            B.st = reinterpret_cast<jdmi::SqmrState *>(base + o_st);
+            T **vec[7] = {&B.r, &B.q, &B.t, &B.d, &B.x, &B.u, &B.b};
+            for (int i = 0; i < 7; ++i) *vec[i] = reinterpret_cast<T *>(base + o_vec[i]);
+            Solver<T, PC> sv(S, pc, eps, B);
+            // the p x p matrices live on the stack (p <= 64)
+            double Mh[64 * 64 + 1], work[64 * 64 + 1], h[65];
+            const int k_ = linear_solve_core(sv, shift, d_Q, pcols, d_b, d_x, rtol, maxit,
+                                             reinterpret_cast<T *>(base + o_qt), reinterpret_cast<T *>(base + o_y),
+                                             reinterpret_cast<double *>(base + o_m), Mh, work, h);
             if (its) *its = k_;
         };
         if (S.opt.precision == JD_MIXED) run(float(0), S.pc32, S.eps32);
