@@ -36,6 +36,13 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=16, help="0 disables the serving leg")
     ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--serve-warmup", type=int, default=8,
+                    help="closed-loop requests that measure the saturated rate before the Poisson stream")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the serving stream (for long streams such as the 256-request mix)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="preconditioner parameter study (kappa, epsilon, z_drop, last-level size, segments) "
+                         "at the benchmark lattice: one JSON line per setting")
     ap.add_argument("--kernels-only", action="store_true",
                     help="setup, then only launches of the dominant kernel and a 256 MB copy "
                          "(for hardware counter runs)")
@@ -191,6 +198,54 @@ def apply_roofline(torch, prob, n, reps=20):
             "method_frac": round(method / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+SWEEP = [dict()] + [dict(kappa=v) for v in (2.5, 10.0, 20.0)] + [dict(drop_tol=v) for v in (1e-2, 5e-3, 2.5e-3)] \
+    + [dict(z_drop=v) for v in (2e-2, 5e-3)] + [dict(coarse_max=v) for v in (4096, 8192)] \
+    + [dict(z_parts=v) for v in (1, 4, 8)]
+
+
+def sweep(jd, torch, L, k, tol=1e-10):
+    """Table 5 of the paper, on the GPU: the multilevel preconditioner's parameters one at
+    a time around the defaults (kappa 5, epsilon 1/sqrt(n), z_drop min(1e-2, 10 epsilon),
+    last level <= 1536, 6 segments): setup time, levels, fill, nnz of the coupling blocks
+    and of the inverse factor's segments, the binary32 apply, and the solves."""
+    import numpy as np
+    n = L ** 3
+    rows = []
+    for cfg in SWEEP:
+        t0 = time.time()
+        prob = jd.Problem(L, 16.5, 0, 0.0, precision="mixed", **cfg)
+        setup = time.time() - t0
+        pc = prob.precond()
+        lv, seg = pc.levels(), pc.segments()
+        s = torch.cuda.current_stream()
+        x = torch.randn(n, dtype=torch.float32, device="cuda")
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            pc.apply(x, y, "mixed", stream=s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(10):
+            pc.apply(x, y, "mixed", stream=s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        info = prob.info()
+        row = {"setting": cfg or "defaults", "setup_s": round(setup, 2), "levels": info["levels"],
+               "coarse_n": info["coarse_n"], "fill": round(info["fill"], 3), "nnz_G": int(sum(lv["nnzG"])),
+               "nnz_Z": int(pc.factor_nnz()), "segments": seg["segments"], "device_bytes": int(info["device_bytes"]),
+               "apply_us": round(e0.elapsed_time(e1) * 100, 1)}
+        pc.close()
+        for prec in ("mixed", "fp64"):
+            prob.set_precision(prec)
+            ev, _, res, i2 = prob.solve(k, tol)
+            row[prec] = {"solve_s": round(i2["solve_s"], 3), "outer": i2["outer_its"], "inner": i2["inner_its"],
+                         "converged": i2["n_converged"], "max_resid": float(np.nanmax(res))}
+        prob.close()
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+    return rows
+
+
 def serving(jd, nreq, workers, warm=8):
     """Continuous batching of the mixed request stream: a closed-loop warm-up measures
     the saturated request rate, then nreq requests arrive as a Poisson process at 0.8
@@ -322,6 +377,12 @@ def main():
     if a.kernels_only:
         kernels_only(jd, torch, a.L)
         return
+    if a.sweep:
+        print(json.dumps({"sweep": sweep(jd, torch, a.L, a.k), "L": a.L, "k": a.k}), flush=True)
+        return
+    if a.serve_only:
+        print(json.dumps({"serving": serving(jd, a.serve_requests, a.serve_workers, a.serve_warmup)}), flush=True)
+        return
     L, W, seed, sigma, k, tol = a.L, 16.5, 0, 0.0, a.k, 1e-10
     t0 = time.time()
     prob = jd.Problem(L, W, seed, sigma, precision="mixed")
@@ -410,7 +471,7 @@ def main():
             print(f"# seed {sd}: setup {i2['setup_s']:.1f} s, solve {i2['solve_s']:.3f} s, outer {i2['outer_its']}, "
                   f"inner {i2['inner_its']}, converged {i2['n_converged']}", file=sys.stderr, flush=True)
     if a.serve_requests > 0:
-        out["serving"] = serving(jd, a.serve_requests, a.serve_workers)
+        out["serving"] = serving(jd, a.serve_requests, a.serve_workers, a.serve_warmup)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(k, L)
     print(json.dumps(out), flush=True)

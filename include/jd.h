@@ -53,6 +53,13 @@ enum { JD_FP64 = 0, JD_MIXED = 1, JD_MIXED_FACTORS = 2 };
  * zeros, so a site on a face has no coupling across it). */
 enum { JD_BC_PERIODIC = 0, JD_BC_HARDWALL = 1 };
 
+/* The model (section 8.2, Table 6).  JD_MODEL_ANDERSON: random diagonal of width W,
+ * couplings -1 (section 3).  JD_MODEL_OFFDIAG, the off-diagonal ("inverse") model:
+ * constant diagonal 1.28 and a random value on every bond, uniform on [-W/2, W/2)
+ * (W = 1: the paper's [-1/2, 1/2]); the bond from site s to its +x, +y, +z neighbour
+ * (d = 0, 1, 2) takes output n + 3 s + d + 1 of the SplitMix64 stream of `seed`. */
+enum { JD_MODEL_ANDERSON = 0, JD_MODEL_OFFDIAG = 1 };
+
 /*
  * Options; a zero-initialised struct selects every default.
  *  precision  JD_FP64: every step in binary64.  JD_MIXED: stencil SpMV in
@@ -100,8 +107,9 @@ enum { JD_BC_PERIODIC = 0, JD_BC_HARDWALL = 1 };
  *             same results; the serving workers always launch kernel by kernel).
  *             bit 1 (JD_FLAG_LEVELS): apply the factorisation level by level (two
  *             dependent sparse passes per level) instead of through Z.
- *  bc         JD_BC_PERIODIC (0) or JD_BC_HARDWALL; ||A||_inf is then the largest row
- *             sum, couplings (6 on the torus, fewer on the faces of the box) plus |eps|.
+ *  bc         JD_BC_PERIODIC (0) or JD_BC_HARDWALL.  ||A||_inf is the largest row sum
+ *             of |entries| (6 + max|eps| for the diagonal model on the torus).
+ *  model      JD_MODEL_ANDERSON (0) or JD_MODEL_OFFDIAG.
  *  stream     stream for the solve's device work (NULL: a library-created blocking stream).
  */
 typedef struct jd_options {
@@ -119,6 +127,7 @@ typedef struct jd_options {
     int flags;
     int z_parts;
     int bc;
+    int model;
     void *stream;
 } jd_options;
 
@@ -202,13 +211,20 @@ void jd_problem_free(jd_problem *p);
  */
 int jd_gen_diag(int L, double W, uint64_t seed, double *d_eps, float *d_eps32, void *stream);
 
+/* jd_gen_hop -- the bond values of the off-diagonal model (see JD_MODEL_OFFDIAG) into
+ * a device array d_hop[d n + s] of 3 n binary64 values (bond from s to s + e_d), and
+ * their binary32 rounding (d_hop32 may be NULL). */
+int jd_gen_hop(int L, double W, uint64_t seed, double *d_hop, float *d_hop32, void *stream);
+
 /*
  * jd_stencil_spmv -- y = (A - shift I) x on the lattice (section 3,
- * eq. (eigenequation)); only eps is stored, the couplings are implicit.
+ * eq. (eigenequation)); only eps (and, for the off-diagonal model, the bond values)
+ * is stored, the lattice structure is implicit.
  *   bc JD_BC_PERIODIC or JD_BC_HARDWALL (section 8.2).
- *   precision JD_FP64: d_eps, d_x, d_y are double*; JD_MIXED: float*.
+ *   d_hop NULL: couplings -1; else 3 n bond values laid out as by jd_gen_hop.
+ *   precision JD_FP64: d_eps, d_hop, d_x, d_y are double*; JD_MIXED: float*.
  */
-int jd_stencil_spmv(int L, int bc, int precision, const void *d_eps, double shift,
+int jd_stencil_spmv(int L, int bc, int precision, const void *d_eps, const void *d_hop, double shift,
                     const void *d_x, void *d_y, void *stream);
 
 /*
@@ -304,6 +320,7 @@ typedef struct jd_request {
     int precision;    /* JD_FP64, JD_MIXED or JD_MIXED_FACTORS */
     int flags;        /* jd_options flags (JD_FLAG_LEVELS; JD_FLAG_GRAPHS is ignored) */
     int bc;           /* JD_BC_PERIODIC or JD_BC_HARDWALL */
+    int model;        /* JD_MODEL_ANDERSON or JD_MODEL_OFFDIAG */
 } jd_request;
 
 typedef struct jd_result {

@@ -20,6 +20,9 @@ JD_FP64, JD_MIXED, JD_MIXED_FACTORS = 0, 1, 2
 JD_BC_PERIODIC, JD_BC_HARDWALL = 0, 1
 _BC = {"periodic": JD_BC_PERIODIC, "hardwall": JD_BC_HARDWALL, JD_BC_PERIODIC: JD_BC_PERIODIC,
        JD_BC_HARDWALL: JD_BC_HARDWALL}
+JD_MODEL_ANDERSON, JD_MODEL_OFFDIAG = 0, 1
+_MODEL = {"anderson": JD_MODEL_ANDERSON, "offdiag": JD_MODEL_OFFDIAG, JD_MODEL_ANDERSON: JD_MODEL_ANDERSON,
+          JD_MODEL_OFFDIAG: JD_MODEL_OFFDIAG}
 JD_FLAG_GRAPHS = 1
 JD_FLAG_LEVELS = 2
 _PREC = {"fp64": JD_FP64, "mixed": JD_MIXED, "mixed_factors": JD_MIXED_FACTORS, JD_FP64: JD_FP64,
@@ -38,13 +41,13 @@ class Options(ctypes.Structure):
                 ("max_levels", ctypes.c_int), ("z_drop", ctypes.c_double), ("jmin", ctypes.c_int), ("jmax", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int), ("switch_tol", ctypes.c_double),
                 ("flags", ctypes.c_int), ("z_parts", ctypes.c_int), ("bc", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("model", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 class Request(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int), ("W", ctypes.c_double), ("seed", ctypes.c_uint64), ("sigma", ctypes.c_double),
                 ("k", ctypes.c_int), ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("flags", ctypes.c_int),
-                ("bc", ctypes.c_int)]
+                ("bc", ctypes.c_int), ("model", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -78,7 +81,7 @@ EXPORTS = ["jd_solve", "jd_setup", "jd_problem_solve", "jd_problem_info", "jd_pr
            "jd_problem_linear_solve", "jd_last_error", "jd_version", "jd_server_create", "jd_server_submit",
            "jd_server_poll", "jd_server_wait", "jd_server_footprint", "jd_server_destroy",
            "jd_host_matching", "jd_host_split_cycles", "jd_host_factor", "jd_set_allocator",
-           "jd_problem_linear_solve_noalloc", "jd_problem_lanczos"]
+           "jd_problem_linear_solve_noalloc", "jd_problem_lanczos", "jd_gen_hop"]
 
 _lib = None
 
@@ -103,7 +106,8 @@ def lib():
         "jd_problem_set_solve_options": (I, [P, OP]),
         "jd_problem_free": (None, [P]),
         "jd_gen_diag": (I, [I, D, U64, P, P, P]),
-        "jd_stencil_spmv": (I, [I, I, I, P, D, P, P, P]),
+        "jd_stencil_spmv": (I, [I, I, I, P, P, D, P, P, P]),
+        "jd_gen_hop": (I, [I, D, U64, P, P, P]),
         "jd_precond_create": (I, [I, D, U64, D, OP, ctypes.POINTER(P)]),
         "jd_precond_apply": (I, [P, I, P, P, P]),
         "jd_precond_levels": (I, [P, I, P, P, P]),
@@ -143,7 +147,7 @@ def make_options(precision="fp64", stream=None, **kw):
     o.precision = _PREC[precision]
     for k, v in kw.items():
         if v is not None:
-            setattr(o, k, _BC[v] if k == "bc" else v)
+            setattr(o, k, _BC[v] if k == "bc" else _MODEL[v] if k == "model" else v)
     if stream is not None:
         o.stream = ctypes.c_void_p(_stream_ptr(stream))
     return o
@@ -348,12 +352,18 @@ def gen_diag(L, W, seed, eps64, eps32=None, stream=None):
                              _dev(eps32, "torch.float32", n, "eps32"), _stream_ptr(stream)))
 
 
-def stencil_spmv(L, eps, shift, x, y, precision="fp64", stream=None, bc="periodic"):
+def gen_hop(L, W, seed, hop64, hop32=None, stream=None):
+    n = int(L) ** 3
+    _check(lib().jd_gen_hop(L, float(W), seed, _dev(hop64, "torch.float64", 3 * n, "hop64"),
+                            _dev(hop32, "torch.float32", 3 * n, "hop32"), _stream_ptr(stream)))
+
+
+def stencil_spmv(L, eps, shift, x, y, precision="fp64", stream=None, bc="periodic", hop=None):
     n = int(L) ** 3
     pr = _PREC[precision]
     dt = _VEC_DTYPE.get(pr)
-    _check(lib().jd_stencil_spmv(L, _BC[bc], pr, _dev(eps, dt, n, "eps"), float(shift), _dev(x, dt, n, "x"),
-                                 _dev(y, dt, n, "y"), _stream_ptr(stream)))
+    _check(lib().jd_stencil_spmv(L, _BC[bc], pr, _dev(eps, dt, n, "eps"), _dev(hop, dt, 3 * n, "hop"), float(shift),
+                                 _dev(x, dt, n, "x"), _dev(y, dt, n, "y"), _stream_ptr(stream)))
 
 
 def version():
@@ -419,9 +429,9 @@ class Server:
         self._h = h
 
     @staticmethod
-    def request(L, W, seed, sigma, k, tol=1e-10, precision="mixed", flags=0, bc="periodic"):
+    def request(L, W, seed, sigma, k, tol=1e-10, precision="mixed", flags=0, bc="periodic", model="anderson"):
         return Request(int(L), float(W), int(seed), float(sigma), int(k), float(tol), _PREC[precision], int(flags),
-                       _BC[bc])
+                       _BC[bc], _MODEL[model])
 
     def submit(self, req):
         t = ctypes.c_uint64()

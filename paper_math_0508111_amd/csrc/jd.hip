@@ -283,6 +283,15 @@ struct MixedPrecond {
 struct Setup {
     int L = 0, n = 0;
     int bc = JD_BC_PERIODIC;
+    int model = JD_MODEL_ANDERSON;
+    double *hop64 = nullptr;  // bond values of the off-diagonal model (3 n), else NULL
+    float *hop32 = nullptr;
+    template <typename T>
+    const T *hop() const
+    {
+        if constexpr (std::is_same<T, float>::value) return hop32;
+        else return hop64;
+    }
     double W = 0, sigma = 0;
     uint64_t seed = 0;
     jd_options opt{};
@@ -298,6 +307,9 @@ struct Setup {
     double setup_s = 0;
     int n2x2 = 0;
 };
+
+// The constant diagonal of the off-diagonal model (section 8.2: its transition value).
+constexpr double kOffdiagDiagonal = 1.28;
 
 // Default search-space sizes.  On large lattices the eigenvalues near sigma are
 // ~1 / (n rho) apart and a larger space carries the outer iteration further per
@@ -353,6 +365,7 @@ void check_problem_args(int L, double W, double sigma, const jd_options *opt)
         if (opt->max_inner < 0 || opt->max_outer < 0 || opt->max_levels < 0) throw JdError(JD_EINVAL, "negative iteration cap");
         if (opt->flags & ~(JD_FLAG_GRAPHS | JD_FLAG_LEVELS)) throw JdError(JD_EINVAL, "unknown flag bits");
         if (opt->bc != JD_BC_PERIODIC && opt->bc != JD_BC_HARDWALL) throw JdError(JD_EINVAL, "unknown boundary condition");
+        if (opt->model != JD_MODEL_ANDERSON && opt->model != JD_MODEL_OFFDIAG) throw JdError(JD_EINVAL, "unknown model");
         if (opt->z_parts < 0 || opt->z_parts > 32) throw JdError(JD_EINVAL, "z_parts must be in [0, 32]");
         if (!std::isfinite(opt->z_drop)) throw JdError(JD_EINVAL, "non-finite option");
         if (!std::isfinite(opt->drop_tol) || !std::isfinite(opt->kappa) || opt->kappa < 0 ||
@@ -411,25 +424,38 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
     const int n = S.n;
     S.eps64 = S.mem.alloc<double>(n);
     S.eps32 = S.mem.alloc<float>(n);
-    jdmi::launch_gen_diag(L, W, seed, S.eps64, S.eps32, S.stream);
-    HIPCHK(hipGetLastError());
-    std::vector<double> eps(n);
-    HIPCHK(hipMemcpyAsync(eps.data(), S.eps64, n * sizeof(double), hipMemcpyDeviceToHost, S.stream));
-    HIPCHK(hipStreamSynchronize(S.stream));
-    // ||A||_inf: the largest row sum, couplings (6 on the torus; fewer on the faces of a
-    // box with hard walls) plus |eps|
     S.bc = S.opt.bc;
+    S.model = S.opt.model;
+    std::vector<double> eps(n), hop;
+    if (S.model == JD_MODEL_OFFDIAG) {
+        // section 8.2: constant diagonal, random bond values of width W
+        std::fill(eps.begin(), eps.end(), kOffdiagDiagonal);
+        std::vector<float> e32(n, float(kOffdiagDiagonal));
+        HIPCHK(hipMemcpyAsync(S.eps64, eps.data(), n * sizeof(double), hipMemcpyHostToDevice, S.stream));
+        HIPCHK(hipMemcpyAsync(S.eps32, e32.data(), n * sizeof(float), hipMemcpyHostToDevice, S.stream));
+        S.hop64 = S.mem.alloc<double>(3 * size_t(n));
+        S.hop32 = S.mem.alloc<float>(3 * size_t(n));
+        jdmi::launch_gen_hop(L, W, seed, S.hop64, S.hop32, S.stream);
+        HIPCHK(hipGetLastError());
+        hop.resize(3 * size_t(n));
+        HIPCHK(hipMemcpyAsync(hop.data(), S.hop64, hop.size() * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+        HIPCHK(hipStreamSynchronize(S.stream));
+    } else {
+        jdmi::launch_gen_diag(L, W, seed, S.eps64, S.eps32, S.stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(eps.data(), S.eps64, n * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+        HIPCHK(hipStreamSynchronize(S.stream));
+    }
+    jdmi::Csr A = jdmi::anderson_shifted(L, eps.data(), sigma, S.bc, hop.empty() ? nullptr : hop.data());
+    // ||A||_inf: the largest row sum of |entries| (couplings and |eps|)
     double anorm = 0;
     for (int s = 0; s < n; ++s) {
-        int deg = 6;
-        if (S.bc == JD_BC_HARDWALL) {
-            const int i = s % L, j = (s / L) % L, k = s / (L * L);
-            deg = (i > 0) + (i < L - 1) + (j > 0) + (j < L - 1) + (k > 0) + (k < L - 1);
-        }
-        anorm = std::max(anorm, deg + std::fabs(eps[s]));
+        double row = std::fabs(eps[s]);
+        for (int64_t p = A.ptr[s]; p < A.ptr[s + 1]; ++p)
+            if (A.col[p] != s) row += std::fabs(A.val[p]);
+        anorm = std::max(anorm, row);
     }
     S.anorm = anorm;
-    jdmi::Csr A = jdmi::anderson_shifted(L, eps.data(), sigma, S.bc);
     jdmi::SetupParams prm;
     prm.drop_tol = S.opt.drop_tol;
     prm.kappa = S.opt.kappa;
@@ -619,7 +645,7 @@ struct Solver {
         const int *skip_a = &B.st->done;
         const int *skip_b = &B.st->done_next;
         // t = (I - Qt Qt^T)(A - shift I) q
-        jdmi::launch_stencil_state<T>(S.L, S.bc, eps, B.st, B.q, B.t, s);
+        jdmi::launch_stencil_state<T>(S.L, S.bc, eps, B.st, B.q, B.t, s, S.template hop<T>());
         if (p > 0) {
             jdmi::launch_multidot<T>(n, p, Qt, n, B.t, B.partial, B.coef, s, skip_a);
             jdmi::launch_sub_qc<T>(n, p, Qt, n, B.coef, B.t, s, skip_a);
@@ -773,7 +799,7 @@ void emit_outputs(Setup &S, const double *Q, const std::vector<double> &lam, int
         const int q = idx[c];
         out.evals[c] = lam[q];
         if (out.resid) {
-            jdmi::launch_stencil<double>(S.L, S.bc, S.eps64, 0.0, Q + size_t(q) * n, Au, s);
+            jdmi::launch_stencil<double>(S.L, S.bc, S.eps64, 0.0, Q + size_t(q) * n, Au, s, nullptr, S.hop64);
             jdmi::launch_axpby_d(n, -lam[q], Q + size_t(q) * n, 1.0, Au, s);
             jdmi::launch_dot<double>(n, Au, Au, partial, red, s);
             double rr;
@@ -841,15 +867,23 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
     double *V = mem.alloc<double>(size_t(n) * jmax);
     double *AV = mem.alloc<double>(size_t(n) * jmax);
     double *V2 = mem.alloc<double>(size_t(n) * jmax);  // restart / deflation target
-    double *Q = mem.alloc<double>(size_t(n) * k);
+    // Locked pairs need not arrive in the order of their distance to sigma (two nearly
+    // equidistant eigenvalues can swap).  After k are locked the iteration goes on with
+    // the next pair until a guard residual places it farther than the k-th locked value;
+    // a nearer one found meanwhile is locked too (at most kx beyond k), and the k nearest
+    // locked pairs are returned.
+    const int kx = std::min(3, n - k);
+    const int kq = k + kx;
+    const double guard_tol = std::min(1e-8, 100.0 * tol);
+    double *Q = mem.alloc<double>(size_t(n) * kq);
     double *t64 = mem.alloc<double>(n);
     double *u64 = mem.alloc<double>(n);
     double *Au64 = mem.alloc<double>(n);
     double *r64 = mem.alloc<double>(n);
-    T *Qt = mem.alloc<T>(size_t(n) * (k + 1));
-    T *Y = mem.alloc<T>(size_t(n) * (k + 1));
+    T *Qt = mem.alloc<T>(size_t(n) * (kq + 1));
+    T *Y = mem.alloc<T>(size_t(n) * (kq + 1));
     double *dsm = mem.alloc<double>(size_t(jmax) * jmax);  // small matrices / vectors
-    double *dM = mem.alloc<double>(size_t(k + 1) * (k + 1));
+    double *dM = mem.alloc<double>(size_t(kq + 1) * (kq + 1));
     double *partial = sv.B.partial;
     double *red = mem.alloc<double>(256);
 
@@ -869,8 +903,19 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
     jdmi::launch_convert<T, double>(n, sv.B.u, t64, 1.0, s);
 
     int m = 0, nq = 0, outer = 0, inner_total = 0, solves_this_pair = 0;
-    std::vector<double> H(size_t(jmax) * jmax, 0.0), lam(k, 0.0);
-    std::vector<double> Hq(size_t(k + 1) * (k + 1), 0.0);
+    // block start: the first min(k, jmin) directions are preconditioned random vectors.
+    // One start vector has a component along one direction of each eigenspace only, so a
+    // degenerate cluster (the clean lattice, W = 0) could be found incompletely.
+    int start_left = std::min(k, jmin) - 1;
+    std::vector<double> H(size_t(jmax) * jmax, 0.0), lam(kq, 0.0);
+    std::vector<double> Hq(size_t(kq + 1) * (kq + 1), 0.0);
+    // distance to sigma of the k-th nearest locked value
+    auto kth_locked = [&]() {
+        std::vector<double> d(nq);
+        for (int i = 0; i < nq; ++i) d[i] = std::fabs(lam[i] - sigma);
+        std::nth_element(d.begin(), d.begin() + (k - 1), d.end());
+        return d[k - 1];
+    };
     std::vector<double> hw, hZ, hcol(256);
     bool finished = false;
     while (!finished && outer < max_outer) {
@@ -896,7 +941,7 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
         }
         jdmi::launch_scale_by_inv_sqrt(n, red, t64, s);
         HIPCHK(hipMemcpyAsync(V + size_t(m) * n, t64, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        jdmi::launch_stencil<double>(S.L, S.bc, S.eps64, 0.0, V + size_t(m) * n, AV + size_t(m) * n, s);
+        jdmi::launch_stencil<double>(S.L, S.bc, S.eps64, 0.0, V + size_t(m) * n, AV + size_t(m) * n, s, nullptr, S.hop64);
         jdmi::launch_multidot<double>(n, m + 1, V, n, AV + size_t(m) * n, partial, red, s);
         d2h(hcol.data(), red, m + 1);
         for (int i = 0; i <= m; ++i) {
@@ -933,9 +978,17 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
             d2h(&rr, red, 1);
             rnorm = std::sqrt(std::max(rr, 0.0));
             bool locked = false;
+            // guard: with k pairs locked, the next Ritz pair is converged only far enough
+            // to place its eigenvalue (within rnorm of theta, ||u|| = 1): if that is
+            // farther from sigma than the k-th locked one, the k locked are the nearest
+            // the iteration finds; otherwise the pair is locked and the k nearest kept
+            if (nq >= k && rnorm <= guard_tol * anorm && std::fabs(theta - sigma) - rnorm > kth_locked()) {
+                finished = true;
+                break;
+            }
             if (rnorm <= tol * anorm) {
                 // acceptance on a freshly computed residual and Rayleigh quotient
-                jdmi::launch_stencil<double>(S.L, S.bc, S.eps64, 0.0, u64, Au64, s);
+                jdmi::launch_stencil<double>(S.L, S.bc, S.eps64, 0.0, u64, Au64, s, nullptr, S.hop64);
                 jdmi::launch_dot<double>(n, u64, Au64, partial, red, s);
                 jdmi::launch_dot<double>(n, u64, u64, partial, red + 1, s);
                 double q2[2];
@@ -955,8 +1008,8 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
                     jdmi::launch_multidot<T>(n, nq + 1, Qt, n, Y + size_t(nq) * n, partial, red, s);
                     d2h(hcol.data(), red, nq + 1);
                     for (int i = 0; i <= nq; ++i) {
-                        Hq[i + size_t(nq) * (k + 1)] = hcol[i];
-                        Hq[nq + size_t(i) * (k + 1)] = hcol[i];
+                        Hq[i + size_t(nq) * (kq + 1)] = hcol[i];
+                        Hq[nq + size_t(i) * (kq + 1)] = hcol[i];
                     }
                     ++nq;
                     solves_this_pair = 0;
@@ -971,7 +1024,10 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
                     std::fill(H.begin(), H.end(), 0.0);
                     for (int c = 1; c < m; ++c) H[(c - 1) + size_t(c - 1) * jmax] = hw[ord[c]];
                     --m;
-                    if (nq == k) { finished = true; break; }
+                    if (nq == kq) {
+                        finished = true;
+                        break;
+                    }
                     if (m == 0) break;
                     continue;
                 }
@@ -998,6 +1054,15 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
             for (int c = 0; c < jmin; ++c) H[c + size_t(c) * jmax] = hw[ord[c]];
             m = jmin;
         }
+        if (start_left > 0) {
+            jdmi::launch_random_vector(n, (S.seed ^ 0x5DEECE66Dull) + 0x9E3779B97F4A7C15ull * uint64_t(start_left), r64,
+                                       s);
+            --start_left;
+            jdmi::launch_convert<double, T>(n, r64, sv.B.b, 1.0, s);
+            pc.apply(sv.B.b, sv.B.u, s);
+            jdmi::launch_convert<T, double>(n, sv.B.u, t64, 1.0, s);
+            continue;
+        }
         // ---- correction equation ----
         const int p = nq + 1;
         jdmi::launch_convert<double, T>(n, u64, Qt + size_t(nq) * n, 1.0, s);
@@ -1010,7 +1075,7 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
                 double v;
                 if (i == nq) v = hcol[j];
                 else if (j == nq) v = hcol[i];
-                else v = Hq[i + size_t(j) * (k + 1)];
+                else v = Hq[i + size_t(j) * (kq + 1)];
                 Mh[i + size_t(j) * p] = v;
             }
         if (!small_inverse(p, Mh)) throw JdError(JD_EDEVICE, "singular projected preconditioner matrix");
@@ -1031,14 +1096,14 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
 
     emit_outputs(S, Q, lam, nq, k, out, Au64, partial, red);
     if (info) {
-        info->n_converged = nq;
+        info->n_converged = std::min(nq, k);
         info->outer_its = outer;
         info->inner_its = inner_total;
         info->solve_s = solve_s;
         fill_setup_info(S, info);
         info->device_bytes = S.mem.bytes + mem.bytes + sv.mem.bytes;
     }
-    return nq == k ? JD_OK : JD_ENOCONV;
+    return nq >= k ? JD_OK : JD_ENOCONV;
 }
 
 // Shift-and-invert Lanczos (section 4.1): Lanczos on (A - sigma I)^{-1}, each product an
@@ -1171,7 +1236,7 @@ int si_lanczos_run(Setup &S, const P &pc, int k, double tol, double inner_tol, O
             std::vector<double> rq(want);
             for (int c = 0; c < want; ++c) {
                 double *u = V2 + size_t(c) * n;
-                jdmi::launch_stencil<double>(S.L, S.bc, S.eps64, 0.0, u, Au, s);
+                jdmi::launch_stencil<double>(S.L, S.bc, S.eps64, 0.0, u, Au, s, nullptr, S.hop64);
                 jdmi::launch_dot<double>(n, u, Au, partial, red, s);
                 jdmi::launch_dot<double>(n, u, u, partial, red + 1, s);
                 double q2[2];
@@ -1494,8 +1559,19 @@ int jd_gen_diag(int L, double W, uint64_t seed, double *d_eps, float *d_eps32, v
     });
 }
 
-int jd_stencil_spmv(int L, int bc, int precision, const void *d_eps, double shift, const void *d_x, void *d_y,
-                    void *stream)
+int jd_gen_hop(int L, double W, uint64_t seed, double *d_hop, float *d_hop32, void *stream)
+{
+    return guarded([&] {
+        check_problem_args(L, W, 0.0, nullptr);
+        if (!d_hop) throw JdError(JD_EINVAL, "d_hop must not be NULL");
+        jdmi::launch_gen_hop(L, W, seed, d_hop, d_hop32, static_cast<hipStream_t>(stream));
+        HIPCHK(hipGetLastError());
+        return JD_OK;
+    });
+}
+
+int jd_stencil_spmv(int L, int bc, int precision, const void *d_eps, const void *d_hop, double shift, const void *d_x,
+                    void *d_y, void *stream)
 {
     return guarded([&] {
         check_problem_args(L, 0.0, shift, nullptr);
@@ -1505,10 +1581,10 @@ int jd_stencil_spmv(int L, int bc, int precision, const void *d_eps, double shif
         hipStream_t s = static_cast<hipStream_t>(stream);
         if (precision == JD_FP64)
             jdmi::launch_stencil<double>(L, bc, static_cast<const double *>(d_eps), shift, static_cast<const double *>(d_x),
-                                         static_cast<double *>(d_y), s);
+                                         static_cast<double *>(d_y), s, nullptr, static_cast<const double *>(d_hop));
         else if (precision == JD_MIXED)
             jdmi::launch_stencil<float>(L, bc, static_cast<const float *>(d_eps), shift, static_cast<const float *>(d_x),
-                                        static_cast<float *>(d_y), s);
+                                        static_cast<float *>(d_y), s, nullptr, static_cast<const float *>(d_hop));
         else
             throw JdError(JD_EINVAL, "unknown precision");
         HIPCHK(hipGetLastError());
@@ -1858,6 +1934,7 @@ void check_request(const jd_request &r)
         throw JdError(JD_EINVAL, "unknown precision");
     if (r.flags & ~(JD_FLAG_GRAPHS | JD_FLAG_LEVELS)) throw JdError(JD_EINVAL, "unknown flag bits");
     if (r.bc != JD_BC_PERIODIC && r.bc != JD_BC_HARDWALL) throw JdError(JD_EINVAL, "unknown boundary condition");
+    if (r.model != JD_MODEL_ANDERSON && r.model != JD_MODEL_OFFDIAG) throw JdError(JD_EINVAL, "unknown model");
 }
 
 }  // namespace
@@ -1888,6 +1965,7 @@ struct jd_server {
         jd_options o{};
         o.precision = q.r.precision;
         o.bc = q.r.bc;
+        o.model = q.r.model;
         o.flags = q.r.flags & ~JD_FLAG_GRAPHS;  // workers launch eagerly
         o.stream = stream;
         jd_problem *p = nullptr;

@@ -23,10 +23,12 @@ struct SqmrState {
 
 // ---- K1 / K2 --------------------------------------------------------------------
 void launch_gen_diag(int L, double W, uint64_t seed, double *eps, float *eps32, hipStream_t s);
-// bc: 0 periodic, 1 hard walls
+// random bond values hop[d n + s] (bond from s to s + e_d), hop32 may be NULL
+void launch_gen_hop(int L, double W, uint64_t seed, double *hop, float *hop32, hipStream_t s);
+// bc: 0 periodic, 1 hard walls; hop: bond values (NULL: the constant coupling -1)
 template <typename T>
 void launch_stencil(int L, int bc, const T *eps, double shift, const T *x, T *y, hipStream_t s,
-                    const int *skip = nullptr);
+                    const int *skip = nullptr, const T *hop = nullptr);
 
 // ---- multilevel apply ---------------------------------------------------------------
 template <typename T>
@@ -123,7 +125,8 @@ void launch_sqmr_params(SqmrState *st, double shift, double tol, hipStream_t s);
 void launch_sqmr_scalar_start(SqmrState *st, const double *rr, const double *rho, hipStream_t s);
 // t = (A - st->shift I) q, skipped when st->done
 template <typename T>
-void launch_stencil_state(int L, int bc, const T *eps, const SqmrState *st, const T *x, T *y, hipStream_t s);
+void launch_stencil_state(int L, int bc, const T *eps, const SqmrState *st, const T *x, T *y, hipStream_t s,
+                          const T *hop = nullptr);
 template <typename T>
 void launch_copy(int n, const T *x, T *y, hipStream_t s);
 // sigma = q.t (stored in *sigma) and, in the same final reduction, alpha = rho / sigma

@@ -77,6 +77,30 @@ void launch_gen_diag(int L, double W, uint64_t seed, double *eps, float *eps32, 
     hipLaunchKernelGGL(k_gen_diag, dim3(nblocks(n)), dim3(kBlock), 0, s, n, W, seed, eps, eps32);
 }
 
+// The off-diagonal model: bond (s, d) (site s to its +x, +y, +z neighbour) takes output
+// n + 3 s + d + 1 of the same SplitMix64 stream, t = W (u - 1/2); stored as hop[d n + s].
+__global__ void __launch_bounds__(kBlock) k_gen_hop(int n, double W, uint64_t seed, double *hop, float *hop32)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    for (int d = 0; d < 3; ++d) {
+        const uint64_t m = uint64_t(n) + 3ull * uint64_t(s) + uint64_t(d) + 1ull;
+        uint64_t z = seed + m * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const double t = W * (double(z >> 11) * 0x1.0p-53 - 0.5);
+        hop[size_t(d) * n + s] = t;
+        if (hop32) hop32[size_t(d) * n + s] = float(t);
+    }
+}
+
+void launch_gen_hop(int L, double W, uint64_t seed, double *hop, float *hop32, hipStream_t s)
+{
+    const int n = L * L * L;
+    hipLaunchKernelGGL(k_gen_hop, dim3(nblocks(n)), dim3(kBlock), 0, s, n, W, seed, hop, hop32);
+}
+
 // ---------------------------------------------------------------------------------
 // K2: y = (A - shift I) x with A = -T + diag(eps) on the periodic lattice, or on the box
 // with hard walls (a neighbour outside the box contributes nothing).
@@ -101,42 +125,69 @@ __device__ inline T neighbour_sum(int L, int n, int s, const T *__restrict__ x, 
     return ((xm + xp) + (ym + yp)) + (zm + zp);
 }
 
+// Random bond values (the off-diagonal model): sum over the site's bonds of t x, the
+// bond to s + e_d stored at hop[d n + s], the bond to s - e_d at hop[d n + (s - e_d)].
+template <typename T>
+__device__ inline T bond_sum(int L, int n, int s, const T *__restrict__ x, const T *__restrict__ hop, int bc)
+{
+    const int LL = L * L;
+    const int c[3] = {s % L, (s / L) % L, s / LL};
+    const int stride[3] = {1, L, LL};
+    T acc = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T *t = hop + size_t(d) * n;
+        const int up = c[d] == L - 1 ? s - (L - 1) * stride[d] : s + stride[d];
+        const int dn = c[d] == 0 ? s + (L - 1) * stride[d] : s - stride[d];
+        const bool has_up = bc == 0 || c[d] < L - 1, has_dn = bc == 0 || c[d] > 0;
+        const T a = has_up ? t[s] * x[up] : T(0);
+        const T b = has_dn ? t[dn] * x[dn] : T(0);
+        acc += a + b;
+    }
+    return acc;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_stencil(int L, int n, int bc, const T *__restrict__ eps, T shift,
                                                     const T *__restrict__ x, T *__restrict__ y,
-                                                    const int *skip)
+                                                    const int *skip, const T *__restrict__ hop)
 {
     if (skip && *skip) return;
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
-    y[s] = (eps[s] - shift) * x[s] - neighbour_sum(L, n, s, x, bc);
+    if (hop) y[s] = (eps[s] - shift) * x[s] + bond_sum(L, n, s, x, hop, bc);
+    else y[s] = (eps[s] - shift) * x[s] - neighbour_sum(L, n, s, x, bc);
 }
 
 template <typename T>
-void launch_stencil(int L, int bc, const T *eps, double shift, const T *x, T *y, hipStream_t s, const int *skip)
+void launch_stencil(int L, int bc, const T *eps, double shift, const T *x, T *y, hipStream_t s, const int *skip,
+                    const T *hop)
 {
     const int n = L * L * L;
-    hipLaunchKernelGGL(k_stencil<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, L, n, bc, eps, T(shift), x, y, skip);
+    hipLaunchKernelGGL(k_stencil<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, L, n, bc, eps, T(shift), x, y, skip,
+                       hop);
 }
 
 // the same product with the shift read from the solver state (graph-replayable)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_stencil_state(int L, int n, int bc, const T *__restrict__ eps,
                                                           const SqmrState *st, const T *__restrict__ x,
-                                                          T *__restrict__ y)
+                                                          T *__restrict__ y, const T *__restrict__ hop)
 {
     if (st->done) return;
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
     const T shift = T(st->shift);
-    y[s] = (eps[s] - shift) * x[s] - neighbour_sum(L, n, s, x, bc);
+    if (hop) y[s] = (eps[s] - shift) * x[s] + bond_sum(L, n, s, x, hop, bc);
+    else y[s] = (eps[s] - shift) * x[s] - neighbour_sum(L, n, s, x, bc);
 }
 
 template <typename T>
-void launch_stencil_state(int L, int bc, const T *eps, const SqmrState *st, const T *x, T *y, hipStream_t s)
+void launch_stencil_state(int L, int bc, const T *eps, const SqmrState *st, const T *x, T *y, hipStream_t s,
+                          const T *hop)
 {
     const int n = L * L * L;
-    hipLaunchKernelGGL(k_stencil_state<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, L, n, bc, eps, st, x, y);
+    hipLaunchKernelGGL(k_stencil_state<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, L, n, bc, eps, st, x, y, hop);
 }
 
 template <typename T>
@@ -913,8 +964,10 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
 
 // ---- explicit instantiations ------------------------------------------------------
 #define JD_INST(T)                                                                                        \
-    template void launch_stencil<T>(int, int, const T *, double, const T *, T *, hipStream_t, const int *);    \
-    template void launch_stencil_state<T>(int, int, const T *, const SqmrState *, const T *, T *, hipStream_t); \
+    template void launch_stencil<T>(int, int, const T *, double, const T *, T *, hipStream_t, const int *,       \
+                                    const T *);                                                                 \
+    template void launch_stencil_state<T>(int, int, const T *, const SqmrState *, const T *, T *, hipStream_t,  \
+                                          const T *);                                                           \
     template void launch_copy<T>(int, const T *, T *, hipStream_t);                                       \
     template void launch_gather<T>(int, const int *, const T *, T *, hipStream_t, const int *);            \
     template void launch_scatter<T>(int, const int *, const T *, T *, hipStream_t, const int *);           \

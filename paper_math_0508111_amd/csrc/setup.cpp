@@ -64,9 +64,12 @@ void set_setup_threads(int threads)
 #endif
 }
 
-Csr anderson_shifted(int L, const double *eps, double sigma, int bc)
+Csr anderson_shifted(int L, const double *eps, double sigma, int bc, const double *hop)
 {
     const bool wall = bc != 0;
+    const int64_t nn = int64_t(L) * L * L;
+    // coupling of the bond from site a to a + e_d (d = 0, 1, 2), -1 without bond values
+    auto t = [&](int d, int a) { return hop ? hop[d * nn + a] : -1.0; };
     const int n = L * L * L;
     Csr A;
     A.n = n;
@@ -84,12 +87,14 @@ Csr anderson_shifted(int L, const double *eps, double sigma, int bc)
         };
         add(s, eps[s] - sigma);
         // with hard walls a neighbour across a face of the box is absent
-        if (!wall || i < L - 1) add((i + 1) % L + L * (j + L * k), -1.0);
-        if (!wall || i > 0) add((i + L - 1) % L + L * (j + L * k), -1.0);
-        if (!wall || j < L - 1) add(i + L * ((j + 1) % L + L * k), -1.0);
-        if (!wall || j > 0) add(i + L * ((j + L - 1) % L + L * k), -1.0);
-        if (!wall || k < L - 1) add(i + L * (j + L * ((k + 1) % L)), -1.0);
-        if (!wall || k > 0) add(i + L * (j + L * ((k + L - 1) % L)), -1.0);
+        const int xm = (i + L - 1) % L + L * (j + L * k), ym = i + L * ((j + L - 1) % L + L * k);
+        const int zm = i + L * (j + L * ((k + L - 1) % L));
+        if (!wall || i < L - 1) add((i + 1) % L + L * (j + L * k), t(0, s));
+        if (!wall || i > 0) add(xm, t(0, xm));
+        if (!wall || j < L - 1) add(i + L * ((j + 1) % L + L * k), t(1, s));
+        if (!wall || j > 0) add(ym, t(1, ym));
+        if (!wall || k < L - 1) add(i + L * (j + L * ((k + 1) % L)), t(2, s));
+        if (!wall || k > 0) add(zm, t(2, zm));
         std::sort(e, e + m);
         for (int t = 0; t < m; ++t) { A.col.push_back(e[t].first); A.val.push_back(e[t].second); }
         A.ptr[s + 1] = int64_t(A.col.size());

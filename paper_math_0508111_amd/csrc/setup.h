@@ -204,8 +204,9 @@ void set_setup_threads(int threads);
 // OpenMP threads available to the calling thread (OMP_NUM_THREADS when set).
 int setup_thread_budget();
 
-// A - sigma I for the Anderson lattice (hopping -1), CSR; bc 0: periodic, 1: hard walls.
-Csr anderson_shifted(int L, const double *eps, double sigma, int bc = 0);
+// A - sigma I for the Anderson lattice, CSR; bc 0: periodic, 1: hard walls; couplings -1,
+// or the bond values hop[d n + s] (bond from site s to s + e_d) when hop is not NULL.
+Csr anderson_shifted(int L, const double *eps, double sigma, int bc = 0, const double *hop = nullptr);
 
 
 

@@ -37,7 +37,16 @@ CASES = {
     "L60_W12_s1000041_k7": dict(L=60, W=12.0, seed=1000041, sigma=0.6205487042125981, k=7),
     # hard-wall boundary conditions (section 8.2, Table 6)
     "L30_W16.5_s0_k5_hardwall": dict(L=30, W=16.5, seed=0, sigma=0.0, k=5, bc="hardwall"),
+    # the off-diagonal model (section 8.2, Table 6): diagonal 1.28, bonds on [-1/2, 1/2]
+    "L30_W1_s0_k5_offdiag": dict(L=30, W=1.0, seed=0, sigma=0.0, k=5, model="offdiag"),
 }
+
+
+def _model(c):
+    """(eps, hop) of a case: the diagonal model, or the off-diagonal one."""
+    if c.get("model", "anderson") == "offdiag":
+        return generator.offdiag_model(c["L"], c["W"], c["seed"])
+    return generator.disorder(c["L"], c["W"], c["seed"]), None
 
 
 def _machine():
@@ -58,7 +67,7 @@ def _machine():
     return f"{threads} threads, {model}"
 
 
-def certify(out, eps):
+def certify(out, eps, hop=None):
     """Inertia certificate of a stored result (Sylvester's law on the exact LDL^T).
 
     rho is halfway between the k-th and the (k+1)-th distance to sigma; the window
@@ -72,7 +81,7 @@ def certify(out, eps):
     d_k, d_next = abs(lams[-1] - sigma), abs(out["next"] - sigma)
     rho = 0.5 * (d_k + d_next)
     t0 = time.time()
-    count = eig.count_in_window(out["L"], eps, sigma - rho, sigma + rho, bc=out.get("bc", "periodic"))
+    count = eig.count_in_window(out["L"], eps, sigma - rho, sigma + rho, bc=out.get("bc", "periodic"), hop=hop)
     assert count == k, (count, k)
     iv = [(lams[i] - res[i], lams[i] + res[i]) for i in range(k)]
     kt = []
@@ -94,11 +103,11 @@ def certify(out, eps):
 
 def run(name, c):
     t0 = time.time()
-    eps = generator.disorder(c["L"], c["W"], c["seed"])
+    eps, hop = _model(c)
     tm = {}
     bc = c.get("bc", "periodic")
     lams, X, res, anorm = eig.nearest_eigenpairs(c["L"], eps, c["sigma"], c["k"] + 1,
-                                                 method="lanczos", timings=tm, bc=bc)
+                                                 method="lanczos", timings=tm, bc=bc, hop=hop)
     out = dict(c)
     out.pop("dense", None)
     out.update(lams=[float(v) for v in lams[:c["k"]]], next=float(lams[c["k"]]),
@@ -107,12 +116,12 @@ def run(name, c):
                lanczos_seconds=round(tm["lanczos_s"], 1), machine=_machine(),
                cite="section 3 eq. (eigenequation); problem: k eigenvalues nearest sigma")
     if c.get("dense"):
-        A = lattice.hamiltonian(c["L"], eps, bc=bc).toarray()
+        A = lattice.hamiltonian(c["L"], eps, bc=bc, hop=hop).toarray()
         w = jacobi.eigh(A, vectors=False)[0]
         idx = eig.select_nearest(w, c["sigma"], c["k"] + 1)
         out["lams_dense_jacobi"] = [float(v) for v in w[idx][:c["k"]]]
         assert np.allclose(out["lams_dense_jacobi"], out["lams"], atol=1e-12, rtol=0)
-    certify(out, eps)
+    certify(out, eps, hop)
     with open(os.path.join(HERE, name + ".json"), "w") as fh:
         json.dump(out, fh, indent=1)
     print(name, "done in", out["seconds"], "s", flush=True)
@@ -123,8 +132,8 @@ def certify_stored(name):
     path = os.path.join(HERE, name + ".json")
     with open(path) as fh:
         out = json.load(fh)
-    eps = generator.disorder(out["L"], out["W"], out["seed"])
-    certify(out, eps)
+    eps, hop = _model(out)
+    certify(out, eps, hop)
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(name, "certified in", out["certificate"]["seconds"], "s", flush=True)

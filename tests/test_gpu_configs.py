@@ -144,3 +144,18 @@ def test_clean_lattice_hardwall_clusters(L, sigma, precision):
                                          bc="hardwall")
     assert info["status"] == 0 and info["n_converged"] == k
     _check_closed_form(L, sigma, k, evals, evecs, resid, vals, bc="hardwall")
+
+
+def test_hard_serving_request_against_certified_oracle():
+    # W = 12, L = 60 near the band centre: the multilevel setup stalls (kappa raised) and
+    # the solve takes the larger search space and longer inner solves
+    g = _golden("L60_W12_s1000041_k7")
+    assert g["certificate"]["inertia_count"] == g["k"]
+    L, W, seed, sigma, k = g["L"], g["W"], g["seed"], g["sigma"], g["k"]
+    evals, evecs, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, vectors=True, precision="mixed")
+    assert info["status"] == 0 and np.max(np.abs(evals - np.array(g["lams"]))) <= 1e-9
+    eps = generator.disorder(L, W, seed)
+    for c in range(k):
+        r = np.linalg.norm(lattice.matvec(L, eps, evecs[:, c]) - evals[c] * evecs[:, c])
+        assert r <= 1e-10 * g["anorm"] * 1.0001
+    assert np.abs(evecs.T @ evecs - np.eye(k)).max() <= 1e-8

@@ -414,3 +414,67 @@ def test_si_lanczos_restarts_and_rejects_binary32():
         p.lanczos(k)
     assert e.value.code == jd.JD_ENOTIMPL
     p.close()
+
+
+# --- the off-diagonal model: random bond values (section 8.2, Table 6) ---------------------
+
+@pytest.mark.parametrize("L,W,seed", [(2, 1.0, 5), (7, 1.0, 3), (40, 1.0, 0)])
+def test_gen_hop_bit_exact(L, W, seed):
+    n = L ** 3
+    h64 = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    h32 = torch.empty(3 * n, dtype=torch.float32, device="cuda")
+    jd.gen_hop(L, W, seed, h64, h32, stream=stream())
+    torch.cuda.synchronize()
+    ref = generator.hoppings(L, W, seed).reshape(-1)
+    assert np.array_equal(h64.cpu().numpy(), ref)
+    assert np.array_equal(h32.cpu().numpy(), ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("L,bc,shift", [(2, "periodic", 0.0), (3, "periodic", 0.4), (3, "hardwall", 0.0),
+                                        (33, "periodic", -0.2), (64, "hardwall", 0.1)])
+def test_stencil_parity_offdiag(L, bc, shift):
+    n = L ** 3
+    eps, hop = generator.offdiag_model(L, 1.0, 2)
+    x = seeded_inputs.vector(n, 9)
+    ref = lattice.matvec(L, eps, x, shift=shift, bc=bc, hop=hop)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    jd.stencil_spmv(L, dev(eps), shift, dev(x), y, "fp64", stream=stream(), bc=bc, hop=dev(hop.reshape(-1)))
+    torch.cuda.synchronize()
+    scale = np.abs(eps - shift) * np.abs(x) + 6 * 0.5 * np.abs(x).max()
+    assert np.all(np.abs(y.cpu().numpy() - ref) <= 12 * np.finfo(float).eps * scale)
+    y32 = torch.empty(n, dtype=torch.float32, device="cuda")
+    jd.stencil_spmv(L, dev(eps, torch.float32), shift, dev(x, torch.float32), y32, "mixed", stream=stream(), bc=bc,
+                    hop=dev(hop.reshape(-1), torch.float32))
+    torch.cuda.synchronize()
+    assert np.all(np.abs(y32.cpu().numpy().astype(np.float64) - ref) <= 24 * U32 * scale)
+
+
+@pytest.mark.parametrize("L,seed,sigma,k,precision,bc", [(8, 3, 0.0, 5, "fp64", "periodic"),
+                                                         (12, 5, 0.3, 6, "mixed", "periodic"),
+                                                         (11, 8, -0.2, 4, "mixed_factors", "hardwall")])
+def test_solve_offdiag_live_oracle(L, seed, sigma, k, precision, bc):
+    eps, hop = generator.offdiag_model(L, 1.0, seed)
+    ref, X, _, anorm = eig.nearest_eigenpairs(L, eps, sigma, k, bc=bc, hop=hop)
+    evals, evecs, resid, info = jd.solve(L, 1.0, seed, sigma, k, 1e-10, vectors=True, precision=precision, bc=bc,
+                                         model="offdiag")
+    assert info["n_converged"] == k and abs(info["anorm"] - anorm) <= 1e-14 * anorm
+    assert np.all(np.abs(evals - ref) <= 1e-9), (evals, ref)
+    for c in range(k):
+        x = evecs[:, c]
+        r = np.linalg.norm(lattice.matvec(L, eps, x, bc=bc, hop=hop) - evals[c] * x)
+        assert r <= 1e-10 * anorm * 1.0001
+    assert np.abs(evecs.T @ evecs - np.eye(k)).max() <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_solve_offdiag_against_stored_oracle(precision):
+    g = _golden("L30_W1_s0_k5_offdiag")
+    assert g["model"] == "offdiag" and g["certificate"]["inertia_count"] == g["k"]
+    L, W, seed, sigma, k = g["L"], g["W"], g["seed"], g["sigma"], g["k"]
+    evals, evecs, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, vectors=True, precision=precision,
+                                         model="offdiag")
+    assert info["n_converged"] == k and np.max(np.abs(evals - np.array(g["lams"]))) <= 1e-9
+    eps, hop = generator.offdiag_model(L, W, seed)
+    for c in range(k):
+        r = np.linalg.norm(lattice.matvec(L, eps, evecs[:, c], hop=hop) - evals[c] * evecs[:, c])
+        assert r <= 1e-10 * g["anorm"] * 1.0001

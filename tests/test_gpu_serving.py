@@ -64,3 +64,52 @@ def test_footprint_estimate_covers_the_device_memory(L, W, k):
     _, _, _, info = jd.solve(L, W, 1000000 + L, 0.1, k, 1e-10, precision="mixed")
     assert info["status"] == 0
     assert 0 < info["device_bytes"] <= jd.Server.footprint(req)
+
+
+def test_hard_large_request_alone_and_in_the_mix():
+    # the largest lattice of the serving mix at W = 12 near the band centre (the stalled
+    # setup path), against its inertia-certified oracle result, alone and among other
+    # requests (an L = 40 one, hard walls and the off-diagonal model among them)
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "L60_W12_s1000041_k7.json")) as fh:
+        g = json.load(fh)
+    assert g["certificate"]["inertia_count"] == g["k"]
+    hard = (g["L"], g["W"], g["seed"], g["sigma"], g["k"])
+    alone, _, res_alone, info = jd.solve(*hard, 1e-10, precision="mixed")
+    assert info["status"] == 0 and np.max(np.abs(alone - np.array(g["lams"]))) <= 1e-9
+    others = [jd.Server.request(40, 16.5, 1000002, 0.11, 10), jd.Server.request(12, 16.5, 1000000, 0.3, 4),
+              jd.Server.request(14, 21.0, 1000007, -0.4, 3, bc="hardwall"),
+              jd.Server.request(10, 1.0, 1000008, 0.0, 4, model="offdiag")]
+    srv = jd.Server(workers=4)
+    tickets = [srv.submit(others[0]), srv.submit(jd.Server.request(*hard)), srv.submit(others[1]),
+               srv.submit(others[2]), srv.submit(others[3])]
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    assert all(r["status"] == 0 for r in res), [r["error"] for r in res]
+    assert np.array_equal(res[1]["evals"], alone)  # bit for bit
+    ref40 = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                        "L40_W16.5_s1000002_k10.json")))
+    assert np.max(np.abs(res[0]["evals"] - np.array(ref40["lams"]))) <= 1e-9
+    eps = generator.disorder(14, 21.0, 1000007)
+    ref_hw = eig.nearest_eigenpairs(14, eps, -0.4, 3, bc="hardwall")[0]
+    assert np.max(np.abs(res[3]["evals"] - ref_hw)) <= 1e-9
+    ref_od = eig.anderson_nearest(10, 1.0, 1000008, 0.0, 4, model="offdiag")[0]
+    assert np.max(np.abs(res[4]["evals"] - ref_od)) <= 1e-9
+
+
+def test_failed_request_is_reported_and_the_others_are_served():
+    # a request whose solve fails after its setup (binary32 factors with binary64 vectors
+    # need the inverse factor form, not the level-by-level apply) between good requests:
+    # its ticket reports the error, its memory is returned, the others complete
+    good = [jd.Server.request(10, 16.5, 1000010 + i, 0.1 * i, 3) for i in range(3)]
+    bad = jd.Server.request(10, 16.5, 1000020, 0.0, 3, precision="mixed_factors", flags=jd.JD_FLAG_LEVELS)
+    srv = jd.Server(hbm_budget_bytes=2 * max(jd.Server.footprint(r) for r in good + [bad]), workers=2)
+    tickets = [srv.submit(good[0]), srv.submit(bad), srv.submit(good[1]), srv.submit(good[2])]
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    assert res[1]["status"] == jd.JD_ENOTIMPL and "inverse factor" in res[1]["error"]
+    for r, q in zip([res[0], res[2], res[3]], good):
+        assert r["status"] == 0
+        ref = eig.anderson_nearest(q.L, q.W, q.seed, q.sigma, q.k)[0]
+        assert np.max(np.abs(r["evals"] - ref)) <= 1e-9
