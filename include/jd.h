@@ -110,6 +110,8 @@ enum { JD_MODEL_ANDERSON = 0, JD_MODEL_OFFDIAG = 1 };
  *  bc         JD_BC_PERIODIC (0) or JD_BC_HARDWALL.  ||A||_inf is the largest row sum
  *             of |entries| (6 + max|eps| for the diagonal model on the torus).
  *  model      JD_MODEL_ANDERSON (0) or JD_MODEL_OFFDIAG.
+ *  inner_tol_min  floor of the relative tolerance 2^(-j) of the j-th correction
+ *             equation solved for the current pair (0 -> 1e-10); a solve-time option.
  *  stream     stream for the solve's device work (NULL: a library-created blocking stream).
  */
 typedef struct jd_options {
@@ -128,6 +130,7 @@ typedef struct jd_options {
     int z_parts;
     int bc;
     int model;
+    double inner_tol_min;
     void *stream;
 } jd_options;
 
@@ -195,7 +198,7 @@ int jd_problem_lanczos(jd_problem *p, int k, double tol, double inner_tol, doubl
  * is needed. */
 int jd_problem_set_precision(jd_problem *p, int precision);
 /* Replace the solve-time options of later jd_problem_solve calls: jmin, jmax,
- * max_outer, max_inner, switch_tol and the JD_FLAG_GRAPHS bit of flags are taken from
+ * max_outer, max_inner, switch_tol, inner_tol_min and the JD_FLAG_GRAPHS bit of flags are taken from
  * *opt (0 -> the default, as in jd_setup); every setup option of *opt is ignored.
  * JD_EINVAL for out-of-range values, and the problem keeps its previous options. */
 int jd_problem_set_solve_options(jd_problem *p, const jd_options *opt);
@@ -210,6 +213,16 @@ void jd_problem_free(jd_problem *p);
  *   d_eps32 may be NULL.
  */
 int jd_gen_diag(int L, double W, uint64_t seed, double *d_eps, float *d_eps32, void *stream);
+
+/*
+ * jd_block_product -- out = V S, the dense tall-skinny products of Rayleigh-Ritz
+ * (section 4.2: the restart V <- V S and the deflation after locking), on the FP64
+ * matrix cores.  V: n x m, S: m x mout, out: n x mout, all binary64 device arrays in
+ * column-major order with leading dimensions ldv >= n, lds >= m, ldo >= n; out must not
+ * overlap V or S.
+ */
+int jd_block_product(int n, int m, int mout, const double *d_V, int64_t ldv, const double *d_S, int lds,
+                     double *d_out, int64_t ldo, void *stream);
 
 /* jd_gen_hop -- the bond values of the off-diagonal model (see JD_MODEL_OFFDIAG) into
  * a device array d_hop[d n + s] of 3 n binary64 values (bond from s to s + e_d), and

@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
                 ("max_levels", ctypes.c_int), ("z_drop", ctypes.c_double), ("jmin", ctypes.c_int), ("jmax", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int), ("switch_tol", ctypes.c_double),
                 ("flags", ctypes.c_int), ("z_parts", ctypes.c_int), ("bc", ctypes.c_int),
-                ("model", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("model", ctypes.c_int), ("inner_tol_min", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
 class Request(ctypes.Structure):
@@ -81,7 +81,7 @@ EXPORTS = ["jd_solve", "jd_setup", "jd_problem_solve", "jd_problem_info", "jd_pr
            "jd_problem_linear_solve", "jd_last_error", "jd_version", "jd_server_create", "jd_server_submit",
            "jd_server_poll", "jd_server_wait", "jd_server_footprint", "jd_server_destroy",
            "jd_host_matching", "jd_host_split_cycles", "jd_host_factor", "jd_set_allocator",
-           "jd_problem_linear_solve_noalloc", "jd_problem_lanczos", "jd_gen_hop"]
+           "jd_problem_linear_solve_noalloc", "jd_problem_lanczos", "jd_gen_hop", "jd_block_product"]
 
 _lib = None
 
@@ -108,6 +108,7 @@ def lib():
         "jd_gen_diag": (I, [I, D, U64, P, P, P]),
         "jd_stencil_spmv": (I, [I, I, I, P, P, D, P, P, P]),
         "jd_gen_hop": (I, [I, D, U64, P, P, P]),
+        "jd_block_product": (I, [I, I, I, P, ctypes.c_int64, P, I, P, ctypes.c_int64, P]),
         "jd_precond_create": (I, [I, D, U64, D, OP, ctypes.POINTER(P)]),
         "jd_precond_apply": (I, [P, I, P, P, P]),
         "jd_precond_levels": (I, [P, I, P, P, P]),
@@ -350,6 +351,21 @@ def gen_diag(L, W, seed, eps64, eps32=None, stream=None):
     n = int(L) ** 3
     _check(lib().jd_gen_diag(L, float(W), seed, _dev(eps64, "torch.float64", n, "eps64"),
                              _dev(eps32, "torch.float32", n, "eps32"), _stream_ptr(stream)))
+
+
+def block_product(V, S, out, stream=None):
+    """out = V S (jd_block_product); V (n, m), S (m, mout), out (n, mout): device float64
+    tensors whose transposes are contiguous (column-major storage)."""
+    n, m = int(V.shape[0]), int(V.shape[1])
+    mout = int(S.shape[1])
+    if int(S.shape[0]) != m or tuple(out.shape) != (n, mout):
+        raise ValueError("shapes do not match: V (n, m), S (m, mout), out (n, mout)")
+    for t, name in ((V, "V"), (S, "S"), (out, "out")):
+        if not t.t().is_contiguous():
+            raise ValueError(f"{name}: column-major storage expected (its transpose contiguous)")
+    _check(lib().jd_block_product(n, m, mout, _dev(V.t(), "torch.float64", n * m, "V"), n,
+                                  _dev(S.t(), "torch.float64", m * mout, "S"), m,
+                                  _dev(out.t(), "torch.float64", n * mout, "out"), n, _stream_ptr(stream)))
 
 
 def gen_hop(L, W, seed, hop64, hop32=None, stream=None):

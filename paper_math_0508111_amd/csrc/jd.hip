@@ -172,6 +172,7 @@ struct DevPrecond {
         d.long_col = mem.upload(h.long_col, s);
         d.long_val = mem.upload(cast_vec<T>(h.long_val), s);
         d.slice_ptr = mem.upload(h.slice_ptr, s);
+        d.slice_row = mem.upload(h.slice_row, s);
         d.rowidx = mem.upload(h.rowidx, s);
         d.col = mem.upload(h.col, s);
         d.val = mem.upload(cast_vec<T>(h.val), s);
@@ -371,6 +372,7 @@ void check_problem_args(int L, double W, double sigma, const jd_options *opt)
         if (!std::isfinite(opt->drop_tol) || !std::isfinite(opt->kappa) || opt->kappa < 0 ||
             !std::isfinite(opt->agg_tau) || !std::isfinite(opt->schur_tol) || !std::isfinite(opt->switch_tol))
             throw JdError(JD_EINVAL, "non-finite option");
+        if (!(opt->inner_tol_min >= 0 && opt->inner_tol_min < 1)) throw JdError(JD_EINVAL, "bad inner_tol_min");
     }
 }
 
@@ -858,6 +860,8 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
     // to binary32 accuracy)
     const double switch_tol = o.switch_tol != 0 ? o.switch_tol : (o.precision == JD_MIXED ? -1.0 : 1e-3);
     const int max_outer = o.max_outer > 0 ? o.max_outer : 60 * k + 200;
+    // smallest relative tolerance of a correction equation's SQMR solve
+    const double inner_floor = o.inner_tol_min > 0 ? o.inner_tol_min : 1e-10;
     if (jmax > 120) throw JdError(JD_EINVAL, "jmax too large");
     const double anorm = S.anorm;
     const double sigma = S.sigma;
@@ -1086,7 +1090,7 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
         jdmi::launch_multidot<T>(n, p, Qt, n, sv.B.b, partial, red, s);
         jdmi::launch_sub_qc<T>(n, p, Qt, n, red, sv.B.b, s);
         ++solves_this_pair;
-        const double rtol = std::max(std::pow(2.0, -double(solves_this_pair)), 1e-10);
+        const double rtol = std::max(std::pow(2.0, -double(solves_this_pair)), inner_floor);
         inner_total += sv.sqmr(shift, Qt, Y, p, dM, rtol, max_inner);
         jdmi::launch_convert<T, double>(n, sv.B.x, t64, 1.0, s);
     }
@@ -1463,6 +1467,7 @@ int jd_problem_set_solve_options(jd_problem *p, const jd_options *opt)
         check_search_space(opt->jmin, opt->jmax);
         if (opt->max_inner < 0 || opt->max_outer < 0) throw JdError(JD_EINVAL, "negative iteration cap");
         if (!std::isfinite(opt->switch_tol)) throw JdError(JD_EINVAL, "bad switch_tol");
+        if (!(opt->inner_tol_min >= 0 && opt->inner_tol_min < 1)) throw JdError(JD_EINVAL, "bad inner_tol_min");
         if (opt->flags & ~(JD_FLAG_GRAPHS | JD_FLAG_LEVELS)) throw JdError(JD_EINVAL, "unknown flag bits");
         jd_options &o = p->S.opt;
         o.jmin = opt->jmin;
@@ -1470,6 +1475,7 @@ int jd_problem_set_solve_options(jd_problem *p, const jd_options *opt)
         o.max_outer = opt->max_outer;
         o.max_inner = opt->max_inner;
         o.switch_tol = opt->switch_tol;
+        o.inner_tol_min = opt->inner_tol_min;
         o.flags = (o.flags & ~JD_FLAG_GRAPHS) | (opt->flags & JD_FLAG_GRAPHS);
         return JD_OK;
     });
@@ -1554,6 +1560,19 @@ int jd_gen_diag(int L, double W, uint64_t seed, double *d_eps, float *d_eps32, v
         check_problem_args(L, W, 0.0, nullptr);
         if (!d_eps) throw JdError(JD_EINVAL, "d_eps must not be NULL");
         jdmi::launch_gen_diag(L, W, seed, d_eps, d_eps32, static_cast<hipStream_t>(stream));
+        HIPCHK(hipGetLastError());
+        return JD_OK;
+    });
+}
+
+int jd_block_product(int n, int m, int mout, const double *d_V, int64_t ldv, const double *d_S, int lds,
+                     double *d_out, int64_t ldo, void *stream)
+{
+    return guarded([&] {
+        if (n < 1 || m < 1 || mout < 0) throw JdError(JD_EINVAL, "sizes must satisfy n >= 1, m >= 1, mout >= 0");
+        if (ldv < n || ldo < n || lds < m) throw JdError(JD_EINVAL, "leading dimensions too small");
+        if (!d_V || (mout > 0 && (!d_S || !d_out))) throw JdError(JD_EINVAL, "NULL device pointer");
+        jdmi::launch_gemm_vs(n, m, mout, d_V, ldv, d_S, lds, d_out, ldo, static_cast<hipStream_t>(stream));
         HIPCHK(hipGetLastError());
         return JD_OK;
     });

@@ -72,8 +72,9 @@ struct Hyb {
     const int64_t *long_ptr = nullptr; // nlong + 1
     const int *long_col = nullptr;
     const Tv *long_val = nullptr;
-    const int64_t *slice_ptr = nullptr;  // nslices + 1, in entries (multiples of 64)
-    const int *rowidx = nullptr;         // nslices * kSliceRows, -1 for padding rows
+    const int64_t *slice_ptr = nullptr;  // nslices + 1, in entries (multiples of 64) | shape code
+    const int64_t *slice_row = nullptr;  // nslices + 1, first rowidx entry of each slice
+    const int *rowidx = nullptr;         // the slices' rows, -1 for padding rows
     const int *col = nullptr;
     const Tv *val = nullptr;
 };

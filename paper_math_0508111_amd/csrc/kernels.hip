@@ -402,10 +402,12 @@ __global__ void __launch_bounds__(kBlock) k_hyb_spmv(Hyb<Tv> A, const Tx *__rest
         }
         return;
     }
-    // a slice of kSliceRows short rows, kSliceLanes lanes per row
+    // a slice of R = kSliceRows << sc short rows, 64 / R lanes per row
     const int slice = -1 - code;
-    const int64_t b = A.slice_ptr[slice];
-    const int groups = int((A.slice_ptr[slice + 1] - b) >> 6);
+    const int64_t p0 = A.slice_ptr[slice];
+    const int sc = int(p0 & 3);
+    const int64_t b = p0 & ~int64_t(63);
+    const int groups = int(((A.slice_ptr[slice + 1] & ~int64_t(63)) - b) >> 6);
     const int *c = A.col + b + lane;
     const Tv *v = A.val + b + lane;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -421,11 +423,11 @@ __global__ void __launch_bounds__(kBlock) k_hyb_spmv(Hyb<Tv> A, const Tx *__rest
     }
     for (; j < groups; ++j) a0 += double(nt_load(v + int64_t(j) * 64)) * double(x[nt_load(c + int64_t(j) * 64)]);
     double a = (a0 + a1) + (a2 + a3);
-    // lanes l, l + kSliceRows, l + 2 kSliceRows, ... hold the pieces of row l
-#pragma unroll
-    for (int o = kSliceRows; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
-    if (lane < kSliceRows) {
-        const int r = A.rowidx[int64_t(slice) * kSliceRows + lane];
+    // lanes l, l + R, l + 2 R, ... hold the pieces of row l
+    const int R = kSliceRows << sc;
+    for (int o = R; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
+    if (lane < R) {
+        const int r = A.rowidx[A.slice_row[slice] + lane];
         if (r >= 0) y[out_perm ? out_perm[r] : r] = Tx(a);
     }
 }
@@ -568,39 +570,73 @@ void launch_gemv_vs(int n, int m, const double *V, int64_t ldv, const double *s,
     hipLaunchKernelGGL(k_gemv_vs, dim3(nblocks(n)), dim3(kBlock), 0, st, n, m, V, ldv, s, y);
 }
 
-// Vout[:, c0 .. c0+7] = V * S[:, c0 .. c0+7]
+// Vout[:, 0 .. mout) = V[:, 0 .. m) S (column-major, the restart and deflation products
+// of Rayleigh-Ritz) on the FP64 matrix cores: v_mfma_f64_16x16x4 multiplies a 16 x 4
+// block of V (lane l holds row l % 16, column l / 16) by a 4 x 16 block of S (lane l
+// holds row l / 16, column l % 16) into a 16 x 16 tile of which lane l holds rows
+// l / 16 + 4 j (j = 0..3) of column l % 16 (checked on the device).  A workgroup covers 128 rows (each wave
+// two 16-row blocks) and a slab of 64 output columns (blockIdx.y), and stages S through
+// LDS 16 rows at a time; V is read once per slab (once when mout <= 64).
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kMmRows = 128, kMmCols = 64, kMmK = 16;
+
 __global__ void __launch_bounds__(kBlock) k_gemm_vs(int n, int m, int mout, const double *__restrict__ V,
                                                     int64_t ldv, const double *__restrict__ S, int lds,
                                                     double *__restrict__ Vout, int64_t ldo)
 {
-    __shared__ double ss[128 * 8];
-    const int c0 = blockIdx.y * 8;
-    const int nc = min(8, mout - c0);
-    for (int t = threadIdx.x; t < m * 8; t += kBlock) {
-        const int r = t / 8, c = t % 8;
-        ss[t] = (c < nc) ? S[r + int64_t(c0 + c) * lds] : 0.0;
+    __shared__ double sb[kMmK][kMmCols];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = lane >> 4, r16 = lane & 15;
+    const int c0 = blockIdx.y * kMmCols;
+    const int64_t rbase = int64_t(blockIdx.x) * kMmRows + wave * 32;
+    v4d acc[2][kMmCols / 16];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int t = 0; t < kMmCols / 16; ++t) acc[h][t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < m; k0 += kMmK) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < kMmK * kMmCols; e += kBlock) {
+            const int kk = e / kMmCols, cc = e % kMmCols;
+            const int k = k0 + kk, c = c0 + cc;
+            sb[kk][cc] = (k < m && c < mout) ? S[k + int64_t(c) * lds] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kMmK; kk += 4) {
+            const int k = k0 + kk + q;
+            double a[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t row = rbase + h * 16 + r16;
+                a[h] = (row < n && k < m) ? V[row + int64_t(k) * ldv] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < kMmCols / 16; ++t) {
+                const double b = sb[kk + q][t * 16 + r16];
+                acc[0][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b, acc[0][t], 0, 0, 0);
+                acc[1][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b, acc[1][t], 0, 0, 0);
+            }
+        }
     }
-    __syncthreads();
-    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
-    double acc[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-    for (int k = 0; k < m; ++k) {
-        const double v = V[i + int64_t(k) * ldv];
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] += v * ss[k * 8 + c];
-    }
+        for (int t = 0; t < kMmCols / 16; ++t) {
+            const int col = c0 + t * 16 + r16;
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
-        if (c < nc) Vout[i + int64_t(c0 + c) * ldo] = acc[c];
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = rbase + h * 16 + q + 4 * j;
+                if (row < n && col < mout) Vout[row + int64_t(col) * ldo] = acc[h][t][j];
+            }
+        }
 }
 
 void launch_gemm_vs(int n, int m, int mout, const double *V, int64_t ldv, const double *S, int lds, double *Vout,
                     int64_t ldo, hipStream_t st)
 {
-    if (mout <= 0) return;
-    dim3 grid(nblocks(n), (mout + 7) / 8);
+    if (mout <= 0 || n <= 0) return;
+    dim3 grid(unsigned((int64_t(n) + kMmRows - 1) / kMmRows), unsigned((mout + kMmCols - 1) / kMmCols));
     hipLaunchKernelGGL(k_gemm_vs, grid, dim3(kBlock), 0, st, n, m, mout, V, ldv, S, lds, Vout, ldo);
 }
 

@@ -1167,7 +1167,7 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L, int parts)
 // offsets shifted to the global numbering.
 HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val, const int *row_code)
 {
-    constexpr int P = kHybParts, C = kSliceRows, G = kSliceLanes;
+    constexpr int P = kHybParts;
     constexpr size_t kWindow = 2048;
     auto len = [&](int r) { return ptr[r + 1] - ptr[r]; };
     auto rcode = [&](int r) { return row_code ? row_code[r] : r; };
@@ -1199,40 +1199,61 @@ HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val, con
             auto b = shortr.begin() + w0, e = shortr.begin() + std::min(shortr.size(), w0 + kWindow);
             std::stable_sort(b, e, [&](int a, int c) { return len(a) > len(c); });
         }
-        for (size_t s0 = 0; s0 < shortr.size(); s0 += C) {
+        // slices of 8 << c rows with 8 >> c lanes per row: the lanes per row minimise the
+        // padded slots of the slice's longest row (ceil(w / g) g) within 8 groups, larger
+        // on ties; a slice does not cross a sorting window
+        for (size_t s0 = 0; s0 < shortr.size();) {
+            const size_t wend = std::min(shortr.size(), (s0 / kWindow + 1) * kWindow);
+            const int64_t w0 = len(shortr[s0]);
+            int g = kSliceLanes, code = 0;
+            int64_t best = (w0 + g - 1) / g * g;
+            for (int c = 1; c <= 3; ++c) {
+                const int gc = kSliceLanes >> c;
+                const int64_t grp = (w0 + gc - 1) / gc;
+                if (grp <= 8 && grp * gc < best) {
+                    best = grp * gc;
+                    g = gc;
+                    code = c;
+                }
+            }
+            const int R = 64 / g;
+            const size_t cnt = std::min<size_t>(size_t(R), wend - s0);
             int64_t w = 0;
-            for (size_t l = 0; l < size_t(C) && s0 + l < shortr.size(); ++l) w = std::max(w, len(shortr[s0 + l]));
-            const int64_t base = h.slice_ptr.back(), groups = (w + G - 1) / G;
+            for (size_t l = 0; l < cnt; ++l) w = std::max(w, len(shortr[s0 + l]));
+            const int64_t base = h.slice_ptr.back(), groups = (w + g - 1) / g;
+            h.slice_ptr.back() = base | code;
             // padding reads the slice's first entry's location (a value the product reads anyway)
             const int pad = len(shortr[s0]) > 0 ? col[ptr[shortr[s0]]] : 0;
             h.slice_ptr.push_back(base + groups * 64);
             h.col.resize(size_t(base + groups * 64), pad);
             h.val.resize(size_t(base + groups * 64), 0.0);
-            for (int l = 0; l < C; ++l) {
-                if (s0 + l >= shortr.size()) {
+            for (int l = 0; l < R; ++l) {
+                if (size_t(l) >= cnt) {
                     h.rowidx.push_back(-1);
                     continue;
                 }
                 const int r = shortr[s0 + l];
                 h.rowidx.push_back(rcode(r));
                 for (int64_t j = 0; j < len(r); ++j) {
-                    const int64_t at = base + (j / G) * 64 + (j % G) * C + l;
+                    const int64_t at = base + (j / g) * 64 + (j % g) * R + l;
                     h.col[at] = col[ptr[r] + j];
                     h.val[at] = val[ptr[r] + j];
                 }
             }
+            h.slice_row.push_back(int64_t(h.rowidx.size()));
             h.task.push_back(-int(h.slice_ptr.size() - 1));  // -1 - slice index within the part
+            s0 += cnt;
         }
     }
     // offsets of every part in the concatenated arrays
-    struct Off { size_t task, long_row, long_ent, slice, slice_ent; };
+    struct Off { size_t task, long_row, long_ent, slice, slice_ent, rows; };
     Off off[P + 1];
-    off[0] = {0, 0, 0, 0, 0};
+    off[0] = {0, 0, 0, 0, 0, 0};
     for (int part = 0; part < P; ++part) {
         const HybHost &q = parts[part];
         off[part + 1] = {off[part].task + q.task.size(), off[part].long_row + q.long_row.size(),
                          off[part].long_ent + q.long_col.size(), off[part].slice + (q.slice_ptr.size() - 1),
-                         off[part].slice_ent + q.col.size()};
+                         off[part].slice_ent + q.col.size(), off[part].rows + q.rowidx.size()};
     }
     HybHost h;
     const Off &tot = off[P];
@@ -1242,11 +1263,13 @@ HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val, con
     h.long_col.resize(tot.long_ent);
     h.long_val.resize(tot.long_ent);
     h.slice_ptr.resize(tot.slice + 1);
-    h.rowidx.resize(tot.slice * C);
+    h.slice_row.resize(tot.slice + 1);
+    h.rowidx.resize(tot.rows);
     h.col.resize(tot.slice_ent);
     h.val.resize(tot.slice_ent);
     h.long_ptr[0] = 0;
     h.slice_ptr[0] = 0;
+    h.slice_row[0] = 0;
     for (int part = 0; part < P; ++part) {
         h.tbeg[part] = int(off[part].task);
         h.tend[part] = int(off[part + 1].task);
@@ -1263,12 +1286,18 @@ HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val, con
         for (size_t i = 1; i < q.long_ptr.size(); ++i) h.long_ptr[o.long_row + i] = int64_t(o.long_ent) + q.long_ptr[i];
         std::copy(q.long_col.begin(), q.long_col.end(), h.long_col.begin() + o.long_ent);
         std::copy(q.long_val.begin(), q.long_val.end(), h.long_val.begin() + o.long_ent);
-        for (size_t i = 1; i < q.slice_ptr.size(); ++i)
+        // each part writes the starts of its slices (the shift keeps the shape code in the
+        // low bits: the offsets are multiples of 64); the common end is written below
+        for (size_t i = 0; i + 1 < q.slice_ptr.size(); ++i) {
             h.slice_ptr[o.slice + i] = int64_t(o.slice_ent) + q.slice_ptr[i];
-        std::copy(q.rowidx.begin(), q.rowidx.end(), h.rowidx.begin() + o.slice * C);
+            h.slice_row[o.slice + i] = int64_t(o.rows) + q.slice_row[i];
+        }
+        std::copy(q.rowidx.begin(), q.rowidx.end(), h.rowidx.begin() + o.rows);
         std::copy(q.col.begin(), q.col.end(), h.col.begin() + o.slice_ent);
         std::copy(q.val.begin(), q.val.end(), h.val.begin() + o.slice_ent);
     }
+    h.slice_ptr[tot.slice] = int64_t(tot.slice_ent);
+    h.slice_row[tot.slice] = int64_t(tot.rows);
     return h;
 }
 

@@ -84,13 +84,15 @@ struct SetupParams {
 // Device layout of a sparse product (built on the host; the kernel reads it as
 // jdmi::Hyb).  The rows are cut into kHybParts contiguous parts of equal nonzero count;
 // inside a part, rows with more than kLongRow entries are kept in CSR (longest first,
-// one wave each) and the other rows form slices of kSliceRows rows with kSliceLanes
-// lanes per row: entry j of the slice's row l sits at
-// slice_ptr[s] + (j / kSliceLanes) * 64 + (j % kSliceLanes) * kSliceRows + l
+// one wave each) and the other rows form slices of R = kSliceRows << c rows with
+// g = kSliceLanes >> c lanes per row (c = 0..3: 8 x 8, 16 x 4, 32 x 2, 64 x 1, chosen
+// per slice to pad its longest row least): entry j of the slice's row l sits at
+// base + (j / g) * 64 + (j % g) * R + l, with base = slice_ptr[s] & ~63 and
+// c = slice_ptr[s] & 3; the slice's rows are rowidx[slice_row[s] .. slice_row[s] + R)
 // (padding: value 0 and the column of the slice's first entry, so that it reads a
-// location the product reads anyway).  Short rows are sorted by decreasing length
-// inside windows of 2048 consecutive rows, so a slice holds rows of similar length that
-// are also neighbours in row order.  Row and column numbers are the element offsets the
+// location the product reads anyway; row -1).  Short rows are sorted by decreasing
+// length inside windows of 2048 consecutive rows, so a slice holds rows of similar
+// length that are also neighbours in row order.  Row and column numbers are the element offsets the
 // kernel writes and reads (see InverseFactor for the buffer they address).
 constexpr int kHybParts = 8;
 constexpr int kLongRow = 96;
@@ -103,8 +105,9 @@ struct HybHost {
     std::vector<int64_t> long_ptr{0};
     std::vector<int> long_col;
     std::vector<double> long_val;
-    std::vector<int64_t> slice_ptr{0};     // in entries (multiples of 64)
-    std::vector<int> rowidx, col;          // rowidx: kSliceRows per slice, -1 for padding rows
+    std::vector<int64_t> slice_ptr{0};     // in entries (multiples of 64) | shape code
+    std::vector<int64_t> slice_row{0};     // first rowidx entry of each slice
+    std::vector<int> rowidx, col;          // rowidx: R per slice, -1 for padding rows
     std::vector<double> val;
 };
 // CSR with nrows rows -> the hybrid layout; row i is written to row_code[i] (i when NULL).

@@ -478,3 +478,21 @@ def test_solve_offdiag_against_stored_oracle(precision):
     for c in range(k):
         r = np.linalg.norm(lattice.matvec(L, eps, evecs[:, c], hop=hop) - evals[c] * evecs[:, c])
         assert r <= 1e-10 * g["anorm"] * 1.0001
+
+
+# --- the dense tall-skinny products of Rayleigh-Ritz on the matrix cores (section 4.2) --------
+
+@pytest.mark.parametrize("n,m,mout", [(1, 1, 1), (17, 3, 2), (1000, 16, 16), (4099, 17, 65), (70001, 90, 30),
+                                      (33333, 90, 89), (5000, 120, 120), (129, 5, 0)])
+def test_block_product_against_library_matmul(n, m, mout):
+    rng = np.random.default_rng(n + m + mout)
+    V = rng.standard_normal((m, n))   # stored transposed: column-major n x m on the device
+    S = rng.standard_normal((mout, m))
+    dV = torch.as_tensor(V, device="cuda").t()
+    dS = torch.as_tensor(S, device="cuda").t()
+    dO = torch.full((mout, n), float("nan"), dtype=torch.float64, device="cuda").t()
+    jd.block_product(dV, dS, dO, stream=stream())
+    torch.cuda.synchronize()
+    ref = V.T @ S.T
+    bound = 2 * m * np.finfo(float).eps * (np.abs(V.T) @ np.abs(S.T))
+    assert np.all(np.abs(dO.cpu().numpy() - ref) <= bound + 1e-300)
