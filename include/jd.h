@@ -62,11 +62,12 @@ enum { JD_MODEL_ANDERSON = 0, JD_MODEL_OFFDIAG = 1 };
 
 /*
  * Options; a zero-initialised struct selects every default.
- *  precision  JD_FP64: every step in binary64.  JD_MIXED: stencil SpMV in
- *             binary32; preconditioner factors and the inner SQMR vectors stored in
- *             binary32, with dot products and factor products accumulated in
- *             binary64 and rounded once (the level-by-level apply of JD_FLAG_LEVELS
- *             accumulates in binary32); Gram-Schmidt, Rayleigh-Ritz, residual norms
+ *  precision  JD_FP64: every step in binary64.  JD_MIXED: inner SQMR vectors and
+ *             preconditioner factors stored in binary32; the inner stencil product
+ *             applies the binary64 operator to the binary32 vector, and dot products
+ *             and factor products accumulate in binary64, each result rounded once
+ *             (the level-by-level apply of JD_FLAG_LEVELS accumulates in binary32);
+ *             Gram-Schmidt, Rayleigh-Ritz, residual norms
  *             and acceptance in binary64.  JD_MIXED_FACTORS: only the preconditioner
  *             factors stored in binary32; stencil product and SQMR vectors in binary64.
  *  drop_tol   epsilon of section 7.2: an entry of a factor column is dropped when
@@ -90,18 +91,17 @@ enum { JD_MODEL_ANDERSON = 0, JD_MODEL_OFFDIAG = 1 };
  *             domain) are dropped (0 -> min(1e-2, 10 drop_tol); < 0 -> none).
  *  z_parts    the number S of segments: level cuts at 1, 3, 9, 27, ... (0 -> 6 for
  *             n >= 2^19, 4 for n >= 2^16, else 3; 1 -> a single explicit inverse).
- *  jmin, jmax search-space sizes after / before a restart (0 -> for n >= 2^19 or a
- *             setup that stalled (see kappa): max(k+20,30) and min(3 jmin, 120), else
- *             max(k+5,10) and min(2 jmin, 120)); jmin < 120, jmax <= 120, and
+ *  jmin, jmax search-space sizes after / before a restart (0 -> after a setup that
+ *             stalled (see kappa): max(k+20,30) and min(3 jmin, 120); else for
+ *             n >= 2^19: max(k+10,20) and min(3 jmin, 120); else max(k+5,10) and
+ *             min(2 jmin, 120)); jmin < 120, jmax <= 120, and
  *             jmin < jmax when both are given (JD_EINVAL otherwise); a jmin given
  *             alone raises the default jmax to at least jmin + 1.
  *  max_outer  outer Jacobi-Davidson iterations (0 -> 60 k + 200).
  *  max_inner  SQMR steps per correction equation (0 -> 40, or 80 after a setup that
  *             stalled).
  *  switch_tol the correction operator uses sigma until ||r|| < switch_tol ||A||_inf,
- *             then the Ritz value theta; < 0: always sigma (0 -> 1e-3, and always
- *             sigma for JD_MIXED, whose binary32 inner solves lose accuracy on the
- *             nearly singular A - theta I).
+ *             then the Ritz value theta; < 0: always sigma (0 -> 1e-3).
  *  flags      bit 0 (JD_FLAG_GRAPHS): replay the inner iteration as a captured HIP graph
  *             instead of launching it kernel by kernel (same kernels in the same order,
  *             same results; the serving workers always launch kernel by kernel).

@@ -286,21 +286,13 @@ struct Setup {
     int bc = JD_BC_PERIODIC;
     int model = JD_MODEL_ANDERSON;
     double *hop64 = nullptr;  // bond values of the off-diagonal model (3 n), else NULL
-    float *hop32 = nullptr;
-    template <typename T>
-    const T *hop() const
-    {
-        if constexpr (std::is_same<T, float>::value) return hop32;
-        else return hop64;
-    }
     double W = 0, sigma = 0;
     uint64_t seed = 0;
     jd_options opt{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
     DevMem mem;
-    double *eps64 = nullptr;
-    float *eps32 = nullptr;
+    double *eps64 = nullptr;  // site energies; every precision applies this operator
     double anorm = 0;
     jdmi::Multilevel ml;
     DevPrecond<double> pc64;
@@ -314,15 +306,19 @@ constexpr double kOffdiagDiagonal = 1.28;
 
 // Default search-space sizes.  On large lattices the eigenvalues near sigma are
 // ~1 / (n rho) apart and a larger space carries the outer iteration further per
-// correction (at L = 100: 153 instead of 262 outer iterations with binary32 inner
-// solves, 76 instead of 83 in binary64); on small ones the host Rayleigh-Ritz of the
-// larger space costs more than it saves, unless the problem is hard: a multilevel
-// setup that stalled (W = 12 near the band centre) leaves a weaker preconditioner,
-// and there the larger space (with longer inner solves) is what converges at all.
+// correction (at L = 100, k = 10 with binary32 inner solves: 20 / 60 takes 106 outer
+// iterations and 1.29 s, 30 / 90 takes 109 and 1.36 s, and the small-lattice 15 / 30
+// took about twice as many outer iterations); on small ones the host Rayleigh-Ritz of
+// the larger space costs more than it saves.  A multilevel setup that stalled (W = 12
+// near the band centre) leaves a weaker preconditioner, and there the largest space
+// (with longer inner solves) is what converges at all.
 void default_search_space(int k, int64_t n, int &jmin, int &jmax, bool hard = false)
 {
-    if (hard || n >= (int64_t(1) << 19)) {
+    if (hard) {
         jmin = std::max(k + 20, 30);
+        jmax = std::min(3 * jmin, 120);
+    } else if (n >= (int64_t(1) << 19)) {
+        jmin = std::max(k + 10, 20);
         jmax = std::min(3 * jmin, 120);
     } else {
         jmin = std::max(k + 5, 10);
@@ -425,25 +421,21 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
     S.mem.stream = S.stream;
     const int n = S.n;
     S.eps64 = S.mem.alloc<double>(n);
-    S.eps32 = S.mem.alloc<float>(n);
     S.bc = S.opt.bc;
     S.model = S.opt.model;
     std::vector<double> eps(n), hop;
     if (S.model == JD_MODEL_OFFDIAG) {
         // section 8.2: constant diagonal, random bond values of width W
         std::fill(eps.begin(), eps.end(), kOffdiagDiagonal);
-        std::vector<float> e32(n, float(kOffdiagDiagonal));
         HIPCHK(hipMemcpyAsync(S.eps64, eps.data(), n * sizeof(double), hipMemcpyHostToDevice, S.stream));
-        HIPCHK(hipMemcpyAsync(S.eps32, e32.data(), n * sizeof(float), hipMemcpyHostToDevice, S.stream));
         S.hop64 = S.mem.alloc<double>(3 * size_t(n));
-        S.hop32 = S.mem.alloc<float>(3 * size_t(n));
-        jdmi::launch_gen_hop(L, W, seed, S.hop64, S.hop32, S.stream);
+        jdmi::launch_gen_hop(L, W, seed, S.hop64, nullptr, S.stream);
         HIPCHK(hipGetLastError());
         hop.resize(3 * size_t(n));
         HIPCHK(hipMemcpyAsync(hop.data(), S.hop64, hop.size() * sizeof(double), hipMemcpyDeviceToHost, S.stream));
         HIPCHK(hipStreamSynchronize(S.stream));
     } else {
-        jdmi::launch_gen_diag(L, W, seed, S.eps64, S.eps32, S.stream);
+        jdmi::launch_gen_diag(L, W, seed, S.eps64, nullptr, S.stream);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(eps.data(), S.eps64, n * sizeof(double), hipMemcpyDeviceToHost, S.stream));
         HIPCHK(hipStreamSynchronize(S.stream));
@@ -577,7 +569,6 @@ template <typename T, typename P>
 struct Solver {
     Setup &S;
     const P &pc;
-    const T *eps;
     hipStream_t s;
     int n;
     bool graphs;
@@ -588,8 +579,8 @@ struct Solver {
     std::vector<Pair> cache;
     bool noalloc = false;
 
-    Solver(Setup &S_, const P &pc_, const T *eps_, bool graphs_)
-        : S(S_), pc(pc_), eps(eps_), s(S_.stream), n(S_.n), graphs(graphs_), mem(S_.stream)
+    Solver(Setup &S_, const P &pc_, bool graphs_)
+        : S(S_), pc(pc_), s(S_.stream), n(S_.n), graphs(graphs_), mem(S_.stream)
     {
         B.r = mem.alloc<T>(n);
         B.q = mem.alloc<T>(n);
@@ -614,8 +605,8 @@ struct Solver {
     // Buffers supplied by the caller (every device pointer of bufs; flags_host unused):
     // nothing is allocated, no events or graphs are created, and the host reads the stop
     // flag synchronously after every few steps instead of one step behind.
-    Solver(Setup &S_, const P &pc_, const T *eps_, const SqmrBufs<T> &bufs)
-        : S(S_), pc(pc_), eps(eps_), s(S_.stream), n(S_.n), graphs(false), B(bufs), mem(S_.stream), noalloc(true)
+    Solver(Setup &S_, const P &pc_, const SqmrBufs<T> &bufs)
+        : S(S_), pc(pc_), s(S_.stream), n(S_.n), graphs(false), B(bufs), mem(S_.stream), noalloc(true)
     {
         B.flags_host = nullptr;
     }
@@ -647,7 +638,7 @@ struct Solver {
         const int *skip_a = &B.st->done;
         const int *skip_b = &B.st->done_next;
         // t = (I - Qt Qt^T)(A - shift I) q
-        jdmi::launch_stencil_state<T>(S.L, S.bc, eps, B.st, B.q, B.t, s, S.template hop<T>());
+        jdmi::launch_stencil_state<T>(S.L, S.bc, S.eps64, B.st, B.q, B.t, s, S.hop64);
         if (p > 0) {
             jdmi::launch_multidot<T>(n, p, Qt, n, B.t, B.partial, B.coef, s, skip_a);
             jdmi::launch_sub_qc<T>(n, p, Qt, n, B.coef, B.t, s, skip_a);
@@ -841,7 +832,7 @@ void fill_setup_info(const Setup &S, jd_info *info)
 }
 
 template <typename T, typename P>
-int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, jd_info *info)
+int jd_run(Setup &S, const P &pc, int k, double tol, Outputs out, jd_info *info)
 {
     const double t0 = now_s();
     const int n = S.n;
@@ -856,9 +847,9 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
     jmax = std::max(jmax, jmin + 1);
     const int max_inner = o.max_inner > 0 ? o.max_inner : (hard ? 80 : 40);
     // the correction operator's shift moves from sigma to theta once ||r|| < switch_tol
-    // ||A||; binary32 inner solves keep sigma (near convergence A - theta I is singular
-    // to binary32 accuracy)
-    const double switch_tol = o.switch_tol != 0 ? o.switch_tol : (o.precision == JD_MIXED ? -1.0 : 1e-3);
+    // ||A|| (also for binary32 inner vectors: their operator is the binary64 one, so
+    // A - theta I is not perturbed by the rounding of eps)
+    const double switch_tol = o.switch_tol != 0 ? o.switch_tol : 1e-3;
     const int max_outer = o.max_outer > 0 ? o.max_outer : 60 * k + 200;
     // smallest relative tolerance of a correction equation's SQMR solve
     const double inner_floor = o.inner_tol_min > 0 ? o.inner_tol_min : 1e-10;
@@ -866,7 +857,7 @@ int jd_run(Setup &S, const P &pc, const T *eps, int k, double tol, Outputs out, 
     const double anorm = S.anorm;
     const double sigma = S.sigma;
 
-    Solver<T, P> sv(S, pc, eps, (o.flags & JD_FLAG_GRAPHS) != 0);
+    Solver<T, P> sv(S, pc, (o.flags & JD_FLAG_GRAPHS) != 0);
     DevMem mem(s);
     double *V = mem.alloc<double>(size_t(n) * jmax);
     double *AV = mem.alloc<double>(size_t(n) * jmax);
@@ -1134,7 +1125,7 @@ int si_lanczos_run(Setup &S, const P &pc, int k, double tol, double inner_tol, O
     const int max_inner = o.max_inner > 0 ? o.max_inner : 1000;
     const double anorm = S.anorm;
     const double shift_norm = anorm + std::fabs(S.sigma);  // >= ||A - sigma I||_inf
-    Solver<double, P> sv(S, pc, S.eps64, false);
+    Solver<double, P> sv(S, pc, false);
     DevMem mem(s);
     const int ld = mmax + 1;
     double *V = mem.alloc<double>(size_t(n) * ld);
@@ -1504,12 +1495,12 @@ int jd_problem_solve(jd_problem *p, int k, double tol, double *evals, double *ev
         if (!p) throw JdError(JD_EINVAL, "NULL problem");
         check_solve_args(p->S.n, k, tol, evals);
         Outputs o{evals, evecs_host, resid, evecs_device};
-        if (p->S.opt.precision == JD_MIXED) return jd_run<float>(p->S, p->S.pc32, p->S.eps32, k, tol, o, info);
+        if (p->S.opt.precision == JD_MIXED) return jd_run<float>(p->S, p->S.pc32, k, tol, o, info);
         if (p->S.opt.precision == JD_MIXED_FACTORS) {
             MixedPrecond mp{p->S.pc32, p->S.pc64};
-            return jd_run<double>(p->S, mp, p->S.eps64, k, tol, o, info);
+            return jd_run<double>(p->S, mp, k, tol, o, info);
         }
-        return jd_run<double>(p->S, p->S.pc64, p->S.eps64, k, tol, o, info);
+        return jd_run<double>(p->S, p->S.pc64, k, tol, o, info);
     });
 }
 
@@ -1828,10 +1819,10 @@ int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int 
         Setup &S = p->S;
         const int n = S.n;
         hipStream_t s = S.stream;
-        auto run = [&](auto tag, const auto &pc, const auto *eps) {
+        auto run = [&](auto tag, const auto &pc) {
             using T = decltype(tag);
             using PC = std::decay_t<decltype(pc)>;
-            Solver<T, PC> sv(S, pc, eps, (S.opt.flags & JD_FLAG_GRAPHS) != 0);
+            Solver<T, PC> sv(S, pc, (S.opt.flags & JD_FLAG_GRAPHS) != 0);
             DevMem mem(s);
             T *Qt = mem.alloc<T>(size_t(n) * std::max(pcols, 1));
             T *Y = mem.alloc<T>(size_t(n) * std::max(pcols, 1));
@@ -1841,9 +1832,9 @@ int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int 
                                              work.data(), h.data());
             if (its) *its = k_;
         };
-        if (S.opt.precision == JD_MIXED) run(float(0), S.pc32, S.eps32);
-        else if (S.opt.precision == JD_MIXED_FACTORS) run(double(0), MixedPrecond{S.pc32, S.pc64}, S.eps64);
-        else run(double(0), S.pc64, S.eps64);
+        if (S.opt.precision == JD_MIXED) run(float(0), S.pc32);
+        else if (S.opt.precision == JD_MIXED_FACTORS) run(double(0), MixedPrecond{S.pc32, S.pc64});
+        else run(double(0), S.pc64);
         return JD_OK;
     });
 }
@@ -1856,7 +1847,7 @@ int jd_problem_linear_solve_noalloc(jd_problem *p, double shift, const double *d
         Setup &S = p->S;
         const int n = S.n;
         unsigned char *base = static_cast<unsigned char *>(scratch_address());
-        auto run = [&](auto tag, const auto &pc, const auto *eps) {
+        auto run = [&](auto tag, const auto &pc) {
             using T = decltype(tag);
             using PC = std::decay_t<decltype(pc)>;
             // carve the scratch array: reduction partials and small results, the solver
@@ -1887,7 +1878,7 @@ int jd_problem_linear_solve_noalloc(jd_problem *p, double shift, const double *d
             B.st = reinterpret_cast<jdmi::SqmrState *>(base + o_st);
             T **vec[7] = {&B.r, &B.q, &B.t, &B.d, &B.x, &B.u, &B.b};
             for (int i = 0; i < 7; ++i) *vec[i] = reinterpret_cast<T *>(base + o_vec[i]);
-            Solver<T, PC> sv(S, pc, eps, B);
+            Solver<T, PC> sv(S, pc, B);
             // the p x p matrices live on the stack (p <= 64)
             double Mh[64 * 64 + 1], work[64 * 64 + 1], h[65];
             const int k_ = linear_solve_core(sv, shift, d_Q, pcols, d_b, d_x, rtol, maxit,
@@ -1895,9 +1886,9 @@ int jd_problem_linear_solve_noalloc(jd_problem *p, double shift, const double *d
                                              reinterpret_cast<double *>(base + o_m), Mh, work, h);
             if (its) *its = k_;
         };
-        if (S.opt.precision == JD_MIXED) run(float(0), S.pc32, S.eps32);
-        else if (S.opt.precision == JD_MIXED_FACTORS) run(double(0), MixedPrecond{S.pc32, S.pc64}, S.eps64);
-        else run(double(0), S.pc64, S.eps64);
+        if (S.opt.precision == JD_MIXED) run(float(0), S.pc32);
+        else if (S.opt.precision == JD_MIXED_FACTORS) run(double(0), MixedPrecond{S.pc32, S.pc64});
+        else run(double(0), S.pc64);
         return JD_OK;
     });
 }

@@ -124,10 +124,11 @@ template <typename T>
 void launch_sqmr_init(int n, const T *b, T *r, T *x, T *d, hipStream_t s);
 void launch_sqmr_params(SqmrState *st, double shift, double tol, hipStream_t s);
 void launch_sqmr_scalar_start(SqmrState *st, const double *rr, const double *rho, hipStream_t s);
-// t = (A - st->shift I) q, skipped when st->done
+// t = (A - st->shift I) q with the binary64 operator (eps, bond values) applied to q and
+// the result rounded once; skipped when st->done
 template <typename T>
-void launch_stencil_state(int L, int bc, const T *eps, const SqmrState *st, const T *x, T *y, hipStream_t s,
-                          const T *hop = nullptr);
+void launch_stencil_state(int L, int bc, const double *eps, const SqmrState *st, const T *x, T *y, hipStream_t s,
+                          const double *hop = nullptr);
 template <typename T>
 void launch_copy(int n, const T *x, T *y, hipStream_t s);
 // sigma = q.t (stored in *sigma) and, in the same final reduction, alpha = rho / sigma

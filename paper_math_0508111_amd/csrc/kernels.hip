@@ -168,23 +168,69 @@ void launch_stencil(int L, int bc, const T *eps, double shift, const T *x, T *y,
                        hop);
 }
 
-// the same product with the shift read from the solver state (graph-replayable)
+// The product of the inner iteration, with the shift read from the solver state
+// (graph-replayable).  The operator is the binary64 one (eps and bond values in
+// binary64) applied to the stored vector x of either precision, and the result is
+// rounded once: binary32 inner vectors then see rounding of the product only, not an
+// operator perturbed by eps rounded to binary32 (near sigma that perturbation, of order
+// 1e-7 ||A||, is not small against the eigenvalue spacing).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_stencil_state(int L, int n, int bc, const T *__restrict__ eps,
+__device__ inline double bond_sum64(int L, int n, int s, const T *__restrict__ x, const double *__restrict__ hop, int bc)
+{
+    const int LL = L * L;
+    const int c[3] = {s % L, (s / L) % L, s / LL};
+    const int stride[3] = {1, L, LL};
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double *t = hop + size_t(d) * n;
+        const int up = c[d] == L - 1 ? s - (L - 1) * stride[d] : s + stride[d];
+        const int dn = c[d] == 0 ? s + (L - 1) * stride[d] : s - stride[d];
+        const bool has_up = bc == 0 || c[d] < L - 1, has_dn = bc == 0 || c[d] > 0;
+        const double a = has_up ? t[s] * double(x[up]) : 0.0;
+        const double b = has_dn ? t[dn] * double(x[dn]) : 0.0;
+        acc += a + b;
+    }
+    return acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_stencil_state(int L, int n, int bc, const double *__restrict__ eps,
                                                           const SqmrState *st, const T *__restrict__ x,
-                                                          T *__restrict__ y, const T *__restrict__ hop)
+                                                          T *__restrict__ y, const double *__restrict__ hop)
 {
     if (st->done) return;
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
-    const T shift = T(st->shift);
-    if (hop) y[s] = (eps[s] - shift) * x[s] + bond_sum(L, n, s, x, hop, bc);
-    else y[s] = (eps[s] - shift) * x[s] - neighbour_sum(L, n, s, x, bc);
+    const double shift = st->shift;
+    const double xs = double(x[s]);
+    if (hop) {
+        y[s] = T((eps[s] - shift) * xs + bond_sum64(L, n, s, x, hop, bc));
+    } else {
+        const int LL = L * L;
+        const int i = s % L, jk = s / L, j = jk % L, k = jk / L;
+        double nb;
+        if (bc == 0) {
+            const int xm = (i == 0) ? s + L - 1 : s - 1;
+            const int xp = (i == L - 1) ? s - L + 1 : s + 1;
+            const int ym = (j == 0) ? s + LL - L : s - L;
+            const int yp = (j == L - 1) ? s - LL + L : s + L;
+            const int zm = (k == 0) ? s + n - LL : s - LL;
+            const int zp = (k == L - 1) ? s - n + LL : s + LL;
+            nb = ((double(x[xm]) + double(x[xp])) + (double(x[ym]) + double(x[yp]))) + (double(x[zm]) + double(x[zp]));
+        } else {
+            const double xm = i > 0 ? double(x[s - 1]) : 0.0, xp = i < L - 1 ? double(x[s + 1]) : 0.0;
+            const double ym = j > 0 ? double(x[s - L]) : 0.0, yp = j < L - 1 ? double(x[s + L]) : 0.0;
+            const double zm = k > 0 ? double(x[s - LL]) : 0.0, zp = k < L - 1 ? double(x[s + LL]) : 0.0;
+            nb = ((xm + xp) + (ym + yp)) + (zm + zp);
+        }
+        y[s] = T((eps[s] - shift) * xs - nb);
+    }
 }
 
 template <typename T>
-void launch_stencil_state(int L, int bc, const T *eps, const SqmrState *st, const T *x, T *y, hipStream_t s,
-                          const T *hop)
+void launch_stencil_state(int L, int bc, const double *eps, const SqmrState *st, const T *x, T *y, hipStream_t s,
+                          const double *hop)
 {
     const int n = L * L * L;
     hipLaunchKernelGGL(k_stencil_state<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, L, n, bc, eps, st, x, y, hop);
@@ -1002,8 +1048,8 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
 #define JD_INST(T)                                                                                        \
     template void launch_stencil<T>(int, int, const T *, double, const T *, T *, hipStream_t, const int *,       \
                                     const T *);                                                                 \
-    template void launch_stencil_state<T>(int, int, const T *, const SqmrState *, const T *, T *, hipStream_t,  \
-                                          const T *);                                                           \
+    template void launch_stencil_state<T>(int, int, const double *, const SqmrState *, const T *, T *,         \
+                                          hipStream_t, const double *);                                         \
     template void launch_copy<T>(int, const T *, T *, hipStream_t);                                       \
     template void launch_gather<T>(int, const int *, const T *, T *, hipStream_t, const int *);            \
     template void launch_scatter<T>(int, const int *, const T *, T *, hipStream_t, const int *);           \

@@ -108,11 +108,13 @@ def _check_closed_form(L, sigma, k, evals, evecs, resid, vals, bc="periodic"):
         done[members] = True
         mask = np.abs(lam3 - evals[c]) <= 1e-7
         assert mask.sum() == len(members), (evals[c], mask.sum(), len(members))
-        Y = xhat[members][:, mask].T  # (wave vectors of the cluster) x (its vectors)
-        smin = np.linalg.svd(Y, compute_uv=False).min()
+        # the sine of the largest principal angle is the norm of the cluster vectors'
+        # component outside the eigenspace (taken directly: sqrt(1 - cos^2) cannot
+        # resolve angles below about 2e-8)
+        Y = xhat[members][:, ~mask]  # (its vectors) x (the other wave vectors)
         others = vals[np.abs(vals - evals[c]) > 1e-7]
         gap = np.min(np.abs(others - evals[c]))
-        sin_max = np.sqrt(max(0.0, 1.0 - smin ** 2))
+        sin_max = np.sqrt(max(0.0, np.linalg.eigvalsh(Y @ Y.conj().T).max()))
         assert sin_max <= 10 * 1e-10 * anorm / gap + 1e-12, (evals[c], sin_max)
 
 
