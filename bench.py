@@ -43,6 +43,12 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="preconditioner parameter study (kappa, epsilon, z_drop, last-level size, segments) "
                          "at the benchmark lattice: one JSON line per setting")
+    ap.add_argument("--table5", action="store_true",
+                    help="the epsilon x kappa grid of the paper's Table 5 (use with --L 70 --k 5): one JSON "
+                         "line per setting")
+    ap.add_argument("--lanczos", action="store_true",
+                    help="JD against shift-and-invert Lanczos on one setup of the benchmark lattice "
+                         "(binary64 and binary32-factor splits): one JSON line")
     ap.add_argument("--kernels-only", action="store_true",
                     help="setup, then only launches of the dominant kernel and a 256 MB copy "
                          "(for hardware counter runs)")
@@ -201,9 +207,11 @@ def apply_roofline(torch, prob, n, reps=20):
 SWEEP = [dict()] + [dict(kappa=v) for v in (2.5, 10.0, 20.0)] + [dict(drop_tol=v) for v in (1e-2, 5e-3, 2.5e-3)] \
     + [dict(z_drop=v) for v in (2e-2, 5e-3)] + [dict(coarse_max=v) for v in (4096, 8192)] \
     + [dict(z_parts=v) for v in (1, 4, 8)]
+# the grid of the paper's Table 5 (epsilon x kappa, at M = 70, five eigenvalues nearest 0)
+TABLE5 = [dict(drop_tol=e, kappa=k) for k in (5.0, 10.0, 20.0) for e in (1e-2, 5e-3, 2.5e-3, 1e-3)]
 
 
-def sweep(jd, torch, L, k, tol=1e-10):
+def sweep(jd, torch, L, k, tol=1e-10, settings=None):
     """Table 5 of the paper, on the GPU: the multilevel preconditioner's parameters one at
     a time around the defaults (kappa 5, epsilon 1/sqrt(n), z_drop min(1e-2, 10 epsilon),
     last level <= 1536, 6 segments): setup time, levels, fill, nnz of the coupling blocks
@@ -211,7 +219,7 @@ def sweep(jd, torch, L, k, tol=1e-10):
     import numpy as np
     n = L ** 3
     rows = []
-    for cfg in SWEEP:
+    for cfg in settings if settings is not None else SWEEP:
         t0 = time.time()
         prob = jd.Problem(L, 16.5, 0, 0.0, precision="mixed", **cfg)
         setup = time.time() - t0
@@ -244,6 +252,35 @@ def sweep(jd, torch, L, k, tol=1e-10):
         print(json.dumps(row), flush=True)
         rows.append(row)
     return rows
+
+
+def lanczos_leg(jd, L, k, tol=1e-10, W=16.5, seed=0, sigma=0.0):
+    """Section 4.1 / Tables 2-3 of the paper on the GPU: the same k pairs nearest sigma by
+    Jacobi-Davidson and by shift-and-invert Lanczos (each product with (A - sigma I)^-1 an
+    SQMR solve to 1e-10 with the same multilevel preconditioner), from one setup, with
+    binary64 vectors and binary64 or binary32 factors."""
+    import numpy as np
+    t0 = time.time()
+    prob = jd.Problem(L, W, seed, sigma, precision="mixed")
+    setup = time.time() - t0
+    print(f"# lanczos leg: setup {setup:.1f} s", file=sys.stderr, flush=True)
+    out = {"L": L, "W": W, "seed": seed, "sigma": sigma, "k": k, "tol": tol, "setup_s": round(setup, 2)}
+    for prec in ("fp64", "mixed_factors"):
+        prob.set_precision(prec)
+        ev_jd, _, res_jd, i_jd = prob.solve(k, tol)
+        print(f"# {prec} JD {i_jd['solve_s']:.3f} s", file=sys.stderr, flush=True)
+        ev_l, _, res_l, i_l = prob.lanczos(k, tol)
+        print(f"# {prec} SI-Lanczos {i_l['solve_s']:.3f} s", file=sys.stderr, flush=True)
+        out[prec] = {
+            "jd": {"solve_s": round(i_jd["solve_s"], 3), "outer": i_jd["outer_its"], "inner": i_jd["inner_its"],
+                   "converged": i_jd["n_converged"], "max_resid": float(np.nanmax(res_jd))},
+            "si_lanczos": {"solve_s": round(i_l["solve_s"], 3), "products": i_l["outer_its"], "inner": i_l["inner_its"],
+                           "converged": i_l["n_converged"], "status": i_l["status"],
+                           "max_resid": float(np.nanmax(res_l))},
+            "max_abs_eval_diff": float(np.nanmax(np.abs(np.sort(ev_jd) - np.sort(ev_l)))),
+        }
+    prob.close()
+    return out
 
 
 def serving(jd, nreq, workers, warm=8):
@@ -377,8 +414,12 @@ def main():
     if a.kernels_only:
         kernels_only(jd, torch, a.L)
         return
-    if a.sweep:
-        print(json.dumps({"sweep": sweep(jd, torch, a.L, a.k), "L": a.L, "k": a.k}), flush=True)
+    if a.sweep or a.table5:
+        rows = sweep(jd, torch, a.L, a.k, settings=TABLE5 if a.table5 else None)
+        print(json.dumps({"sweep": rows, "L": a.L, "k": a.k}), flush=True)
+        return
+    if a.lanczos:
+        print(json.dumps({"lanczos": lanczos_leg(jd, a.L, a.k)}), flush=True)
         return
     if a.serve_only:
         print(json.dumps({"serving": serving(jd, a.serve_requests, a.serve_workers, a.serve_warmup)}), flush=True)

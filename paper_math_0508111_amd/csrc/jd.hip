@@ -163,17 +163,24 @@ struct DevPrecond {
         d.nlong = int(h.long_row.size());
         d.nslices = int(h.slice_ptr.size()) - 1;
         for (int k = 0; k < jdmi::kHybParts; ++k) {
-            d.tbeg[k] = h.tbeg[k];
-            d.tend[k] = h.tend[k];
+            d.ntask[k] = h.ntask[k];
+            d.plong[k] = h.plong[k];
+            d.long0[k] = h.long0[k];
+            d.slice0[k] = h.slice0[k];
         }
-        d.task = mem.upload(h.task, s);
         d.long_row = mem.upload(h.long_row, s);
         d.long_ptr = mem.upload(h.long_ptr, s);
         d.long_col = mem.upload(h.long_col, s);
         d.long_val = mem.upload(cast_vec<T>(h.long_val), s);
-        d.slice_ptr = mem.upload(h.slice_ptr, s);
-        d.slice_row = mem.upload(h.slice_row, s);
-        d.rowidx = mem.upload(h.rowidx, s);
+        std::vector<int64_t> desc(2 * h.slice_ptr.size());
+        for (size_t i = 0; i < h.slice_ptr.size(); ++i) {
+            desc[2 * i] = h.slice_ptr[i];
+            desc[2 * i + 1] = h.slice_row[i];
+        }
+        d.slice_desc = mem.upload(desc, s);
+        std::vector<int> rows(h.rowidx);
+        rows.resize(rows.size() + 64, -1);  // every lane of the last slice reads a row number
+        d.rowidx = mem.upload(rows, s);
         d.col = mem.upload(h.col, s);
         d.val = mem.upload(cast_vec<T>(h.val), s);
         return d;
@@ -244,11 +251,11 @@ struct DevPrecond {
             // (region 0 -> 1), Z_{S-1}^T .. Z_1^T, Z_0^T with the output permutation
             T *r1 = buf + size_t(n), *r2 = buf + 2 * size_t(n);
             jdmi::launch_gather<T>(n, site_of, in, r2, s, skip);
-            for (const auto &z : zdown) jdmi::launch_hyb_spmv<T, T>(z, buf, buf, nullptr, s, skip);
+            for (const auto &z : zdown) jdmi::launch_hyb_spmv<T, T>(z, buf, buf, s, skip);
             jdmi::launch_dinv<T>(n, dd, dof, dp, buf, r1, s, skip);
             jdmi::launch_coarse_idx<T>(coarse_n, cld, cidx, cinv, buf, yc, r1, s, skip);
-            for (int i = int(zup.size()) - 1; i >= 1; --i) jdmi::launch_hyb_spmv<T, T>(zup[i], buf, buf, nullptr, s, skip);
-            jdmi::launch_hyb_spmv<T, T>(zup[0], buf, out, site_of, s, skip);
+            for (int i = int(zup.size()) - 1; i >= 1; --i) jdmi::launch_hyb_spmv<T, T>(zup[i], buf, buf, s, skip);
+            jdmi::launch_hyb_spmv<T, T>(zup[0], buf, out, s, skip);  // rows are the output sites
             return;
         }
         jdmi::launch_gather<T>(n, perm, in, w, s, skip);
@@ -272,12 +279,12 @@ struct MixedPrecond {
         const int n = pd.n;
         double *buf = pd.buf, *r1 = buf + size_t(n), *r2 = buf + 2 * size_t(n);
         jdmi::launch_gather<double>(n, pd.site_of, in, r2, s, skip);
-        for (const auto &z : pc.zdown) jdmi::launch_hyb_spmv<float, double>(z, buf, buf, nullptr, s, skip);
+        for (const auto &z : pc.zdown) jdmi::launch_hyb_spmv<float, double>(z, buf, buf, s, skip);
         jdmi::launch_dinv<double>(n, pd.dd, pd.dof, pd.dp, buf, r1, s, skip);
         jdmi::launch_coarse_idx<double>(pd.coarse_n, pd.cld, pd.cidx, pd.cinv, buf, pd.yc, r1, s, skip);
         for (int i = int(pc.zup.size()) - 1; i >= 1; --i)
-            jdmi::launch_hyb_spmv<float, double>(pc.zup[i], buf, buf, nullptr, s, skip);
-        jdmi::launch_hyb_spmv<float, double>(pc.zup[0], buf, out, pd.site_of, s, skip);
+            jdmi::launch_hyb_spmv<float, double>(pc.zup[i], buf, buf, s, skip);
+        jdmi::launch_hyb_spmv<float, double>(pc.zup[0], buf, out, s, skip);
     }
 };
 
@@ -1705,13 +1712,14 @@ int jd_precond_factor_product(jd_precond *p, int precision, int transpose, const
             T *buf = pc.buf;
             if (!transpose) {
                 if (x) HIPCHK(hipMemcpyAsync(buf + 2 * n, x, n * sizeof(T), hipMemcpyDeviceToDevice, s));
-                for (const auto &z : pc.zdown) jdmi::launch_hyb_spmv<T, T>(z, buf, buf, nullptr, s, nullptr);
+                for (const auto &z : pc.zdown) jdmi::launch_hyb_spmv<T, T>(z, buf, buf, s, nullptr);
                 if (y) HIPCHK(hipMemcpyAsync(y, buf, n * sizeof(T), hipMemcpyDeviceToDevice, s));
             } else {
                 if (x) HIPCHK(hipMemcpyAsync(buf + n, x, n * sizeof(T), hipMemcpyDeviceToDevice, s));
                 for (int i = int(pc.zup.size()) - 1; i >= 1; --i)
-                    jdmi::launch_hyb_spmv<T, T>(pc.zup[i], buf, buf, nullptr, s, nullptr);
-                jdmi::launch_hyb_spmv<T, T>(pc.zup[0], buf, y ? y : buf, y ? pc.site_of : nullptr, s, nullptr);
+                    jdmi::launch_hyb_spmv<T, T>(pc.zup[i], buf, buf, s, nullptr);
+                // its rows are lattice sites: the timing form writes them into region 0
+                jdmi::launch_hyb_spmv<T, T>(pc.zup[0], buf, y ? y : buf, s, nullptr);
             }
         };
         if (precision == JD_FP64) go(p->S->pc64, static_cast<const double *>(d_x), static_cast<double *>(d_y));

@@ -66,21 +66,22 @@ void launch_coarse_idx(int nc, int ld, const int *idx, const T *cinv, const T *y
 template <typename Tv>
 struct Hyb {
     int nlong = 0, nslices = 0;
-    int tbeg[kHybParts] = {}, tend[kHybParts] = {};  // task range of each part
-    const int *task = nullptr;         // >= 0: long row index; < 0: slice -1 - task
+    // per part: tasks (long rows, then slices), long rows, first long row, first slice
+    int ntask[kHybParts] = {}, plong[kHybParts] = {}, long0[kHybParts] = {}, slice0[kHybParts] = {};
     const int *long_row = nullptr;     // row of each long row
     const int64_t *long_ptr = nullptr; // nlong + 1
     const int *long_col = nullptr;
     const Tv *long_val = nullptr;
-    const int64_t *slice_ptr = nullptr;  // nslices + 1, in entries (multiples of 64) | shape code
-    const int64_t *slice_row = nullptr;  // nslices + 1, first rowidx entry of each slice
-    const int *rowidx = nullptr;         // the slices' rows, -1 for padding rows
+    // 2 (nslices + 1) values: for slice s, [2 s] = its first entry (a multiple of 64) | shape
+    // code and [2 s + 1] = its first rowidx entry (one 16-byte load per slice boundary)
+    const int64_t *slice_desc = nullptr;
+    const int *rowidx = nullptr;         // the slices' rows, -1 for padding rows (+ 64 entries -1)
     const int *col = nullptr;
     const Tv *val = nullptr;
 };
-// out_perm (optional): y[out_perm[r]] = (Z w)[r]
+// y[r] = (Z w)[r] for every row number r of the layout
 template <typename Tv, typename Tx>
-void launch_hyb_spmv(const Hyb<Tv> &A, const Tx *x, Tx *y, const int *out_perm, hipStream_t s, const int *skip);
+void launch_hyb_spmv(const Hyb<Tv> &A, const Tx *x, Tx *y, hipStream_t s, const int *skip);
 
 // z[j] = dd[j] y[j] + dof[j] y[dp[j]] for j < m
 template <typename T>

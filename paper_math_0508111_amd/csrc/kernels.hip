@@ -414,84 +414,83 @@ void launch_coarse(int nc, int ld, int off, const T *cinv, const T *w, T *x, hip
 // ---------------------------------------------------------------------------------
 template <typename Tv, typename Tx>
 __global__ void __launch_bounds__(kBlock) k_hyb_spmv(Hyb<Tv> A, const Tx *__restrict__ x, Tx *__restrict__ y,
-                                                     const int *__restrict__ out_perm, const int *skip)
+                                                     const int *skip)
 {
     if (skip && *skip) return;
     const int part = blockIdx.x % kHybParts;
-    const int t = A.tbeg[part] + int(blockIdx.x / kHybParts) * (kBlock / 64) + int(threadIdx.x >> 6);
-    if (t >= A.tend[part]) return;
+    // the wave's task within its part (the same for its 64 lanes)
+    const int i = __builtin_amdgcn_readfirstlane(int(blockIdx.x / kHybParts) * (kBlock / 64) + int(threadIdx.x >> 6));
+    if (i >= A.ntask[part]) return;
     const int lane = threadIdx.x & 63;
-    const int code = A.task[t];
-    if (code >= 0) {
-        // one long row per wave: lanes stride over the row (four entries in flight per
-        // lane: all index and value loads are issued before the dependent gathers)
+    // Four entries per lane in flight: every index and value load of a batch is issued
+    // before its dependent gathers.  In a row's (or slice's) last batch a position past
+    // the end reads the last entry again with weight 0, so a batch never runs serially.
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (i < A.plong[part]) {
+        // one long row per wave: lanes stride over the row
+        const int code = A.long0[part] + i;
         const int64_t b = A.long_ptr[code], e = A.long_ptr[code + 1];
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int64_t p = b + lane;
-        for (; p + 192 < e; p += 256) {
-            const int c0 = nt_load(A.long_col + p), c1 = nt_load(A.long_col + p + 64);
-            const int c2 = nt_load(A.long_col + p + 128), c3 = nt_load(A.long_col + p + 192);
-            const Tv v0 = nt_load(A.long_val + p), v1 = nt_load(A.long_val + p + 64);
-            const Tv v2 = nt_load(A.long_val + p + 128), v3 = nt_load(A.long_val + p + 192);
+        const int r = A.long_row[code];
+        for (int64_t p = b + lane; p < e; p += 256) {
+            const int64_t q1 = min(p + 64, e - 1), q2 = min(p + 128, e - 1), q3 = min(p + 192, e - 1);
+            const int c0 = nt_load(A.long_col + p), c1 = nt_load(A.long_col + q1);
+            const int c2 = nt_load(A.long_col + q2), c3 = nt_load(A.long_col + q3);
+            const Tv v0 = nt_load(A.long_val + p), v1 = nt_load(A.long_val + q1);
+            const Tv v2 = nt_load(A.long_val + q2), v3 = nt_load(A.long_val + q3);
             a0 += double(v0) * double(x[c0]);
-            a1 += double(v1) * double(x[c1]);
-            a2 += double(v2) * double(x[c2]);
-            a3 += double(v3) * double(x[c3]);
+            a1 += (p + 64 < e ? double(v1) : 0.0) * double(x[c1]);
+            a2 += (p + 128 < e ? double(v2) : 0.0) * double(x[c2]);
+            a3 += (p + 192 < e ? double(v3) : 0.0) * double(x[c3]);
         }
-        for (; p < e; p += 64) a0 += double(nt_load(A.long_val + p)) * double(x[nt_load(A.long_col + p)]);
         double a = (a0 + a1) + (a2 + a3);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-        if (lane == 0) {
-            const int r = A.long_row[code];
-            y[out_perm ? out_perm[r] : r] = Tx(a);
-        }
+        if (lane == 0) y[r] = Tx(a);
         return;
     }
     // a slice of R = kSliceRows << sc short rows, 64 / R lanes per row
-    const int slice = -1 - code;
-    const int64_t p0 = A.slice_ptr[slice];
-    const int sc = int(p0 & 3);
+    const int slice = A.slice0[part] + (i - A.plong[part]);
+    const longlong2 d0 = reinterpret_cast<const longlong2 *>(A.slice_desc)[slice];
+    const longlong2 d1 = reinterpret_cast<const longlong2 *>(A.slice_desc)[slice + 1];
+    const int64_t p0 = d0.x, p1 = d1.x, rr = d0.y;
+    const int R = kSliceRows << int(p0 & 3);
     const int64_t b = p0 & ~int64_t(63);
-    const int groups = int(((A.slice_ptr[slice + 1] & ~int64_t(63)) - b) >> 6);
+    const int groups = int(((p1 & ~int64_t(63)) - b) >> 6);
+    // the slice's row numbers are loaded with its first entries (every lane loads: the
+    // array carries 64 entries of padding at its end)
+    const int rl = A.rowidx[rr + lane];
+    const int r = lane < R ? rl : -1;
     const int *c = A.col + b + lane;
     const Tv *v = A.val + b + lane;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int j = 0;
-    for (; j + 3 < groups; j += 4) {
-        const int64_t o = int64_t(j) * 64;
-        const int c0 = nt_load(c + o), c1 = nt_load(c + o + 64), c2 = nt_load(c + o + 128), c3 = nt_load(c + o + 192);
-        const Tv v0 = nt_load(v + o), v1 = nt_load(v + o + 64), v2 = nt_load(v + o + 128), v3 = nt_load(v + o + 192);
+    for (int j = 0; j < groups; j += 4) {
+        const int64_t o0 = int64_t(j) * 64, o1 = int64_t(min(j + 1, groups - 1)) * 64;
+        const int64_t o2 = int64_t(min(j + 2, groups - 1)) * 64, o3 = int64_t(min(j + 3, groups - 1)) * 64;
+        const int c0 = nt_load(c + o0), c1 = nt_load(c + o1), c2 = nt_load(c + o2), c3 = nt_load(c + o3);
+        const Tv v0 = nt_load(v + o0), v1 = nt_load(v + o1), v2 = nt_load(v + o2), v3 = nt_load(v + o3);
         a0 += double(v0) * double(x[c0]);
-        a1 += double(v1) * double(x[c1]);
-        a2 += double(v2) * double(x[c2]);
-        a3 += double(v3) * double(x[c3]);
+        a1 += (j + 1 < groups ? double(v1) : 0.0) * double(x[c1]);
+        a2 += (j + 2 < groups ? double(v2) : 0.0) * double(x[c2]);
+        a3 += (j + 3 < groups ? double(v3) : 0.0) * double(x[c3]);
     }
-    for (; j < groups; ++j) a0 += double(nt_load(v + int64_t(j) * 64)) * double(x[nt_load(c + int64_t(j) * 64)]);
     double a = (a0 + a1) + (a2 + a3);
     // lanes l, l + R, l + 2 R, ... hold the pieces of row l
-    const int R = kSliceRows << sc;
     for (int o = R; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
-    if (lane < R) {
-        const int r = A.rowidx[A.slice_row[slice] + lane];
-        if (r >= 0) y[out_perm ? out_perm[r] : r] = Tx(a);
-    }
+    if (r >= 0) y[r] = Tx(a);
 }
 
 template <typename Tv, typename Tx>
-void launch_hyb_spmv(const Hyb<Tv> &A, const Tx *x, Tx *y, const int *out_perm, hipStream_t s, const int *skip)
+void launch_hyb_spmv(const Hyb<Tv> &A, const Tx *x, Tx *y, hipStream_t s, const int *skip)
 {
     int most = 0;
-    for (int k = 0; k < kHybParts; ++k) most = std::max(most, A.tend[k] - A.tbeg[k]);
+    for (int k = 0; k < kHybParts; ++k) most = std::max(most, A.ntask[k]);
     if (most <= 0) return;
     const int blocks = kHybParts * ((most + kBlock / 64 - 1) / (kBlock / 64));
-    hipLaunchKernelGGL((k_hyb_spmv<Tv, Tx>), dim3(blocks), dim3(kBlock), 0, s, A, x, y, out_perm, skip);
+    hipLaunchKernelGGL((k_hyb_spmv<Tv, Tx>), dim3(blocks), dim3(kBlock), 0, s, A, x, y, skip);
 }
-template void launch_hyb_spmv<float, float>(const Hyb<float> &, const float *, float *, const int *, hipStream_t,
-                                            const int *);
-template void launch_hyb_spmv<double, double>(const Hyb<double> &, const double *, double *, const int *,
-                                              hipStream_t, const int *);
-template void launch_hyb_spmv<float, double>(const Hyb<float> &, const double *, double *, const int *, hipStream_t,
+template void launch_hyb_spmv<float, float>(const Hyb<float> &, const float *, float *, hipStream_t, const int *);
+template void launch_hyb_spmv<double, double>(const Hyb<double> &, const double *, double *, hipStream_t,
+                                              const int *);
+template void launch_hyb_spmv<float, double>(const Hyb<float> &, const double *, double *, hipStream_t,
                                              const int *);
 
 

@@ -1138,7 +1138,9 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L, int parts)
         std::vector<int> ucode(nu);
 #pragma omp parallel for schedule(dynamic, 256)
         for (int i = 0; i < nu; ++i) {
-            ucode[i] = int(s == 0 ? newidx[urow[i]] : n2 + midx[urow[i]]);
+            // the first segment's transposed product is the last of the apply: its rows
+            // are written straight to their lattice sites (the output permutation P^T)
+            ucode[i] = int(s == 0 ? Z.site_of[newidx[urow[i]]] : n2 + midx[urow[i]]);
             std::vector<std::pair<int, double>> row(size_t(tptr[i + 1] - tptr[i]));
             for (int64_t o = tptr[i]; o < tptr[i + 1]; ++o) row[o - tptr[i]] = {tcol[o], tval[o]};
             std::sort(row.begin(), row.end());
@@ -1189,7 +1191,6 @@ HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val, con
         for (int r = rb[part]; r < rb[part + 1]; ++r) (len(r) > kLongRow ? longr : shortr).push_back(r);
         std::stable_sort(longr.begin(), longr.end(), [&](int a, int b) { return len(a) > len(b); });
         for (int r : longr) {
-            h.task.push_back(int(h.long_row.size()));
             h.long_row.push_back(rcode(r));
             h.long_col.insert(h.long_col.end(), col + ptr[r], col + ptr[r + 1]);
             h.long_val.insert(h.long_val.end(), val + ptr[r], val + ptr[r + 1]);
@@ -1241,23 +1242,21 @@ HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val, con
                 }
             }
             h.slice_row.push_back(int64_t(h.rowidx.size()));
-            h.task.push_back(-int(h.slice_ptr.size() - 1));  // -1 - slice index within the part
             s0 += cnt;
         }
     }
     // offsets of every part in the concatenated arrays
-    struct Off { size_t task, long_row, long_ent, slice, slice_ent, rows; };
+    struct Off { size_t long_row, long_ent, slice, slice_ent, rows; };
     Off off[P + 1];
-    off[0] = {0, 0, 0, 0, 0, 0};
+    off[0] = {0, 0, 0, 0, 0};
     for (int part = 0; part < P; ++part) {
         const HybHost &q = parts[part];
-        off[part + 1] = {off[part].task + q.task.size(), off[part].long_row + q.long_row.size(),
-                         off[part].long_ent + q.long_col.size(), off[part].slice + (q.slice_ptr.size() - 1),
-                         off[part].slice_ent + q.col.size(), off[part].rows + q.rowidx.size()};
+        off[part + 1] = {off[part].long_row + q.long_row.size(), off[part].long_ent + q.long_col.size(),
+                         off[part].slice + (q.slice_ptr.size() - 1), off[part].slice_ent + q.col.size(),
+                         off[part].rows + q.rowidx.size()};
     }
     HybHost h;
     const Off &tot = off[P];
-    h.task.resize(tot.task);
     h.long_row.resize(tot.long_row);
     h.long_ptr.resize(tot.long_row + 1);
     h.long_col.resize(tot.long_ent);
@@ -1271,17 +1270,16 @@ HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val, con
     h.slice_ptr[0] = 0;
     h.slice_row[0] = 0;
     for (int part = 0; part < P; ++part) {
-        h.tbeg[part] = int(off[part].task);
-        h.tend[part] = int(off[part + 1].task);
+        const HybHost &q = parts[part];
+        h.plong[part] = int(q.long_row.size());
+        h.ntask[part] = int(q.long_row.size() + (q.slice_ptr.size() - 1));
+        h.long0[part] = int(off[part].long_row);
+        h.slice0[part] = int(off[part].slice);
     }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int part = 0; part < P; ++part) {
         const HybHost &q = parts[part];
         const Off &o = off[part];
-        for (size_t i = 0; i < q.task.size(); ++i) {
-            const int c = q.task[i];
-            h.task[o.task + i] = c >= 0 ? c + int(o.long_row) : c - int(o.slice);
-        }
         std::copy(q.long_row.begin(), q.long_row.end(), h.long_row.begin() + o.long_row);
         for (size_t i = 1; i < q.long_ptr.size(); ++i) h.long_ptr[o.long_row + i] = int64_t(o.long_ent) + q.long_ptr[i];
         std::copy(q.long_col.begin(), q.long_col.end(), h.long_col.begin() + o.long_ent);

@@ -84,7 +84,9 @@ struct SetupParams {
 // Device layout of a sparse product (built on the host; the kernel reads it as
 // jdmi::Hyb).  The rows are cut into kHybParts contiguous parts of equal nonzero count;
 // inside a part, rows with more than kLongRow entries are kept in CSR (longest first,
-// one wave each) and the other rows form slices of R = kSliceRows << c rows with
+// one wave each) and the other rows form slices (one wave each).  The tasks of part k are
+// its plong[k] long rows, numbered from long0[k], then its slices, numbered from
+// slice0[k]: ntask[k] in all.  The slices of R = kSliceRows << c rows with
 // g = kSliceLanes >> c lanes per row (c = 0..3: 8 x 8, 16 x 4, 32 x 2, 64 x 1, chosen
 // per slice to pad its longest row least): entry j of the slice's row l sits at
 // base + (j / g) * 64 + (j % g) * R + l, with base = slice_ptr[s] & ~63 and
@@ -99,8 +101,7 @@ constexpr int kLongRow = 96;
 constexpr int kSliceRows = 8;
 constexpr int kSliceLanes = 64 / kSliceRows;
 struct HybHost {
-    int tbeg[kHybParts] = {}, tend[kHybParts] = {};  // task range of each part
-    std::vector<int> task;                 // >= 0: long row index; < 0: slice -1 - task
+    int ntask[kHybParts] = {}, plong[kHybParts] = {}, long0[kHybParts] = {}, slice0[kHybParts] = {};
     std::vector<int> long_row;
     std::vector<int64_t> long_ptr{0};
     std::vector<int> long_col;
@@ -133,7 +134,7 @@ HybHost to_hyb(int nrows, const int64_t *ptr, const int *col, const double *val,
 //   D^{-1} and the last level: region 0 -> region 1;
 //   up, segment s = S-1 .. 1: writes its pivots to region 2, reading a position from
 //     region 2 when a later segment owns it, else from region 1;
-//   up, segment 0: every position, written through site_of to the output vector.
+//   up, segment 0: every position, its row numbers the lattice sites (the output vector).
 // The layouts store these element offsets directly as row and column numbers.
 constexpr int kMidBlock = 128;
 struct ZSegment {

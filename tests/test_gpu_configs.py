@@ -161,3 +161,19 @@ def test_hard_serving_request_against_certified_oracle():
         r = np.linalg.norm(lattice.matvec(L, eps, evecs[:, c]) - evals[c] * evecs[:, c])
         assert r <= 1e-10 * g["anorm"] * 1.0001
     assert np.abs(evecs.T @ evecs - np.eye(k)).max() <= 1e-8
+
+
+def test_stated_drop_tolerance_at_L50():
+    # L = 50, the five pairs nearest 0 in binary64 with the multilevel drop tolerance 1e-2
+    # (coarser than the 1/sqrt(n) = 2.8e-3 default), against the stored oracle result
+    g = _golden("L50_W16.5_s0_k5")
+    L, W, seed, sigma, k = g["L"], g["W"], g["seed"], g["sigma"], g["k"]
+    evals, evecs, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, vectors=True, precision="fp64",
+                                         drop_tol=1e-2)
+    assert info["status"] == 0 and info["n_converged"] == k
+    assert np.max(np.abs(np.sort(evals) - np.sort(np.array(g["lams"])))) <= 1e-9
+    eps = generator.disorder(L, W, seed)
+    for c in range(k):
+        r = np.linalg.norm(lattice.matvec(L, eps, evecs[:, c]) - evals[c] * evecs[:, c])
+        assert r <= 1e-10 * g["anorm"] * 1.0001
+    assert np.abs(evecs.T @ evecs - np.eye(k)).max() <= 1e-8
