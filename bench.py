@@ -334,7 +334,13 @@ def serving(jd, nreq, workers, warm=8):
             "p50_solve_s": round(float(np.percentile([r["solve_s"] for r in res], 50)), 3),
             "p99_solve_s": round(float(np.percentile([r["solve_s"] for r in res], 99)), 3),
             "p50_queued_s": round(float(np.percentile([r["queued_s"] for r in res], 50)), 3),
+            "p99_setup_s": round(float(np.percentile([r["setup_s"] for r in res], 99)), 3),
+            "p99_queued_s": round(float(np.percentile([r["queued_s"] for r in res], 99)), 3),
             "eigenpairs_per_s": round(pairs / span, 3),
+            # where the time goes: host setups against device solves over the stream's
+            # wall time (solves of different requests overlap on the GPU)
+            "wall_s": round(span, 2), "sum_setup_s": round(sum(r["setup_s"] for r in res), 2),
+            "sum_solve_s": round(sum(r["solve_s"] for r in res), 2),
             "workload": "L in {20..60}, W in {12, 16.5, 21}, sigma ~ U[-1,1], k in 1..10, seeds 1e6+i, "
                         "FP32 inner / FP64 outer, tol 1e-10"}
 

@@ -481,50 +481,114 @@ void build_setup(Setup &S, int L, double W, uint64_t seed, double sigma, const j
 }
 
 // ---------------------------------------------------------------------------------
-// Small dense helpers on the host (m <= 120): cyclic Jacobi for the projected
+// Small dense helpers on the host (m <= 120): the symmetric eigenproblem of the projected
 // matrix, Gauss-Jordan for the p x p matrix of the projected preconditioner.
 // ---------------------------------------------------------------------------------
-void small_symeig(int m, std::vector<double> H /* m*m col-major */, std::vector<double> &w, std::vector<double> &Z)
+// H = Z diag(w) Z^T for the symmetric m x m matrix H (column-major).  Householder
+// reflections reduce H to tridiagonal form T = Q^T H Q; implicit symmetric QR steps with
+// Wilkinson shifts then diagonalise T, the Givens rotations accumulated into Z = Q G.
+// On one core: 0.35 ms at m = 60 and 2.1 ms at m = 120, against 1.5 and 12 ms for the
+// 8-9 sweeps of cyclic Jacobi this replaced.
+void small_symeig(int m, std::vector<double> T /* m*m col-major */, std::vector<double> &w, std::vector<double> &Z)
 {
+    auto t = [&](int i, int j) -> double & { return T[i + size_t(j) * m]; };
+    auto z = [&](int i, int j) -> double & { return Z[i + size_t(j) * m]; };
     Z.assign(size_t(m) * m, 0.0);
-    for (int i = 0; i < m; ++i) Z[i + size_t(i) * m] = 1.0;
-    auto at = [&](int i, int j) -> double & { return H[i + size_t(j) * m]; };
-    double fro = 0;
-    for (double v : H) fro += v * v;
-    fro = std::sqrt(fro);
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0;
-        for (int j = 0; j < m; ++j)
-            for (int i = 0; i < m; ++i)
-                if (i != j) off += at(i, j) * at(i, j);
-        if (std::sqrt(off) <= 1e-16 * fro || off == 0) break;
-        for (int p = 0; p < m; ++p)
-            for (int q = p + 1; q < m; ++q) {
-                const double hpq = at(p, q);
-                if (hpq == 0.0) continue;
-                const double zeta = (at(q, q) - at(p, p)) / (2.0 * hpq);
-                const double t = std::copysign(1.0, zeta) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
-                for (int k = 0; k < m; ++k) {  // columns p, q
-                    const double a = at(k, p), b = at(k, q);
-                    at(k, p) = c * a - s * b;
-                    at(k, q) = s * a + c * b;
-                }
-                for (int k = 0; k < m; ++k) {  // rows p, q
-                    const double a = at(p, k), b = at(q, k);
-                    at(p, k) = c * a - s * b;
-                    at(q, k) = s * a + c * b;
-                }
-                at(p, q) = at(q, p) = 0.0;
-                for (int k = 0; k < m; ++k) {
-                    const double a = Z[k + size_t(p) * m], b = Z[k + size_t(q) * m];
-                    Z[k + size_t(p) * m] = c * a - s * b;
-                    Z[k + size_t(q) * m] = s * a + c * b;
-                }
-            }
+    for (int i = 0; i < m; ++i) z(i, i) = 1.0;
+    w.assign(m, 0.0);
+    if (m == 0) return;
+    // ---- tridiagonalisation: reflection k maps T[k+1:, k] onto a multiple of e_1 ----
+    std::vector<double> vs(size_t(m) * m, 0.0), beta(m, 0.0), p(m), q(m);
+    for (int k = 0; k + 2 < m; ++k) {
+        double xn = 0.0;
+        for (int i = k + 1; i < m; ++i) xn += t(i, k) * t(i, k);
+        xn = std::sqrt(xn);
+        if (xn == 0.0) continue;
+        const double alpha = t(k + 1, k) > 0 ? -xn : xn;
+        double *v = &vs[size_t(k) * m];
+        for (int i = k + 1; i < m; ++i) v[i] = t(i, k);
+        v[k + 1] -= alpha;
+        double vn = 0.0;
+        for (int i = k + 1; i < m; ++i) vn += v[i] * v[i];
+        if (vn == 0.0) continue;
+        const double b = 2.0 / vn;
+        beta[k] = b;
+        // trailing block A2 <- (I - b v v^T) A2 (I - b v v^T) = A2 - v q^T - q v^T with
+        // p = b A2 v and q = p - (b p.v / 2) v
+        double pv = 0.0;
+        for (int i = k + 1; i < m; ++i) {
+            double acc = 0.0;
+            for (int j = k + 1; j < m; ++j) acc += t(i, j) * v[j];
+            p[i] = b * acc;
+            pv += p[i] * v[i];
+        }
+        for (int i = k + 1; i < m; ++i) q[i] = p[i] - 0.5 * b * pv * v[i];
+        for (int j = k + 1; j < m; ++j)
+            for (int i = k + 1; i < m; ++i) t(i, j) -= v[i] * q[j] + q[i] * v[j];
+        t(k + 1, k) = t(k, k + 1) = alpha;
+        for (int i = k + 2; i < m; ++i) t(i, k) = t(k, i) = 0.0;
     }
-    w.resize(m);
-    for (int i = 0; i < m; ++i) w[i] = at(i, i);
+    // Q = H_0 H_1 ... H_{m-3}, accumulated from the last reflection backwards
+    for (int k = m - 3; k >= 0; --k) {
+        if (beta[k] == 0.0) continue;
+        const double *v = &vs[size_t(k) * m];
+        for (int j = k + 1; j < m; ++j) {
+            double acc = 0.0;
+            for (int i = k + 1; i < m; ++i) acc += v[i] * z(i, j);
+            acc *= beta[k];
+            for (int i = k + 1; i < m; ++i) z(i, j) -= acc * v[i];
+        }
+    }
+    // ---- implicit symmetric QR on the tridiagonal T ----
+    // rotation of rows and columns k, k+1 of T (entries within [lo, hi]) and of the
+    // columns k, k+1 of Z: row_k <- c row_k - s row_k+1, row_k+1 <- s row_k + c row_k+1
+    auto rotate = [&](int k, double c, double sn, int lo, int hi) {
+        const int a = std::max(lo, k - 1), e = std::min(hi, k + 2);
+        for (int j = a; j <= e; ++j) {
+            const double x0 = t(k, j), x1 = t(k + 1, j);
+            t(k, j) = c * x0 - sn * x1;
+            t(k + 1, j) = sn * x0 + c * x1;
+        }
+        for (int i = a; i <= e; ++i) {
+            const double x0 = t(i, k), x1 = t(i, k + 1);
+            t(i, k) = c * x0 - sn * x1;
+            t(i, k + 1) = sn * x0 + c * x1;
+        }
+        for (int i = 0; i < m; ++i) {
+            const double x0 = z(i, k), x1 = z(i, k + 1);
+            z(i, k) = c * x0 - sn * x1;
+            z(i, k + 1) = sn * x0 + c * x1;
+        }
+    };
+    constexpr double kEps = 0x1.0p-52;
+    auto small = [&](int i) { return std::fabs(t(i + 1, i)) <= kEps * (std::fabs(t(i, i)) + std::fabs(t(i + 1, i + 1))); };
+    int hi = m - 1, steps = 0;
+    while (hi > 0) {
+        if (small(hi - 1)) {
+            t(hi, hi - 1) = t(hi - 1, hi) = 0.0;
+            --hi;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0 && !small(lo - 1)) --lo;
+        if (lo > 0) t(lo, lo - 1) = t(lo - 1, lo) = 0.0;
+        if (++steps > 30 * m) throw JdError(JD_EDEVICE, "the projected eigenproblem did not converge");
+        // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block nearer its last entry
+        const double e1 = t(hi, hi - 1), dd = 0.5 * (t(hi - 1, hi - 1) - t(hi, hi));
+        const double mu = t(hi, hi) - e1 * e1 / (dd + std::copysign(std::hypot(dd, e1), dd));
+        double x = t(lo, lo) - mu, y = t(lo + 1, lo);
+        for (int k = lo; k < hi; ++k) {
+            const double r = std::hypot(x, y);
+            const double c = r == 0.0 ? 1.0 : x / r, sn = r == 0.0 ? 0.0 : -y / r;
+            rotate(k, c, sn, lo, hi);
+            if (k > lo) t(k + 1, k - 1) = t(k - 1, k + 1) = 0.0;  // the bulge moved on
+            if (k + 1 < hi) {
+                x = t(k + 1, k);
+                y = t(k + 2, k);
+            }
+        }
+    }
+    for (int i = 0; i < m; ++i) w[i] = t(i, i);
 }
 
 // In place: A (p x p column-major) is overwritten by its inverse; I is p*p workspace.
