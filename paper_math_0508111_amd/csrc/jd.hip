@@ -716,10 +716,10 @@ struct Solver {
         }
         jdmi::launch_sqmr_dot_alpha<T>(n, B.q, B.t, B.partial, B.red + 2, B.st, s);
         jdmi::launch_sqmr_update_r<T>(n, B.st, B.t, B.r, B.partial, B.red + 3, s);
-        jdmi::launch_sqmr_update_xd<T>(n, B.st, B.q, B.d, B.x, s);
         precond_projected(B.r, B.u, Qt, Y, p, dM, skip_b);
         jdmi::launch_sqmr_dot_beta<T>(n, B.r, B.u, B.partial, B.red + 4, B.st, s);
-        jdmi::launch_sqmr_update_q<T>(n, B.st, B.u, B.q, s);
+        // d, x from the q of this step, then the next q (one pass over q)
+        jdmi::launch_sqmr_update_xdq<T>(n, B.st, B.u, B.q, B.d, B.x, s);
     }
 
     template <typename F>

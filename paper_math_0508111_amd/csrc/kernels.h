@@ -19,6 +19,7 @@ struct SqmrState {
     int done;         // set before this step: every kernel of the step is skipped
     int done_next;    // set during this step: the rest of the step is skipped
     int breakdown;
+    int done_prev;    // the value of done before the beta step of the last step
 };
 
 // ---- K1 / K2 --------------------------------------------------------------------
@@ -146,10 +147,10 @@ void launch_sqmr_update_r(int n, SqmrState *st, const T *t, T *r, double *partia
 template <typename T>
 void launch_sqmr_dot_beta(int n, const T *r, const T *u, double *partial, double *rho, SqmrState *st,
                           hipStream_t s);
+// the end of a step (after the beta step): d = c1 d + c2 q, x += d if the step was live
+// before the beta step (st->done_prev == 0), then q = u + beta q if it still is
 template <typename T>
-void launch_sqmr_update_xd(int n, SqmrState *st, const T *q, T *d, T *x, hipStream_t s);
-template <typename T>
-void launch_sqmr_update_q(int n, SqmrState *st, const T *u, T *q, hipStream_t s);
+void launch_sqmr_update_xdq(int n, SqmrState *st, const T *u, T *q, T *d, T *x, hipStream_t s);
 // small dense product on the device: out = M c (p x p, double), skip if done
 void launch_small_matvec(int p, const double *M, const double *c, double *out, const int *skip, hipStream_t s);
 

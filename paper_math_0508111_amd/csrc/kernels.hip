@@ -875,6 +875,7 @@ __global__ void k_sqmr_start(SqmrState *st, const double *rr, const double *rho)
     st->breakdown = 0;
     st->done = (st->tau == 0.0 || st->rho == 0.0 || !isfinite(st->rho)) ? 1 : 0;
     st->done_next = st->done;
+    st->done_prev = st->done;
 }
 void launch_sqmr_scalar_start(SqmrState *st, const double *rr, const double *rho, hipStream_t s)
 {
@@ -923,6 +924,7 @@ __device__ inline void sqmr_beta(SqmrState *st, const double *rn_p)
             st->rho = rn;
         }
     }
+    st->done_prev = st->done;
     st->done = st->done_next;
 }
 
@@ -993,38 +995,28 @@ void launch_sqmr_update_r(int n, SqmrState *st, const T *t, T *r, double *partia
     hipLaunchKernelGGL(k_final_sum_sqmr<kOpTheta>, dim3(1), dim3(kBlock), 0, s, nb, partial, rr, &st->done, st);
 }
 
-// d = c1 d + c2 q ; x += d
+// The end of a step, in one pass over q: d = c1 d + c2 q and x += d (when the step was
+// live before the beta step), then q = u + beta q (when it is still live after it).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sqmr_update_xd(int n, const SqmrState *st, const T *__restrict__ q,
-                                                           T *__restrict__ d, T *__restrict__ x)
+__global__ void __launch_bounds__(kBlock) k_sqmr_update_xdq(int n, const SqmrState *st, const T *__restrict__ u,
+                                                            T *__restrict__ q, T *__restrict__ d, T *__restrict__ x)
 {
-    if (st->done) return;
+    const bool xd = !st->done_prev, nq = !st->done;
+    if (!xd && !nq) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const T dv = T(st->c1) * d[i] + T(st->c2) * q[i];
-    d[i] = dv;
-    x[i] += dv;
+    const T qi = q[i];
+    if (xd) {
+        const T dv = T(st->c1) * d[i] + T(st->c2) * qi;
+        d[i] = dv;
+        x[i] += dv;
+    }
+    if (nq) q[i] = u[i] + T(st->beta) * qi;
 }
 template <typename T>
-void launch_sqmr_update_xd(int n, SqmrState *st, const T *q, T *d, T *x, hipStream_t s)
+void launch_sqmr_update_xdq(int n, SqmrState *st, const T *u, T *q, T *d, T *x, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sqmr_update_xd<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, st, q, d, x);
-}
-
-// q = u + beta q (runs after the beta kernel, so it checks the committed flag)
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sqmr_update_q(int n, const SqmrState *st, const T *__restrict__ u,
-                                                          T *__restrict__ q)
-{
-    if (st->done) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    q[i] = u[i] + T(st->beta) * q[i];
-}
-template <typename T>
-void launch_sqmr_update_q(int n, SqmrState *st, const T *u, T *q, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_sqmr_update_q<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, st, u, q);
+    hipLaunchKernelGGL(k_sqmr_update_xdq<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, st, u, q, d, x);
 }
 
 __global__ void k_small_matvec(int p, const double *__restrict__ M, const double *__restrict__ c,
@@ -1071,8 +1063,7 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
                                            hipStream_t);                                                   \
     template void launch_sqmr_dot_beta<T>(int, const T *, const T *, double *, double *, SqmrState *,      \
                                           hipStream_t);                                                    \
-    template void launch_sqmr_update_xd<T>(int, SqmrState *, const T *, T *, T *, hipStream_t);           \
-    template void launch_sqmr_update_q<T>(int, SqmrState *, const T *, T *, hipStream_t);
+    template void launch_sqmr_update_xdq<T>(int, SqmrState *, const T *, T *, T *, T *, hipStream_t);
 JD_INST(float)
 JD_INST(double)
 template void launch_convert<double, float>(int, const double *, float *, double, hipStream_t);
