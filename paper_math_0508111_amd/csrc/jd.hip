@@ -710,14 +710,17 @@ struct Solver {
         const int *skip_b = &B.st->done_next;
         // t = (I - Qt Qt^T)(A - shift I) q
         jdmi::launch_stencil_state<T>(S.L, S.bc, S.eps64, B.st, B.q, B.t, s, S.hop64);
-        if (p > 0) {
-            jdmi::launch_multidot<T>(n, p, Qt, n, B.t, B.partial, B.coef, s, skip_a);
-            jdmi::launch_sub_qc<T>(n, p, Qt, n, B.coef, B.t, s, skip_a);
-        }
-        jdmi::launch_sqmr_dot_alpha<T>(n, B.q, B.t, B.partial, B.red + 2, B.st, s);
+        if (p > 0) jdmi::launch_multidot<T>(n, p, Qt, n, B.t, B.partial, B.coef, s, skip_a);
+        // t -= Qt coef and sigma = q . t in one pass
+        jdmi::launch_sqmr_sub_dot_alpha<T>(n, p, Qt, B.coef, B.t, B.q, B.partial, B.red + 2, B.st, s);
         jdmi::launch_sqmr_update_r<T>(n, B.st, B.t, B.r, B.partial, B.red + 3, s);
-        precond_projected(B.r, B.u, Qt, Y, p, dM, skip_b);
-        jdmi::launch_sqmr_dot_beta<T>(n, B.r, B.u, B.partial, B.red + 4, B.st, s);
+        // u = K^{-1} r - Y M Qt^T K^{-1} r, the last subtraction fused with rho' = r . u
+        pc.apply(B.r, B.u, s, skip_b);
+        if (p > 0) {
+            jdmi::launch_multidot<T>(n, p, Qt, n, B.u, B.partial, B.coef, s, skip_b);
+            jdmi::launch_small_matvec(p, dM, B.coef, B.g, skip_b, s);
+        }
+        jdmi::launch_sqmr_sub_dot_beta<T>(n, p, Y, B.g, B.u, B.r, B.partial, B.red + 4, B.st, s);
         // d, x from the q of this step, then the next q (one pass over q)
         jdmi::launch_sqmr_update_xdq<T>(n, B.st, B.u, B.q, B.d, B.x, s);
     }

@@ -147,6 +147,15 @@ void launch_sqmr_update_r(int n, SqmrState *st, const T *t, T *r, double *partia
 template <typename T>
 void launch_sqmr_dot_beta(int n, const T *r, const T *u, double *partial, double *rho, SqmrState *st,
                           hipStream_t s);
+// the fused forms used inside a step: t -= Qt c then sigma = q . t (and alpha), and
+// u -= Y g then rho' = r . u (and beta); same partial sums as the separate products;
+// ncols <= 128, 0 for no projection
+template <typename T>
+void launch_sqmr_sub_dot_alpha(int n, int ncols, const T *Q, const double *c, T *t, const T *q, double *partial,
+                               double *sigma, SqmrState *st, hipStream_t s);
+template <typename T>
+void launch_sqmr_sub_dot_beta(int n, int ncols, const T *Y, const double *g, T *u, const T *r, double *partial,
+                              double *rho, SqmrState *st, hipStream_t s);
 // the end of a step (after the beta step): d = c1 d + c2 q, x += d if the step was live
 // before the beta step (st->done_prev == 0), then q = u + beta q if it still is
 template <typename T>

@@ -7,6 +7,7 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <stdexcept>
 #include <cmath>
 
 namespace jdmi {
@@ -970,6 +971,54 @@ void launch_sqmr_dot_beta(int n, const T *r, const T *u, double *partial, double
     hipLaunchKernelGGL(k_final_sum_sqmr<kOpBeta>, dim3(1), dim3(kBlock), 0, s, nb, partial, rho, &st->done_next, st);
 }
 
+// y -= Q c (ncols columns, ncols may be 0) and the partial sums of w . y, in one pass:
+// the grid and the order of the products are those of k_multidot_partial with one
+// column, so the partial sums are the same as a separate dot product's
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sub_qc_dot(int n, int ncols, const T *__restrict__ Q, int64_t ldq,
+                                                       const double *__restrict__ c, T *__restrict__ y,
+                                                       const T *__restrict__ w, double *__restrict__ partial,
+                                                       const int *skip)
+{
+    if (skip && *skip) return;
+    __shared__ double cs[128];
+    __shared__ double sh[kBlock / 64];
+    for (int t = threadIdx.x; t < ncols; t += kBlock) cs[t] = c[t];
+    __syncthreads();
+    double dot = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+        double acc = 0.0;
+        for (int k = 0; k < ncols; ++k) acc += double(Q[i + int64_t(k) * ldq]) * cs[k];
+        const T v = ncols > 0 ? T(double(y[i]) - acc) : y[i];
+        if (ncols > 0) y[i] = v;
+        dot += double(w[i]) * double(v);
+    }
+    const double r = block_sum(dot, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+template <typename T>
+void launch_sqmr_sub_dot_alpha(int n, int ncols, const T *Q, const double *c, T *t, const T *q, double *partial,
+                               double *sigma, SqmrState *st, hipStream_t s)
+{
+    if (ncols > 128) throw std::invalid_argument("launch_sqmr_sub_dot_alpha: too many columns");
+    const int nb = red_blocks(n);
+    hipLaunchKernelGGL(k_sub_qc_dot<T>, dim3(nb), dim3(kBlock), 0, s, n, ncols, Q, int64_t(n), c, t, q, partial,
+                       &st->done);
+    hipLaunchKernelGGL(k_final_sum_sqmr<kOpAlpha>, dim3(1), dim3(kBlock), 0, s, nb, partial, sigma, &st->done, st);
+}
+
+template <typename T>
+void launch_sqmr_sub_dot_beta(int n, int ncols, const T *Y, const double *g, T *u, const T *r, double *partial,
+                              double *rho, SqmrState *st, hipStream_t s)
+{
+    if (ncols > 128) throw std::invalid_argument("launch_sqmr_sub_dot_beta: too many columns");
+    const int nb = red_blocks(n);
+    hipLaunchKernelGGL(k_sub_qc_dot<T>, dim3(nb), dim3(kBlock), 0, s, n, ncols, Y, int64_t(n), g, u, r, partial,
+                       &st->done_next);
+    hipLaunchKernelGGL(k_final_sum_sqmr<kOpBeta>, dim3(1), dim3(kBlock), 0, s, nb, partial, rho, &st->done_next, st);
+}
+
 // r -= alpha t, with the partial sums of |r|^2
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_sqmr_update_r(int n, const SqmrState *st, const T *__restrict__ t,
@@ -1063,7 +1112,11 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
                                            hipStream_t);                                                   \
     template void launch_sqmr_dot_beta<T>(int, const T *, const T *, double *, double *, SqmrState *,      \
                                           hipStream_t);                                                    \
-    template void launch_sqmr_update_xdq<T>(int, SqmrState *, const T *, T *, T *, T *, hipStream_t);
+    template void launch_sqmr_update_xdq<T>(int, SqmrState *, const T *, T *, T *, T *, hipStream_t);      \
+    template void launch_sqmr_sub_dot_alpha<T>(int, int, const T *, const double *, T *, const T *,        \
+                                               double *, double *, SqmrState *, hipStream_t);              \
+    template void launch_sqmr_sub_dot_beta<T>(int, int, const T *, const double *, T *, const T *,         \
+                                              double *, double *, SqmrState *, hipStream_t);
 JD_INST(float)
 JD_INST(double)
 template void launch_convert<double, float>(int, const double *, float *, double, hipStream_t);

@@ -177,3 +177,24 @@ def test_stated_drop_tolerance_at_L50():
         r = np.linalg.norm(lattice.matvec(L, eps, evecs[:, c]) - evals[c] * evecs[:, c])
         assert r <= 1e-10 * g["anorm"] * 1.0001
     assert np.abs(evecs.T @ evecs - np.eye(k)).max() <= 1e-8
+
+
+def test_large_single_solve_pairs_checked_by_the_oracle_product():
+    # L = 150 (n = 3 375 000), W = 16.5, k = 10 nearest 0, binary32 preconditioner and
+    # inner solves.  The oracle has no eigenvalues at this size (its exact LDL^T would
+    # need dense fronts of tens of GB); what holds at any size is checked with its own
+    # product instead: every returned pair is an eigenpair to 1e-10 ||A||_inf, the
+    # vectors are orthonormal, and the values are ordered by distance to sigma.
+    L, W, seed, sigma, k = 150, 16.5, 0, 0.0, 10
+    evals, evecs, resid, info = jd.solve(L, W, seed, sigma, k, 1e-10, vectors=True, precision="mixed")
+    assert info["status"] == 0 and info["n_converged"] == k
+    eps = generator.disorder(L, W, seed)
+    anorm = lattice.inf_norm(eps)
+    for c in range(k):
+        x = evecs[:, c]
+        r = np.linalg.norm(lattice.matvec(L, eps, x) - evals[c] * x)
+        assert r <= 1e-10 * anorm * 1.0001, (c, r / anorm)
+        assert abs(resid[c] - r / anorm) <= 1e-3 * max(r / anorm, 1e-16) + 1e-15  # reported = true
+    assert np.abs(evecs.T @ evecs - np.eye(k)).max() <= 1e-8
+    d = np.abs(evals - sigma)
+    assert np.all(np.diff(d) >= 0)
