@@ -252,8 +252,7 @@ struct DevPrecond {
             T *r1 = buf + size_t(n), *r2 = buf + 2 * size_t(n);
             jdmi::launch_gather<T>(n, site_of, in, r2, s, skip);
             for (const auto &z : zdown) jdmi::launch_hyb_spmv<T, T>(z, buf, buf, s, skip);
-            jdmi::launch_dinv<T>(n, dd, dof, dp, buf, r1, s, skip);
-            jdmi::launch_coarse_idx<T>(coarse_n, cld, cidx, cinv, buf, yc, r1, s, skip);
+            jdmi::launch_dinv_coarse<T>(n, dd, dof, dp, coarse_n, cld, cidx, cinv, buf, yc, r1, s, skip);
             for (int i = int(zup.size()) - 1; i >= 1; --i) jdmi::launch_hyb_spmv<T, T>(zup[i], buf, buf, s, skip);
             jdmi::launch_hyb_spmv<T, T>(zup[0], buf, out, s, skip);  // rows are the output sites
             return;
@@ -280,8 +279,8 @@ struct MixedPrecond {
         double *buf = pd.buf, *r1 = buf + size_t(n), *r2 = buf + 2 * size_t(n);
         jdmi::launch_gather<double>(n, pd.site_of, in, r2, s, skip);
         for (const auto &z : pc.zdown) jdmi::launch_hyb_spmv<float, double>(z, buf, buf, s, skip);
-        jdmi::launch_dinv<double>(n, pd.dd, pd.dof, pd.dp, buf, r1, s, skip);
-        jdmi::launch_coarse_idx<double>(pd.coarse_n, pd.cld, pd.cidx, pd.cinv, buf, pd.yc, r1, s, skip);
+        jdmi::launch_dinv_coarse<double>(n, pd.dd, pd.dof, pd.dp, pd.coarse_n, pd.cld, pd.cidx, pd.cinv, buf, pd.yc,
+                                         r1, s, skip);
         for (int i = int(pc.zup.size()) - 1; i >= 1; --i)
             jdmi::launch_hyb_spmv<float, double>(pc.zup[i], buf, buf, s, skip);
         jdmi::launch_hyb_spmv<float, double>(pc.zup[0], buf, out, s, skip);

@@ -84,6 +84,11 @@ struct Hyb {
 template <typename Tv, typename Tx>
 void launch_hyb_spmv(const Hyb<Tv> &A, const Tx *x, Tx *y, hipStream_t s, const int *skip);
 
+// z[j] = dd[j] y[j] + dof[j] y[dp[j]] for j < m, then the last level (as
+// launch_coarse_idx) with the gather of its unknowns fused into the first launch
+template <typename T>
+void launch_dinv_coarse(int m, const T *dd, const T *dof, const int *dp, int nc, int ld, const int *idx,
+                        const T *cinv, const T *y, T *yc, T *z, hipStream_t s, const int *skip);
 // z[j] = dd[j] y[j] + dof[j] y[dp[j]] for j < m
 template <typename T>
 void launch_dinv(int m, const T *dd, const T *dof, const int *dp, const T *y, T *z, hipStream_t s, const int *skip);

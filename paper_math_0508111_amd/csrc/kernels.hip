@@ -368,6 +368,37 @@ __global__ void __launch_bounds__(kBlock) k_coarse_rows(int nc, int ld, const in
     if (lane == 0) z[idx[row]] = T(acc);
 }
 
+// The block-diagonal step z = D^{-1} y (blocks [0, nbd)) and the gather of the last
+// level's unknowns yc = y[idx] (the other blocks) in one launch: both read y only
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dinv_gather(int m, const T *__restrict__ dd, const T *__restrict__ dof,
+                                                        const int *__restrict__ dp, const T *__restrict__ y,
+                                                        T *__restrict__ z, int nc, const int *__restrict__ idx,
+                                                        T *__restrict__ yc, int nbd, const int *skip)
+{
+    if (skip && *skip) return;
+    if (int(blockIdx.x) < nbd) {
+        const int j = blockIdx.x * kBlock + threadIdx.x;
+        if (j < m) z[j] = dd[j] * y[j] + dof[j] * y[dp[j]];
+    } else {
+        const int p = (blockIdx.x - nbd) * kBlock + threadIdx.x;
+        if (p < nc) yc[p] = y[idx[p]];
+    }
+}
+
+template <typename T>
+void launch_dinv_coarse(int m, const T *dd, const T *dof, const int *dp, int nc, int ld, const int *idx,
+                        const T *cinv, const T *y, T *yc, T *z, hipStream_t s, const int *skip)
+{
+    const int nbd = m > 0 ? nblocks(m) : 0, nbg = nc > 0 ? nblocks(nc) : 0;
+    if (nbd + nbg == 0) return;
+    hipLaunchKernelGGL(k_dinv_gather<T>, dim3(nbd + nbg), dim3(kBlock), 0, s, m, dd, dof, dp, y, z, nc, idx, yc, nbd,
+                       skip);
+    if (nc > 0)
+        hipLaunchKernelGGL(k_coarse_rows<T>, dim3(nblocks(nc, kBlock / 64)), dim3(kBlock), 0, s, nc, ld, idx, cinv,
+                           yc, z, skip);
+}
+
 template <typename T>
 void launch_coarse_idx(int nc, int ld, const int *idx, const T *cinv, const T *y, T *yc, T *z, hipStream_t s,
                        const int *skip)
@@ -1100,6 +1131,8 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
                                        const int *);                                                       \
     template void launch_dinv<T>(int, const T *, const T *, const int *, const T *, T *, hipStream_t,      \
                                  const int *);                                                             \
+    template void launch_dinv_coarse<T>(int, const T *, const T *, const int *, int, int, const int *,      \
+                                        const T *, const T *, T *, T *, hipStream_t, const int *);          \
     template void launch_multidot<T>(int, int, const T *, int64_t, const T *, double *, double *,          \
                                      hipStream_t, const int *);                                            \
     template void launch_dot<T>(int, const T *, const T *, double *, double *, hipStream_t, const int *);  \
