@@ -108,6 +108,34 @@ def stencil_bandwidth(jd, torch, L, W, seed, reps=50):
             "achieved_GBs": round(b / (us * 1e-6) / 1e9, 1)}
 
 
+def block_products(jd, torch, n, reps=10):
+    """The Rayleigh-Ritz block products V S on the FP64 matrix cores at the benchmark's
+    sizes: the restart (60 -> 20 columns) and a deflation (60 -> 59).  Bytes: V read
+    once and the output written (8 n (m + mout)); flops 2 n m mout; HIP events."""
+    s = torch.cuda.current_stream()
+    out = []
+    for m, mout in ((60, 20), (60, 59)):
+        V = torch.randn(m, n, dtype=torch.float64, device="cuda").t()
+        S = torch.randn(mout, m, dtype=torch.float64, device="cuda").t()
+        O = torch.empty(mout, n, dtype=torch.float64, device="cuda").t()
+        jd.block_product(V, S, O, stream=s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            jd.block_product(V, S, O, stream=s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        b, f = 8 * n * (m + mout), 2 * n * m * mout
+        out.append({"kernel": "k_gemm_vs", "m": m, "mout": mout, "avg_us": round(us, 1),
+                    "GBs": round(b / (us * 1e-6) / 1e9, 1), "TFLOPs": round(f / (us * 1e-6) / 1e12, 2),
+                    "hbm_frac": round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 3),
+                    "mfma_frac": round(f / (us * 1e-6) / 1e12 / 78.6, 3)})
+        del V, S, O
+    return out
+
+
 def product_bytes(pc, n, sv=4, sx=4):
     """Algorithmic bytes of the 2 S segment products of one apply (the CSR definition of
     each product, not the layout: entries (value + 4-byte index), row pointers (8 bytes),
@@ -197,7 +225,8 @@ def apply_roofline(torch, prob, n, reps=20):
     nnz_g = sum(lv["nnzG"])
     method = 2 * nnz_g * 8 + 2 * sum(lv["sizes"][:-1]) * 4 + 2 * n * 4 + nc * nc * 4 + 2 * n * 4 + 2 * n * 4
     pc.close()
-    return {"avg_us": round(us, 1), "launches": launches + 4, "bytes": int(impl),
+    # + the input gather, D^-1 with the last level's gather, and the last level's product
+    return {"avg_us": round(us, 1), "launches": launches + 3, "bytes": int(impl),
             "achieved_GBs": round(impl / (us * 1e-6) / 1e9, 1), "frac": round(impl / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
             "method_bytes": int(method), "nnz_G": int(nnz_g),
             "method_GBs": round(method / (us * 1e-6) / 1e9, 1),
@@ -503,6 +532,7 @@ def main():
     out["roofline"] = factor_roofline(torch, prob, L ** 3)
     out["apply"] = apply_roofline(torch, prob, L ** 3)
     out["stencil"] = stencil_bandwidth(jd, torch, L, W, seed)
+    out["block_products"] = block_products(jd, torch, L ** 3)
     prob.close()
     if a.seeds:
         # seed-to-seed spread of the same workload (other disorder realisations)
