@@ -110,8 +110,11 @@ enum { JD_MODEL_ANDERSON = 0, JD_MODEL_OFFDIAG = 1 };
  *  bc         JD_BC_PERIODIC (0) or JD_BC_HARDWALL.  ||A||_inf is the largest row sum
  *             of |entries| (6 + max|eps| for the diagonal model on the torus).
  *  model      JD_MODEL_ANDERSON (0) or JD_MODEL_OFFDIAG.
- *  inner_tol_min  floor of the relative tolerance 2^(-j) of the j-th correction
+ *  inner_tol_min  floor of the relative tolerance rate^j of the j-th correction
  *             equation solved for the current pair (0 -> 1e-10); a solve-time option.
+ *  inner_tol_rate the rate of that tolerance, in (0, 1) (0 -> 0.5 for JD_MIXED, whose
+ *             binary32 vectors cannot resolve tighter inner solves, 0.25 for the splits
+ *             with binary64 vectors); a solve-time option.
  *  stream     stream for the solve's device work (NULL: a library-created blocking stream).
  */
 typedef struct jd_options {
@@ -131,6 +134,7 @@ typedef struct jd_options {
     int bc;
     int model;
     double inner_tol_min;
+    double inner_tol_rate;
     void *stream;
 } jd_options;
 
@@ -198,7 +202,7 @@ int jd_problem_lanczos(jd_problem *p, int k, double tol, double inner_tol, doubl
  * is needed. */
 int jd_problem_set_precision(jd_problem *p, int precision);
 /* Replace the solve-time options of later jd_problem_solve calls: jmin, jmax,
- * max_outer, max_inner, switch_tol, inner_tol_min and the JD_FLAG_GRAPHS bit of flags are taken from
+ * max_outer, max_inner, switch_tol, inner_tol_min, inner_tol_rate and the JD_FLAG_GRAPHS bit of flags are taken from
  * *opt (0 -> the default, as in jd_setup); every setup option of *opt is ignored.
  * JD_EINVAL for out-of-range values, and the problem keeps its previous options. */
 int jd_problem_set_solve_options(jd_problem *p, const jd_options *opt);

@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
                 ("max_levels", ctypes.c_int), ("z_drop", ctypes.c_double), ("jmin", ctypes.c_int), ("jmax", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int), ("switch_tol", ctypes.c_double),
                 ("flags", ctypes.c_int), ("z_parts", ctypes.c_int), ("bc", ctypes.c_int),
-                ("model", ctypes.c_int), ("inner_tol_min", ctypes.c_double), ("stream", ctypes.c_void_p)]
+                ("model", ctypes.c_int), ("inner_tol_min", ctypes.c_double), ("inner_tol_rate", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
 
 
 class Request(ctypes.Structure):
@@ -216,7 +217,8 @@ class Problem:
         _check(lib().jd_problem_set_precision(self._h, _PREC[precision]))
 
     def set_solve_options(self, **opts):
-        """jd_problem_set_solve_options: jmin, jmax, max_outer, max_inner, switch_tol, flags."""
+        """jd_problem_set_solve_options: jmin, jmax, max_outer, max_inner, switch_tol, inner_tol_min,
+        inner_tol_rate, flags."""
         o = make_options(**opts)
         _check(lib().jd_problem_set_solve_options(self._h, ctypes.byref(o)))
 

@@ -85,6 +85,20 @@ def test_search_space_sizes_rejected(jd, jmin, jmax):
     assert rc == jd.JD_EINVAL and not h.value
 
 
+@pytest.mark.parametrize("field,value", [("inner_tol_rate", 1.0), ("inner_tol_rate", -0.5),
+                                         ("inner_tol_min", 1.5)])
+def test_inner_tolerance_options_rejected(jd, field, value):
+    """The correction equations' tolerance rate^j (rate in (0, 1)) and its floor are
+    checked before any device call."""
+    lib = jd.lib()
+    ev = np.zeros(4)
+    p = ev.ctypes.data_as(ctypes.c_void_p)
+    o = jd.make_options(precision="fp64", **{field: value})
+    rc = lib.jd_solve(10, 16.5, 0, 0.0, 4, 1e-10, p, None, None, ctypes.byref(o), None)
+    assert rc == jd.JD_EINVAL
+    assert field in lib.jd_last_error().decode()
+
+
 def test_set_allocator_arguments(jd):
     lib = jd.lib()
     fa = jd.ALLOC_FN(lambda n, s, c: None)
