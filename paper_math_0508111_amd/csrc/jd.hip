@@ -926,7 +926,11 @@ int jd_run(Setup &S, const P &pc, int k, double tol, Outputs out, jd_info *info)
     if (o.jmax > 0) jmax = o.jmax;
     // a restart keeps jmin of the jmax columns: a jmin given alone raises the default jmax
     jmax = std::max(jmax, jmin + 1);
-    const int max_inner = o.max_inner > 0 ? o.max_inner : (hard ? 80 : 40);
+    // SQMR steps per correction equation: binary32 vectors converge more slowly per step
+    // (measured at L = 100 over five seeds: 50 against 40 steps, 6.8% less solve time;
+    // with binary64 vectors 60 against 40 costs 7%)
+    const int max_inner =
+        o.max_inner > 0 ? o.max_inner : (hard ? 80 : (std::is_same<T, float>::value ? 50 : 40));
     // the correction operator's shift moves from sigma to theta once ||r|| < switch_tol
     // ||A|| (also for binary32 inner vectors: their operator is the binary64 one, so
     // A - theta I is not perturbed by the rounding of eps)

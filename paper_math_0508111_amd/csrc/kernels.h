@@ -50,12 +50,8 @@ void launch_up(const DevLevel<T> &lv, const T *w, T *x, hipStream_t s, const int
 // last level (dense inverse Cinv, row i at cinv + i * ld): x[off + i] = sum_j Cinv[i, j] w[off + j]
 template <typename T>
 void launch_coarse(int nc, int ld, int off, const T *cinv, const T *w, T *x, hipStream_t s, const int *skip);
-// last level with scattered unknowns: yc[i] = y[idx[i]], then z[idx[i]] = sum_j Cinv[i, j] yc[j];
-// ld is a multiple of 64, and Cinv's row padding and yc[nc .. ld) hold zeros
+// rows of the last level are padded to a multiple of kCoarseAlign (padding holds zeros)
 constexpr int kCoarseAlign = 64;
-template <typename T>
-void launch_coarse_idx(int nc, int ld, const int *idx, const T *cinv, const T *y, T *yc, T *z, hipStream_t s,
-                       const int *skip);
 
 // Product with the explicit inverse factor (y = Z w, or Z^T w) in the hybrid layout of
 // jdmi::HybHost; workgroup b works on part b % kHybParts, so that on an 8-XCD device a
@@ -84,14 +80,13 @@ struct Hyb {
 template <typename Tv, typename Tx>
 void launch_hyb_spmv(const Hyb<Tv> &A, const Tx *x, Tx *y, hipStream_t s, const int *skip);
 
-// z[j] = dd[j] y[j] + dof[j] y[dp[j]] for j < m, then the last level (as
-// launch_coarse_idx) with the gather of its unknowns fused into the first launch
+// The block-diagonal step z[j] = dd[j] y[j] + dof[j] y[dp[j]] (j < m), then the last
+// level with scattered unknowns, z[idx[i]] = sum_j Cinv[i, j] y[idx[j]]: the gather
+// yc[i] = y[idx[i]] shares the first launch with the block-diagonal step (both only read
+// y); ld is a multiple of kCoarseAlign, and Cinv's row padding and yc[nc .. ld) hold zeros
 template <typename T>
 void launch_dinv_coarse(int m, const T *dd, const T *dof, const int *dp, int nc, int ld, const int *idx,
                         const T *cinv, const T *y, T *yc, T *z, hipStream_t s, const int *skip);
-// z[j] = dd[j] y[j] + dof[j] y[dp[j]] for j < m
-template <typename T>
-void launch_dinv(int m, const T *dd, const T *dof, const int *dp, const T *y, T *z, hipStream_t s, const int *skip);
 
 // ---- reductions (deterministic two-stage; results stay on the device) ---------------
 // partial[c * kRedBlocks + b] for c < ncols; out[c] = sum
@@ -138,23 +133,15 @@ void launch_stencil_state(int L, int bc, const double *eps, const SqmrState *st,
                           const double *hop = nullptr);
 template <typename T>
 void launch_copy(int n, const T *x, T *y, hipStream_t s);
-// sigma = q.t (stored in *sigma) and, in the same final reduction, alpha = rho / sigma
-// (skipped when st->done; a zero or non-finite sigma is a breakdown that stops the solve)
-template <typename T>
-void launch_sqmr_dot_alpha(int n, const T *q, const T *t, double *partial, double *sigma, SqmrState *st,
-                           hipStream_t s);
 // r -= alpha t; |r|^2 (stored in *rr) and, in the same final reduction, the theta / c / tau
 // update and the stopping test (skipped when st->done)
 template <typename T>
 void launch_sqmr_update_r(int n, SqmrState *st, const T *t, T *r, double *partial, double *rr, hipStream_t s);
-// rho' = r.u (stored in *rho, skipped when st->done_next) and, in the same final reduction,
-// beta = rho' / rho; then st->done takes the value of st->done_next
-template <typename T>
-void launch_sqmr_dot_beta(int n, const T *r, const T *u, double *partial, double *rho, SqmrState *st,
-                          hipStream_t s);
-// the fused forms used inside a step: t -= Qt c then sigma = q . t (and alpha), and
-// u -= Y g then rho' = r . u (and beta); same partial sums as the separate products;
-// ncols <= 128, 0 for no projection
+// t -= Qt c, then sigma = q.t (stored in *sigma) and, in the same final reduction,
+// alpha = rho / sigma (skipped when st->done; a zero or non-finite sigma is a breakdown
+// that stops the solve).  u -= Y g, then rho' = r.u (stored in *rho, skipped when
+// st->done_next) and, in the same final reduction, beta = rho' / rho; then st->done
+// takes the value of st->done_next.  ncols <= 128, 0 for no projection.
 template <typename T>
 void launch_sqmr_sub_dot_alpha(int n, int ncols, const T *Q, const double *c, T *t, const T *q, double *partial,
                                double *sigma, SqmrState *st, hipStream_t s);

@@ -400,16 +400,6 @@ void launch_dinv_coarse(int m, const T *dd, const T *dof, const int *dp, int nc,
 }
 
 template <typename T>
-void launch_coarse_idx(int nc, int ld, const int *idx, const T *cinv, const T *y, T *yc, T *z, hipStream_t s,
-                       const int *skip)
-{
-    if (nc <= 0) return;
-    hipLaunchKernelGGL(k_gather<T>, dim3(nblocks(nc)), dim3(kBlock), 0, s, nc, idx, y, yc, skip);
-    hipLaunchKernelGGL(k_coarse_rows<T>, dim3(nblocks(nc, kBlock / 64)), dim3(kBlock), 0, s, nc, ld, idx, cinv, yc,
-                       z, skip);
-}
-
-template <typename T>
 void launch_gather(int n, const int *perm, const T *b, T *w, hipStream_t s, const int *skip)
 {
     hipLaunchKernelGGL(k_gather<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, n, perm, b, w, skip);
@@ -525,23 +515,6 @@ template void launch_hyb_spmv<double, double>(const Hyb<double> &, const double 
 template void launch_hyb_spmv<float, double>(const Hyb<float> &, const double *, double *, hipStream_t,
                                              const int *);
 
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_dinv(int m, const T *__restrict__ dd, const T *__restrict__ dof,
-                                                 const int *__restrict__ dp, const T *__restrict__ y,
-                                                 T *__restrict__ z, const int *skip)
-{
-    if (skip && *skip) return;
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j < m) z[j] = dd[j] * y[j] + dof[j] * y[dp[j]];
-}
-
-template <typename T>
-void launch_dinv(int m, const T *dd, const T *dof, const int *dp, const T *y, T *z, hipStream_t s, const int *skip)
-{
-    if (m <= 0) return;
-    hipLaunchKernelGGL(k_dinv<T>, dim3(nblocks(m)), dim3(kBlock), 0, s, m, dd, dof, dp, y, z, skip);
-}
 
 // ---------------------------------------------------------------------------------
 // Reductions.
@@ -982,26 +955,6 @@ __global__ void __launch_bounds__(kBlock) k_final_sum_sqmr(int nparts, const dou
     else sqmr_beta(st, out);
 }
 
-template <typename T>
-void launch_sqmr_dot_alpha(int n, const T *q, const T *t, double *partial, double *sigma, SqmrState *st,
-                           hipStream_t s)
-{
-    const int nb = red_blocks(n);
-    hipLaunchKernelGGL(k_multidot_partial<T>, dim3(nb, 1), dim3(kBlock), 0, s, n, 1, q, int64_t(n), t, partial,
-                       kRedBlocks, &st->done);
-    hipLaunchKernelGGL(k_final_sum_sqmr<kOpAlpha>, dim3(1), dim3(kBlock), 0, s, nb, partial, sigma, &st->done, st);
-}
-
-template <typename T>
-void launch_sqmr_dot_beta(int n, const T *r, const T *u, double *partial, double *rho, SqmrState *st,
-                          hipStream_t s)
-{
-    const int nb = red_blocks(n);
-    hipLaunchKernelGGL(k_multidot_partial<T>, dim3(nb, 1), dim3(kBlock), 0, s, n, 1, r, int64_t(n), u, partial,
-                       kRedBlocks, &st->done_next);
-    hipLaunchKernelGGL(k_final_sum_sqmr<kOpBeta>, dim3(1), dim3(kBlock), 0, s, nb, partial, rho, &st->done_next, st);
-}
-
 // y -= Q c (ncols columns, ncols may be 0) and the partial sums of w . y, in one pass:
 // the grid and the order of the products are those of k_multidot_partial with one
 // column, so the partial sums are the same as a separate dot product's
@@ -1127,10 +1080,6 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
     template void launch_down<T>(const DevLevel<T> &, T *, hipStream_t, const int *);                      \
     template void launch_up<T>(const DevLevel<T> &, const T *, T *, hipStream_t, const int *);             \
     template void launch_coarse<T>(int, int, int, const T *, const T *, T *, hipStream_t, const int *);    \
-    template void launch_coarse_idx<T>(int, int, const int *, const T *, const T *, T *, T *, hipStream_t, \
-                                       const int *);                                                       \
-    template void launch_dinv<T>(int, const T *, const T *, const int *, const T *, T *, hipStream_t,      \
-                                 const int *);                                                             \
     template void launch_dinv_coarse<T>(int, const T *, const T *, const int *, int, int, const int *,      \
                                         const T *, const T *, T *, T *, hipStream_t, const int *);          \
     template void launch_multidot<T>(int, int, const T *, int64_t, const T *, double *, double *,          \
@@ -1140,10 +1089,6 @@ void launch_small_matvec(int p, const double *M, const double *c, double *out, c
                                    const int *, double);                                                   \
     template void launch_sqmr_init<T>(int, const T *, T *, T *, T *, hipStream_t);                        \
     template void launch_sqmr_update_r<T>(int, SqmrState *, const T *, T *, double *, double *,           \
-                                          hipStream_t);                                                    \
-    template void launch_sqmr_dot_alpha<T>(int, const T *, const T *, double *, double *, SqmrState *,     \
-                                           hipStream_t);                                                   \
-    template void launch_sqmr_dot_beta<T>(int, const T *, const T *, double *, double *, SqmrState *,      \
                                           hipStream_t);                                                    \
     template void launch_sqmr_update_xdq<T>(int, SqmrState *, const T *, T *, T *, T *, hipStream_t);      \
     template void launch_sqmr_sub_dot_alpha<T>(int, int, const T *, const double *, T *, const T *,        \
