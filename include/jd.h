@@ -98,8 +98,8 @@ enum { JD_MODEL_ANDERSON = 0, JD_MODEL_OFFDIAG = 1 };
  *             jmin < jmax when both are given (JD_EINVAL otherwise); a jmin given
  *             alone raises the default jmax to at least jmin + 1.
  *  max_outer  outer Jacobi-Davidson iterations (0 -> 60 k + 200).
- *  max_inner  SQMR steps per correction equation (0 -> 40 with binary64 vectors, 50
- *             with binary32 ones, or 80 after a setup that stalled).
+ *  max_inner  SQMR steps per correction equation (0 -> 50 with binary32 vectors; with
+ *             binary64 ones 40, or 80 after a setup that stalled).
  *  switch_tol the correction operator uses sigma until ||r|| < switch_tol ||A||_inf,
  *             then the Ritz value theta; < 0: always sigma (0 -> 1e-3).
  *  flags      bit 0 (JD_FLAG_GRAPHS): replay the inner iteration as a captured HIP graph

@@ -928,9 +928,11 @@ int jd_run(Setup &S, const P &pc, int k, double tol, Outputs out, jd_info *info)
     jmax = std::max(jmax, jmin + 1);
     // SQMR steps per correction equation: binary32 vectors converge more slowly per step
     // (measured at L = 100 over five seeds: 50 against 40 steps, 6.8% less solve time;
-    // with binary64 vectors 60 against 40 costs 7%)
+    // with binary64 vectors 60 against 40 costs 7%).  After a stalled setup binary64
+    // vectors take 80; binary32 ones keep 50 (L = 150: 12.2 s against 15.5 s with 80;
+    // the 20 W = 12, L >= 50 requests of the serving mix: all converge, 3% faster)
     const int max_inner =
-        o.max_inner > 0 ? o.max_inner : (hard ? 80 : (std::is_same<T, float>::value ? 50 : 40));
+        o.max_inner > 0 ? o.max_inner : (std::is_same<T, float>::value ? 50 : (hard ? 80 : 40));
     // the correction operator's shift moves from sigma to theta once ||r|| < switch_tol
     // ||A|| (also for binary32 inner vectors: their operator is the binary64 one, so
     // A - theta I is not perturbed by the rounding of eps)
