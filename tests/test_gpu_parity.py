@@ -292,6 +292,24 @@ def test_solve_options_setter():
     p.close()
 
 
+def test_inner_tolerance_rate_option():
+    # the j-th correction equation of a pair is solved to rate^j: rates other than the
+    # default change the iteration path, and every path converges to the oracle's values
+    ref = np.sort(eig.anderson_nearest(12, 16.5, 5, 0.0, 4)[0])
+    p = jd.Problem(12, 16.5, 5, 0.0, precision="mixed")
+    paths = []
+    for rate in (0.0, 0.1, 0.8):  # 0: the default
+        p.set_solve_options(inner_tol_rate=rate)
+        e, _, _, info = p.solve(4, 1e-10)
+        assert info["status"] == 0 and np.max(np.abs(np.sort(e) - ref)) <= 1e-9, rate
+        paths.append((info["outer_its"], info["inner_its"]))
+    p.close()
+    assert len(set(paths)) > 1, paths
+    # the same option through jd_solve's options
+    e, _, _, info = jd.solve(12, 16.5, 5, 0.0, 4, 1e-10, precision="fp64", inner_tol_rate=0.1)
+    assert info["status"] == 0 and np.max(np.abs(np.sort(e) - ref)) <= 1e-9
+
+
 def test_search_space_set_at_setup_with_jmin_alone():
     # the same rule through jd_solve's options (L = 10, k = 5: default jmax 20)
     ref = eig.anderson_nearest(10, 16.5, 0, 0.0, 5)[0]
