@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-warmup", type=int, default=8,
                     help="closed-loop requests that measure the saturated rate before the Poisson stream")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="Poisson arrival rate in req/s (0: 0.8 of the warm-up's saturated rate)")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the serving stream (for long streams such as the 256-request mix)")
     ap.add_argument("--sweep", action="store_true",
@@ -312,10 +314,11 @@ def lanczos_leg(jd, L, k, tol=1e-10, W=16.5, seed=0, sigma=0.0):
     return out
 
 
-def serving(jd, nreq, workers, warm=8):
-    """Continuous batching of the mixed request stream: a closed-loop warm-up measures
-    the saturated request rate, then nreq requests arrive as a Poisson process at 0.8
-    of that rate; latency = submission -> completion (measured by the server)."""
+def serving(jd, nreq, workers, warm=8, rate=None):
+    """The server on the mixed request stream: a closed-loop warm-up measures the
+    saturated request rate, then nreq requests arrive as a Poisson process at 0.8 of
+    that rate (or at `rate` req/s when given); latency = submission -> completion
+    (measured by the server)."""
     import numpy as np
     from tests import seeded_inputs
     reqs = seeded_inputs.serving_requests(warm + nreq)
@@ -344,9 +347,9 @@ def serving(jd, nreq, workers, warm=8):
         return res, time.time() - t0
 
     _, span = run(reqs[:warm], None, "warm-up")
-    rate = warm / span
-    lam = 0.8 * rate
-    print(f"# serving: saturated {rate:.2f} req/s, Poisson arrivals at {lam:.2f} req/s", file=sys.stderr, flush=True)
+    sat = warm / span
+    lam = rate if rate else 0.8 * sat
+    print(f"# serving: saturated {sat:.2f} req/s, Poisson arrivals at {lam:.2f} req/s", file=sys.stderr, flush=True)
     res, span = run(reqs[warm:], seeded_inputs.poisson_arrivals(nreq, lam), "poisson")
     srv.close()
     for r, q in zip(res, reqs[warm:]):
@@ -356,7 +359,8 @@ def serving(jd, nreq, workers, warm=8):
     lat = np.array([r["latency_s"] for r in res])
     ok = sum(r["status"] == 0 for r in res)
     pairs = sum(r["n_converged"] for r in res)
-    return {"requests": nreq, "workers": workers, "saturated_rps": round(rate, 3), "arrival_rps": round(lam, 3),
+    return {"requests": nreq, "workers": workers, "setup_threads": "adaptive",
+            "saturated_rps": round(sat, 3), "arrival_rps": round(lam, 3),
             "completed_ok": int(ok), "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
             "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
             "p50_setup_s": round(float(np.percentile([r["setup_s"] for r in res], 50)), 3),
@@ -457,7 +461,7 @@ def main():
         print(json.dumps({"lanczos": lanczos_leg(jd, a.L, a.k)}), flush=True)
         return
     if a.serve_only:
-        print(json.dumps({"serving": serving(jd, a.serve_requests, a.serve_workers, a.serve_warmup)}), flush=True)
+        print(json.dumps({"serving": serving(jd, a.serve_requests, a.serve_workers, a.serve_warmup, a.serve_rate)}), flush=True)
         return
     L, W, seed, sigma, k, tol = a.L, 16.5, 0, 0.0, a.k, 1e-10
     t0 = time.time()
@@ -548,7 +552,7 @@ def main():
             print(f"# seed {sd}: setup {i2['setup_s']:.1f} s, solve {i2['solve_s']:.3f} s, outer {i2['outer_its']}, "
                   f"inner {i2['inner_its']}, converged {i2['n_converged']}", file=sys.stderr, flush=True)
     if a.serve_requests > 0:
-        out["serving"] = serving(jd, a.serve_requests, a.serve_workers, a.serve_warmup)
+        out["serving"] = serving(jd, a.serve_requests, a.serve_workers, a.serve_warmup, a.serve_rate)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(k, L)
     print(json.dumps(out), flush=True)

@@ -318,7 +318,7 @@ int jd_problem_linear_solve_noalloc(jd_problem *p, double shift, const double *d
                                     const double *d_b, double *d_x, double rtol, int maxit, int *its);
 
 /*
- * Serving: continuous batching of independent solve requests (the disorder averaging
+ * Serving: independent solve requests run concurrently (the disorder averaging
  * of section 3 needs many realisations).  A request is admitted when a worker is free
  * and its estimated device footprint fits the HBM budget; admitted requests run their
  * host setup and their device solve concurrently, each on its own stream, so work of
@@ -357,9 +357,16 @@ typedef struct jd_server jd_server;
 
 /* hbm_budget_bytes: device memory the server may reserve (0 -> 80% of free memory);
  * workers: concurrently active requests (0 -> 8); setup_threads: host threads of one
- * setup (0 -> half the OpenMP thread budget, OMP_NUM_THREADS).  Host setups are a
- * resource of their own: at most max(1, budget / setup_threads) run at once (the
- * others wait, their time counts in setup_s), while admitted solves all run. */
+ * setup.  Host setups are a resource of their own, drawn from the OpenMP thread budget
+ * (OMP_NUM_THREADS); a setup waiting for threads counts its wait in setup_s, while
+ * admitted solves all run.
+ *   setup_threads > 0: every setup uses that many, and at most
+ *     max(1, budget / setup_threads) run at once.
+ *   setup_threads 0 (adaptive): a setup starts when a thread is free and takes
+ *     budget / max(2, setups running or waiting) threads (at least 1, at most the free
+ *     ones): two setups share the budget at light load, and a backlog runs more,
+ *     narrower setups, which clear it faster.
+ * Results do not depend on the split: the factors are identical for any thread count. */
 int jd_server_create(size_t hbm_budget_bytes, int workers, int setup_threads, jd_server **out);
 /* Queue a request (never blocks); *ticket identifies it.  JD_EINVAL for bad fields, or
  * a footprint larger than the whole budget. */

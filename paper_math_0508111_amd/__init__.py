@@ -439,7 +439,7 @@ def use_torch_allocator(enable=True):
 
 
 class Server:
-    """jd_server_*: continuous batching of independent solve requests."""
+    """jd_server_*: independent solve requests served concurrently (one stream per worker)."""
 
     def __init__(self, hbm_budget_bytes=0, workers=0, setup_threads=0):
         h = ctypes.c_void_p()

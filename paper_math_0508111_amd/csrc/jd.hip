@@ -1989,7 +1989,7 @@ int jd_problem_linear_solve_noalloc(jd_problem *p, double shift, const double *d
 }  // extern "C"
 
 // ---------------------------------------------------------------------------------
-// Serving: continuous batching of independent requests.
+// Serving: independent requests run concurrently, one stream per worker.
 // ---------------------------------------------------------------------------------
 #include <condition_variable>
 #include <deque>
@@ -2049,7 +2049,16 @@ struct jd_server {
     std::set<uint64_t> pending;
     std::map<uint64_t, jd_result> done;
     size_t budget = 0, reserved = 0;
+    // Host setups: with a fixed thread count, at most setup_slots run at once.  Adaptive
+    // (setup_threads 0): a setup starts when a thread of the budget is free and takes
+    // budget / max(2, setups running or waiting) of them, at least one and at most the
+    // free ones.  A setup's parallel efficiency falls with its thread count (measured,
+    // L = 50 on 8 cores: one setup with 8 threads 3.3 s, eight with one thread 11.7 s
+    // each), so under a backlog more, narrower setups clear it faster; at light load
+    // two setups share the budget.  The factors do not depend on the thread count.
     int setup_threads = 1, setup_slots = 1, setups_running = 0;
+    int setup_budget = 1, setup_threads_used = 0, setups_waiting = 0;
+    bool setup_adaptive = false;
     std::condition_variable cv_setup;
     bool stop = false;
     uint64_t next_id = 1;
@@ -2064,7 +2073,6 @@ struct jd_server {
         res.device_bytes = q.est;
         const double t_admit = wall_s();
         res.queued_s = t_admit - q.t_submit;
-        jdmi::set_setup_threads(setup_threads);
         jd_options o{};
         o.precision = q.r.precision;
         o.bc = q.r.bc;
@@ -2072,17 +2080,29 @@ struct jd_server {
         o.flags = q.r.flags & ~JD_FLAG_GRAPHS;  // workers launch eagerly
         o.stream = stream;
         jd_problem *p = nullptr;
+        int threads = setup_threads;
         {
             std::unique_lock<std::mutex> lk(m);
-            cv_setup.wait(lk, [&] { return setups_running < setup_slots; });
+            ++setups_waiting;
+            cv_setup.wait(lk, [&] {
+                return setup_adaptive ? setup_threads_used < setup_budget : setups_running < setup_slots;
+            });
+            if (setup_adaptive) {
+                const int demand = std::max(2, setups_running + setups_waiting);
+                threads = std::max(1, std::min(setup_budget / demand, setup_budget - setup_threads_used));
+            }
+            --setups_waiting;
             ++setups_running;
+            setup_threads_used += threads;
         }
+        jdmi::set_setup_threads(threads);
         int rc = jd_setup(q.r.L, q.r.W, q.r.seed, q.r.sigma, &o, &p);
         {
             std::lock_guard<std::mutex> g(m);
             --setups_running;
+            setup_threads_used -= threads;
         }
-        cv_setup.notify_one();
+        cv_setup.notify_all();
         const double t_setup = wall_s();
         res.setup_s = t_setup - t_admit;
         if (rc == JD_OK) {
@@ -2150,6 +2170,8 @@ int jd_server_create(size_t hbm_budget_bytes, int workers, int setup_threads, jd
         s->budget = hbm_budget_bytes;
         const int w = workers ? workers : 8;
         const int hw = jdmi::setup_thread_budget();
+        s->setup_budget = std::max(1, hw);
+        s->setup_adaptive = setup_threads == 0;
         s->setup_threads = setup_threads ? setup_threads : std::max(1, hw / 2);
         s->setup_slots = std::max(1, std::min(w, hw / s->setup_threads));
         for (int i = 0; i < w; ++i) s->workers.emplace_back([p = s.get()] { p->worker(); });

@@ -1,4 +1,4 @@
-"""Serving (continuous batching) on the GPU: results identical alone and in the mix,
+"""Serving on the GPU: results identical alone and in the mix,
 admission by the HBM budget, checked against the oracle."""
 import numpy as np
 import pytest
