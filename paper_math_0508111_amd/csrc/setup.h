@@ -119,7 +119,7 @@ HybHost to_hyb(int nrows, const int64_t *ptr, const int *col, const double *val,
 // Z = Z_{S-1} ... Z_1 Z_0 and Z_s = (I - G_{b-1}) ... (I - G_a), each formed explicitly
 // (with dropping in the scaled domain).  One explicit Z (S = 1) needs no dependent passes
 // but its rows accumulate the fill of every chain through all levels (85 M entries at
-// L = 100); cutting the chains at a few level boundaries keeps the apply at 2 S + 4
+// L = 100); cutting the chains at a few level boundaries keeps the apply at 2 S + 3
 // launches and stores about a quarter of the entries.  K^{-1} = P^T Z^T D^{-1} Z P.
 //
 // Numbering.  The input vector is gathered in the Morton order of the lattice sites
