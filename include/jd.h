@@ -413,6 +413,21 @@ int jd_host_factor(int n, const int64_t *ptr, const int *col, const double *val,
                    long long *g_nnz, double *g_min_scaled, double *g_max_colsum, int *coarse_n);
 
 /*
+ * jd_host_precond_apply -- x = K^{-1} b for the multilevel preconditioner of A
+ * (sections 6-7), on the host in binary64, through the very layouts the device products
+ * read (the segments of the inverse factor, D^{-1}, the exactly inverted last level,
+ * here inverted on the host), in the device's order.  A check of those layouts: every
+ * row, column and task number is checked against the region of the 3n workspace it may
+ * address, no product may read a value it writes, and no value may be read before it
+ * is written; a failed check returns JD_ESETUP with the reason in jd_last_error().  n
+ * must be L^3 (the layouts follow the Morton order of the lattice); b and x are host
+ * arrays of n values in site order, b finite.  Options as for jd_setup (drop_tol < 0:
+ * nothing dropped, so that K^{-1} A = I).  Returns the number of segments.
+ */
+int jd_host_precond_apply(int n, const int64_t *ptr, const int *col, const double *val, const jd_options *opt,
+                          const double *b, double *x);
+
+/*
  * jd_set_allocator -- device memory from the caller (for instance a framework's caching
  * allocator), so that the library's buffers share the caller's memory pool.  Every device
  * buffer the library allocates after the call -- a problem's operator and factors, the

@@ -81,7 +81,7 @@ EXPORTS = ["jd_solve", "jd_setup", "jd_problem_solve", "jd_problem_info", "jd_pr
            "jd_precond_factor_product", "jd_precond_segments",
            "jd_problem_linear_solve", "jd_last_error", "jd_version", "jd_server_create", "jd_server_submit",
            "jd_server_poll", "jd_server_wait", "jd_server_footprint", "jd_server_destroy",
-           "jd_host_matching", "jd_host_split_cycles", "jd_host_factor", "jd_set_allocator",
+           "jd_host_matching", "jd_host_split_cycles", "jd_host_factor", "jd_host_precond_apply", "jd_set_allocator",
            "jd_problem_linear_solve_noalloc", "jd_problem_lanczos", "jd_gen_hop", "jd_block_product"]
 
 _lib = None

@@ -1904,6 +1904,37 @@ int jd_host_factor(int n, const int64_t *ptr, const int *col, const double *val,
     });
 }
 
+int jd_host_precond_apply(int n, const int64_t *ptr, const int *col, const double *val, const jd_options *opt,
+                          const double *b, double *x)
+{
+    return guarded([&] {
+        if (!b || !x) throw JdError(JD_EINVAL, "b and x must not be NULL");
+        jdmi::Csr A = host_csr(n, ptr, col, val);
+        const int L = int(std::lround(std::cbrt(double(n))));
+        if (int64_t(L) * L * L != n) throw JdError(JD_EINVAL, "n must be the number of sites of an L^3 lattice");
+        jd_options o{};
+        if (opt) o = *opt;
+        fill_defaults(o, n);
+        jdmi::SetupParams prm;
+        prm.drop_tol = o.drop_tol;
+        prm.kappa = o.kappa;
+        prm.agg_tau = o.agg_tau;
+        prm.schur_tol = o.schur_tol;
+        prm.coarse_max = o.coarse_max;
+        prm.max_levels = o.max_levels;
+        prm.z_drop = o.z_drop;
+        prm.z_parts = o.z_parts;
+        prm.inverse_factor = true;
+        prm.host_coarse_inverse = true;
+        jdmi::Multilevel ml;
+        std::string err = jdmi::build_multilevel(A, prm, ml);
+        if (!err.empty()) throw JdError(JD_ESETUP, err);
+        err = jdmi::apply_inverse_factor_host(ml, b, x);
+        if (!err.empty()) throw JdError(JD_ESETUP, "layout check: " + err);
+        return int(ml.z.seg.size());
+    });
+}
+
 int jd_problem_linear_solve(jd_problem *p, double shift, const double *d_Q, int pcols, const double *d_b, double *d_x,
                             double rtol, int maxit, int *its)
 {

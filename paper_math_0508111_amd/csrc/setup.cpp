@@ -1167,6 +1167,119 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L, int parts)
 // CSR -> the hybrid device layout (see HybHost).  The parts are built on their own
 // (in parallel) and then concatenated, with their long-row indices, slice codes and
 // offsets shifted to the global numbering.
+// One product of the layout h on the host (see apply_inverse_factor_host): rows are
+// written to y, columns read from x; every number is checked against its limit, and no
+// row the product writes may be read by it.
+static std::string hyb_product_host(const HybHost &h, const std::vector<double> &x, int64_t xlim, double *y,
+                                    int64_t ylim, std::vector<char> &mark)
+{
+    const int ns = int(h.slice_ptr.size()) - 1;
+    if (ns < 0 || int64_t(h.slice_row.size()) != ns + 1 || int64_t(h.rowidx.size()) != h.slice_row[ns])
+        return "slice arrays of inconsistent sizes";
+    // the tasks of each part cover its long rows and its slices exactly once
+    std::vector<int> seen_long(h.long_row.size(), 0), seen_slice(ns, 0);
+    for (int p = 0; p < kHybParts; ++p)
+        for (int i = 0; i < h.ntask[p]; ++i) {
+            if (i < h.plong[p]) {
+                const int c = h.long0[p] + i;
+                if (c < 0 || c >= int(h.long_row.size())) return "long-row task out of range";
+                ++seen_long[c];
+            } else {
+                const int c = h.slice0[p] + i - h.plong[p];
+                if (c < 0 || c >= ns) return "slice task out of range";
+                ++seen_slice[c];
+            }
+        }
+    for (int v : seen_long) if (v != 1) return "long rows not covered once by the tasks";
+    for (int v : seen_slice) if (v != 1) return "slices not covered once by the tasks";
+    // the rows written, then every column read (a product never reads its own rows)
+    std::vector<int64_t> written;
+    for (int r : h.long_row) {
+        if (r < 0 || r >= ylim) return "long row number out of range";
+        written.push_back(r);
+    }
+    for (int r : h.rowidx) {
+        if (r >= ylim) return "slice row number out of range";
+        if (r >= 0) written.push_back(r);
+    }
+    if (y == x.data())
+        for (int64_t r : written) mark[r] = 1;
+    auto col_ok = [&](int c) { return c >= 0 && c < xlim && !(y == x.data() && mark[c]); };
+    std::string err;
+    for (size_t i = 0; i < h.long_row.size() && err.empty(); ++i) {
+        double a = 0.0;
+        for (int64_t q = h.long_ptr[i]; q < h.long_ptr[i + 1]; ++q) {
+            if (!col_ok(h.long_col[q])) { err = "long-row column out of range or written by the product"; break; }
+            a += h.long_val[q] * x[h.long_col[q]];
+        }
+        y[h.long_row[i]] = a;
+    }
+    for (int s = 0; s < ns && err.empty(); ++s) {
+        const int64_t p0 = h.slice_ptr[s];
+        const int R = kSliceRows << int(p0 & 3);
+        const int64_t b = p0 & ~int64_t(63);
+        const int64_t e = h.slice_ptr[s + 1] & ~int64_t(63);
+        if (e <= b || e > int64_t(h.col.size()) || h.slice_row[s + 1] - h.slice_row[s] != R) {
+            err = "slice extent";
+            break;
+        }
+        const int groups = int((e - b) / 64), lanes = 64 / R;
+        for (int l = 0; l < R && err.empty(); ++l) {
+            double a = 0.0;
+            for (int g = 0; g < groups; ++g)
+                for (int j = 0; j < lanes; ++j) {
+                    const int64_t at = b + int64_t(g) * 64 + int64_t(j) * R + l;
+                    if (!col_ok(h.col[at])) { err = "slice column out of range or written by the product"; break; }
+                    a += h.val[at] * x[h.col[at]];
+                }
+            const int r = h.rowidx[h.slice_row[s] + l];
+            if (r >= 0) y[r] = a;
+        }
+    }
+    if (y == x.data())
+        for (int64_t r : written) mark[r] = 0;
+    return err;
+}
+
+std::string apply_inverse_factor_host(const Multilevel &ml, const double *b, double *x)
+{
+    const int n = ml.n;
+    const InverseFactor &Z = ml.z;
+    const int S = int(Z.seg.size()), nc = ml.coarse_n;
+    if (S == 0 || int(Z.site_of.size()) != n) return "no inverse factor";
+    if (nc > 0 && ml.coarse_inv.size() != size_t(nc) * nc) return "last level not inverted on the host";
+    const int64_t n3 = 3 * int64_t(n);
+    // NaN marks a value no product has written: it reaches x if it is ever read
+    std::vector<double> buf(n3, std::numeric_limits<double>::quiet_NaN());
+    std::vector<char> mark(n3, 0);
+    for (int q = 0; q < n; ++q) buf[2 * int64_t(n) + q] = b[Z.site_of[q]];
+    std::string err;
+    for (int s = 0; s < S && err.empty(); ++s) err = hyb_product_host(Z.seg[s].down, buf, n3, buf.data(), n3, mark);
+    if (!err.empty()) return "down product: " + err;
+    for (int j = 0; j < n; ++j) {
+        if (Z.dp[j] < 0 || Z.dp[j] >= n) return "block partner out of range";
+        buf[int64_t(n) + j] = Z.dd[j] * buf[j] + Z.dof[j] * buf[Z.dp[j]];
+    }
+    std::vector<double> yc(nc);
+    for (int i = 0; i < nc; ++i) {
+        if (Z.coarse_idx[i] < 0 || Z.coarse_idx[i] >= n) return "last-level index out of range";
+        yc[i] = buf[Z.coarse_idx[i]];
+    }
+    for (int i = 0; i < nc; ++i) {
+        double a = 0.0;
+        for (int j = 0; j < nc; ++j) a += ml.coarse_inv[size_t(i) * nc + j] * yc[j];
+        buf[int64_t(n) + Z.coarse_idx[i]] = a;
+    }
+    for (int s = S - 1; s >= 1 && err.empty(); --s) err = hyb_product_host(Z.seg[s].up, buf, n3, buf.data(), n3, mark);
+    if (!err.empty()) return "up product: " + err;
+    std::fill(x, x + n, std::numeric_limits<double>::quiet_NaN());
+    err = hyb_product_host(Z.seg[0].up, buf, n3, x, n, mark);
+    if (!err.empty()) return "first segment's up product: " + err;
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(x[i])) return "a value was read before any product wrote it, or a site was not written";
+    return "";
+}
+
 HybHost to_hyb(int n, const int64_t *ptr, const int *col, const double *val, const int *row_code)
 {
     constexpr int P = kHybParts;

@@ -203,6 +203,16 @@ void build_inverse_factor(Multilevel &ml, double z_drop, int L, int parts);
 // Returns an empty string on success, else a message.
 std::string build_multilevel(const Csr &A, const SetupParams &prm, Multilevel &out);
 
+// x = K^{-1} b on the host, in binary64, through the device layouts of the segmented
+// inverse factor and in the device's order of products: the input gathered in Morton
+// order into region 2 of a 3n workspace, the down products, D^{-1}, the last level
+// (ml.coarse_inv, so the setup must have inverted it on the host), the up products,
+// the last one writing the lattice sites of x.  A check of the layouts: it returns a
+// message if a row or column number leaves its region, a product reads a value it
+// writes itself, a part's tasks do not cover its long rows and slices once each, or a
+// value is read before any product wrote it; else an empty string.
+std::string apply_inverse_factor_host(const Multilevel &ml, const double *b, double *x);
+
 // Host threads used by the setup of the calling thread (OpenMP); <= 0 leaves the default.
 void set_setup_threads(int threads);
 // OpenMP threads available to the calling thread (OMP_NUM_THREADS when set).

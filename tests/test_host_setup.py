@@ -6,7 +6,10 @@
   (section 6.1, eq. (1)-(2); section 5.2: scaled entries at most 1 in modulus);
 * the cycle split of the worked example of figures 3-4 (section 6.2);
 * invariants of the multilevel factorisation (section 7.2: dropped entries below
-  epsilon / kappa, ||L^{-1}||_1 <= kappa for accepted pivots).
+  epsilon / kappa, ||L^{-1}||_1 <= kappa for accepted pivots);
+* the device layouts of the segmented inverse factor, applied on the host with every
+  index checked: the exact inverse when nothing is dropped, a symmetric K^{-1} when
+  entries are dropped.
 """
 import ctypes
 import itertools
@@ -345,3 +348,78 @@ def test_multilevel_identical_for_any_thread_count(jd):
         assert r["levels"] == runs[0]["levels"] and r["coarse"] == runs[0]["coarse"]
         for key in ("perm", "scale", "off", "nB", "n2x2", "gnnz", "gmin", "gcolsum"):
             assert np.array_equal(r[key], runs[0][key]), key
+
+
+def _host_precond_apply(jd, A, b, **opts):
+    ptr, col, val, M = _csr_sparse(A)
+    n = M.shape[0]
+    x = np.zeros(n)
+    o = jd.make_options(**opts)
+    f = jd.lib().jd_host_precond_apply
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 6
+    rc = f(n, _vp(ptr), _vp(col), _vp(val), ctypes.byref(o), _vp(np.ascontiguousarray(b, dtype=np.float64)),
+           _vp(x))
+    return rc, x
+
+
+def _shifted(L, W, seed, sigma, bc="periodic", offdiag=False):
+    from oracle import generator, lattice
+    if offdiag:
+        eps, hop = generator.offdiag_model(L, W, seed)
+        A = lattice.hamiltonian(L, eps, bc=bc, hop=hop)
+    else:
+        A = lattice.hamiltonian(L, generator.disorder(L, W, seed), bc=bc)
+    return (A - sigma * sp.identity(L ** 3)).tocsr()
+
+
+@pytest.mark.parametrize("L,W,sigma,bc,offdiag,parts,cmax", [
+    (8, 16.5, 0.13, "periodic", False, 0, 40),
+    (10, 12.0, 0.13, "hardwall", False, 6, 40),
+    (12, 16.5, -0.2, "periodic", False, 6, 60),
+    (9, 1.0, 0.05, "periodic", True, 6, 40),
+])
+def test_segment_layouts_apply_the_exact_inverse(jd, L, W, sigma, bc, offdiag, parts, cmax):
+    # Nothing dropped (sections 6-7 with epsilon < 0): K^{-1} (A - sigma I) x = x, applied
+    # on the host through the layouts the device products read, in the device's order.
+    # The entry point checks every row, column and task number of the layouts against the
+    # workspace region it may address, that no product reads a value it writes, and that
+    # nothing is read before it is written.
+    A = _shifted(L, W, 3, sigma, bc, offdiag)
+    x0 = np.random.default_rng(L).standard_normal(L ** 3)
+    segs, x = _host_precond_apply(jd, A, A @ x0, drop_tol=-1.0, coarse_max=cmax, z_parts=parts)
+    assert segs >= 1, jd.lib().jd_last_error()
+    if parts:
+        assert segs >= 3  # the level cuts 1, 3, 9, ... give several segments here
+    assert np.max(np.abs(x - x0)) <= 1e-8 * np.max(np.abs(x0))
+
+
+def test_segment_layouts_are_transposes_with_dropping(jd):
+    # with the default dropping K^{-1} = P^T Z^T D^{-1} Z P is no longer the inverse but
+    # stays symmetric: the up layouts must hold exactly the transposes of the down ones
+    A = _shifted(14, 16.5, 5, 0.0)
+    rng = np.random.default_rng(7)
+    u, v = rng.standard_normal(14 ** 3), rng.standard_normal(14 ** 3)
+    s1, ku = _host_precond_apply(jd, A, u, z_parts=4, coarse_max=100)
+    s2, kv = _host_precond_apply(jd, A, v, z_parts=4, coarse_max=100)
+    assert s1 >= 3 and s2 == s1, jd.lib().jd_last_error()
+    assert abs(v @ ku - u @ kv) <= 1e-12 * np.linalg.norm(ku) * np.linalg.norm(v)
+    # and it is a preconditioner: much closer to the inverse than the identity is
+    x0 = rng.standard_normal(14 ** 3)
+    _, x = _host_precond_apply(jd, A, A @ x0, z_parts=4, coarse_max=100)
+    assert np.linalg.norm(x - x0) < 0.5 * np.linalg.norm(A @ x0 - x0)
+
+
+def test_host_precond_apply_arguments(jd):
+    A = _shifted(4, 16.5, 0, 0.1)
+    b = np.ones(64)
+    f = jd.lib().jd_host_precond_apply
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 6
+    ptr, col, val, _ = _csr_sparse(A)
+    x = np.zeros(64)
+    assert f(64, _vp(ptr), _vp(col), _vp(val), None, _vp(b), None) == jd.JD_EINVAL
+    # not a cube: the layouts follow the Morton order of an L^3 lattice
+    B = sp.identity(60, format="csr") * 2.0
+    p2, c2, v2, _ = _csr_sparse(B)
+    assert f(60, _vp(p2), _vp(c2), _vp(v2), None, _vp(b), _vp(x)) == jd.JD_EINVAL
