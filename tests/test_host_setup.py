@@ -374,6 +374,7 @@ def _shifted(L, W, seed, sigma, bc="periodic", offdiag=False):
 
 
 @pytest.mark.parametrize("L,W,sigma,bc,offdiag,parts,cmax", [
+    (2, 16.5, 0.1, "periodic", False, 0, 0),  # every unknown in the last level
     (8, 16.5, 0.13, "periodic", False, 0, 40),
     (10, 12.0, 0.13, "hardwall", False, 6, 40),
     (12, 16.5, -0.2, "periodic", False, 6, 60),
